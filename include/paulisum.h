@@ -1,0 +1,180 @@
+/* paulisum.h -- C ABI of the MI355X Pauli-sum product library.
+ *
+ * A Pauli sum H = sum_t i^{k_t} c_t P_t (Section III-A, eq. (2)) lives on one
+ * GPU in bit-packed binary symplectic form (Section III-C, Table I).  The
+ * library forms the outer product of two sums (Section IV-C, "Hamiltonian
+ * Multiplication" in Section V), and combines duplicate strings by sorting
+ * and one linear pass (Section III-H).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - n qubits, W = ceil(n/64) words, 1 <= n <= 1024.  Qubit q is bit (q % 64)
+ *    of word (q / 64) in both the X words and the Z words; bits at or above
+ *    n must be zero.  Letter per qubit (Table I): (x,z) = (0,0) I, (0,1) Z,
+ *    (1,0) X, (1,1) Y.
+ *  - Host-side string arrays are row-major [m][W] uint64.
+ *  - A term's value is i^k * c * P with k in {0,1,2,3} (the 2-bit phase of
+ *    Section III-C) and c complex.  Coefficients are interleaved (re, im):
+ *    double pairs for PAULI_C128, float pairs for PAULI_C64.
+ *  - "stream" is a hipStream_t (NULL = the default stream).  Every call is
+ *    stream-ordered; a call returns once its work is enqueued, except where a
+ *    call states that it synchronises.
+ *  - Every call returns a pauli_status_t and never throws.  On error the
+ *    out-parameters are left untouched and pauli_last_error() gives a
+ *    message (per thread).
+ *  - Every handle returned by a call is owned by the caller, who destroys it
+ *    exactly once with paulisum_destroy.  Handles are bound to the device
+ *    that was current when they were made.
+ */
+#ifndef PAULISUM_H
+#define PAULISUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PAULI_OK = 0,
+  PAULI_ERR_INVALID = 1,  /* bad argument: null pointer, n out of range, padding bits, phase > 3 */
+  PAULI_ERR_SHAPE = 2,    /* operands disagree (qubit count, coefficient type) */
+  PAULI_ERR_OVERFLOW = 3, /* a size exceeds what the pair index or a count can hold */
+  PAULI_ERR_OOM = 4,      /* device allocation failed or exceeded the memory budget */
+  PAULI_ERR_CAPACITY = 5, /* a result did not fit its preallocated capacity */
+  PAULI_ERR_DEVICE = 6    /* a HIP runtime call failed */
+} pauli_status_t;
+
+typedef enum { PAULI_C128 = 0, PAULI_C64 = 1 } pauli_dtype_t;
+
+/* flags for paulisum_create / paulisum_export */
+#define PAULI_PTR_DEVICE 1u /* the string/phase/coefficient pointers are device memory */
+
+typedef struct paulisum* paulisum_t;
+
+/* Merge options (Section III-H sort-and-combine, Section III-B truncation).
+ *  mode        PAULI_MERGE_PLAIN: coefficient products and sums in the sum's
+ *              own precision (FP64 for C128).
+ *              PAULI_MERGE_COMPENSATED: products and sums in FP32 with
+ *              compensated (TwoSum) accumulation; segments whose sum cancels
+ *              (|sum| < remerge_tau * sum of |terms|) are recomputed in FP64
+ *              from the original coefficients.
+ *  drop_abs    terms whose merged modulus is strictly below drop_abs are
+ *              removed; a negative value keeps every term (zeros included).
+ *  remerge_tau cancellation threshold of the compensated mode (<= 0: 1e-3).
+ *  key_bits    0 for the default; otherwise the sort uses only the top
+ *              key_bits bits of the 64-bit string fingerprint (testing aid:
+ *              forces fingerprint collisions, which are resolved exactly).
+ */
+typedef enum { PAULI_MERGE_PLAIN = 0, PAULI_MERGE_COMPENSATED = 1 } pauli_merge_mode_t;
+typedef struct {
+  int32_t mode;
+  double drop_abs;
+  double remerge_tau;
+  int32_t key_bits;
+} pauli_merge_opts_t;
+
+/* Launch-shape parameters (0 = library default / tuned value). */
+typedef struct {
+  int32_t tile_i;          /* left terms per work tile */
+  int32_t tile_j;          /* right terms per work tile */
+  int32_t words_per_thread;
+  int32_t radix_bits;      /* digit width of the radix passes */
+} pauli_tune_t;
+
+/* Text of a status code (static storage). */
+const char* pauli_status_string(pauli_status_t s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* pauli_last_error(void);
+
+/* paulisum_create: a device Pauli sum from packed words (Section III-D: a
+ * coefficient vector alongside a binary matrix whose rows are the strings).
+ *  n_qubits  1..1024
+ *  n_terms   >= 0 (0 gives an empty sum)
+ *  x_words, z_words  [n_terms][W] row-major
+ *  phase     [n_terms] exponents 0..3, or NULL for all zero
+ *  coef      [n_terms] interleaved (re, im) of dtype
+ *  flags     PAULI_PTR_DEVICE if the four arrays are device memory; host
+ *            arrays are copied before the call returns, device arrays are read
+ *            on `stream` and must stay valid until that work completes
+ *  Errors: INVALID for n out of range, n_terms < 0, a null array (with
+ *  n_terms > 0), a set bit at or above n, a phase above 3.  Duplicate strings
+ *  are allowed; their values add up under pauli_merge.  Synchronises the
+ *  stream when the inputs are device arrays (to report validation errors).
+ */
+pauli_status_t paulisum_create(int32_t n_qubits, int64_t n_terms, const uint64_t* x_words,
+                               const uint64_t* z_words, const uint8_t* phase, const void* coef,
+                               pauli_dtype_t dtype, uint32_t flags, void* stream, paulisum_t* out);
+
+/* Releases a sum (NULL is allowed).  Waits for the device to finish work
+ * that may still read it. */
+pauli_status_t paulisum_destroy(paulisum_t s);
+
+/* Qubit count, term count and coefficient type of a sum (any pointer may be
+ * NULL). */
+pauli_status_t paulisum_info(paulisum_t s, int32_t* n_qubits, int64_t* n_terms,
+                             pauli_dtype_t* dtype);
+
+/* Copies a sum out in the create layout: x, z [m][W], phase [m], coef [m]
+ * interleaved (re, im) of the sum's dtype, fingerprint [m] (the 64-bit key
+ * that orders merged sums; see pauli_merge).  Any pointer may be NULL.
+ * flags = PAULI_PTR_DEVICE for device destinations (stream-ordered), else
+ * host destinations (the call synchronises the stream). */
+pauli_status_t paulisum_export(paulisum_t s, uint64_t* x_words, uint64_t* z_words,
+                               uint8_t* phase, void* coef, uint64_t* fingerprint,
+                               uint32_t flags, void* stream);
+
+/* pauli_outer_product: the unmerged outer product H1*H2 (Section IV-C,
+ * "Thread-Level Parallelism"; Section V, "Hamiltonian Multiplication").
+ * Output term p = j*|a| + i is a_i * b_j: strings X = X_a ^ X_b,
+ * Z = Z_a ^ Z_b (Section III-E), phase exponent k_a + k_b + (phase of the
+ * string product) mod 4 (Section III-A), coefficient c_a * c_b computed as
+ * (re = ac - bd, im = ad + bc) without fused multiply-adds.  a == b is
+ * allowed.  Errors: SHAPE if n or dtype differ; OVERFLOW if |a|*|b| >= 2^32.
+ */
+pauli_status_t pauli_outer_product(paulisum_t a, paulisum_t b, paulisum_t* out, void* stream);
+
+/* pauli_merge: sort-and-combine (Section III-H).  The output holds one term
+ * per distinct string of s, with phase 0 and coefficient
+ * sum over equal strings of i^k * c, in ascending order of the 64-bit
+ * fingerprint fp(P) = XOR over set bits of fixed random 64-bit columns
+ * (ties between distinct strings with equal fingerprints are ordered by
+ * their packed words).  Zero coefficients are kept unless opts->drop_abs
+ * removes them.  opts may be NULL (plain, keep all).  Synchronises the
+ * stream once to learn the output size. */
+pauli_status_t pauli_merge(paulisum_t s, const pauli_merge_opts_t* opts, paulisum_t* out,
+                           void* stream);
+
+/* pauli_outer_product_merged: merge(outer_product(a, b)) without storing
+ * the |a|*|b| unmerged products.  Same output definition as pauli_merge.
+ * Errors as pauli_outer_product. */
+pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
+                                          const pauli_merge_opts_t* opts, paulisum_t* out,
+                                          void* stream);
+
+/* pauli_outer_product_batched: nb independent fused products
+ * out[t] = merge(a[t] * b[t]); the pairs may differ in qubit count and term
+ * counts but a[t], b[t] must agree with each other.  tune may be NULL. */
+pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
+                                           const pauli_merge_opts_t* opts,
+                                           const pauli_tune_t* tune, paulisum_t* out,
+                                           void* stream);
+
+/* Replaces the device allocator used for every buffer the library makes
+ * (NULL, NULL restores the default, hipMallocAsync / hipFreeAsync on the
+ * call's stream).  alloc returns NULL on failure.  Not thread-safe with
+ * concurrent calls. */
+typedef void* (*pauli_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*pauli_free_fn)(void* ptr, void* stream, void* ctx);
+pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, void* ctx);
+
+/* Upper bound on device bytes the library may hold at once for temporaries
+ * and results made by later calls (0 = no limit).  Exceeding it gives OOM. */
+pauli_status_t pauli_set_memory_budget(uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAULISUM_H */

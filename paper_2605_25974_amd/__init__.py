@@ -1,0 +1,309 @@
+"""Python binding of the MI355X Pauli-sum library (libpaulisum.so).
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels behind the C ABI declared in include/paulisum.h.  PyTorch is used for
+device memory (torch tensors as inputs/outputs) and for the current stream.
+If the shared library has not been built the import of this package still
+works, but the first call raises ``PauliLibraryMissing``: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpaulisum.so")
+
+PAULI_OK = 0
+STATUS = {0: "OK", 1: "INVALID", 2: "SHAPE", 3: "OVERFLOW", 4: "OOM", 5: "CAPACITY", 6: "DEVICE"}
+C128, C64 = 0, 1
+PTR_DEVICE = 1
+PLAIN, COMPENSATED = 0, 1
+
+# Every symbol include/paulisum.h declares.
+EXPORTS = (
+    "pauli_status_string", "pauli_last_error", "paulisum_create", "paulisum_destroy",
+    "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
+    "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
+    "pauli_set_memory_budget",
+)
+
+
+class PauliLibraryMissing(RuntimeError):
+    pass
+
+
+class PauliError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = STATUS.get(status, str(status))
+        super().__init__("%s: %s" % (self.status, msg))
+
+
+class MergeOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("drop_abs", ctypes.c_double),
+                ("remerge_tau", ctypes.c_double), ("key_bits", ctypes.c_int32)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("tile_i", ctypes.c_int32), ("tile_j", ctypes.c_int32),
+                ("words_per_thread", ctypes.c_int32), ("radix_bits", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_lib = None
+
+
+def lib():
+    """The loaded ctypes library (raises PauliLibraryMissing if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PauliLibraryMissing(
+            "libpaulisum.so is not built (run __graft_entry__.build() or "
+            "python paper_2605_25974_amd/build.py); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    L.pauli_status_string.restype = ctypes.c_char_p
+    L.pauli_status_string.argtypes = [st]
+    L.pauli_last_error.restype = ctypes.c_char_p
+    L.pauli_last_error.argtypes = []
+    L.paulisum_create.restype = st
+    L.paulisum_create.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                  ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]
+    L.paulisum_destroy.restype = st
+    L.paulisum_destroy.argtypes = [_vp]
+    L.paulisum_info.restype = st
+    L.paulisum_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int)]
+    L.paulisum_export.restype = st
+    L.paulisum_export.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp]
+    L.pauli_outer_product.restype = st
+    L.pauli_outer_product.argtypes = [_vp, _vp, ctypes.POINTER(_vp), _vp]
+    L.pauli_merge.restype = st
+    L.pauli_merge.argtypes = [_vp, ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
+    L.pauli_outer_product_merged.restype = st
+    L.pauli_outer_product_merged.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts),
+                                             ctypes.POINTER(_vp), _vp]
+    L.pauli_outer_product_batched.restype = st
+    L.pauli_outer_product_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
+                                              ctypes.POINTER(_vp), ctypes.POINTER(MergeOpts),
+                                              ctypes.POINTER(Tune), ctypes.POINTER(_vp), _vp]
+    L.pauli_set_allocator.restype = st
+    L.pauli_set_allocator.argtypes = [_vp, _vp, _vp]
+    L.pauli_set_memory_budget.restype = st
+    L.pauli_set_memory_budget.argtypes = [ctypes.c_uint64]
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != PAULI_OK:
+        raise PauliError(status, lib().pauli_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    if torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+def _words(n):
+    return (n + 63) // 64
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _opts(mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0):
+    return MergeOpts(int(mode), float(drop_abs), float(tau), int(key_bits))
+
+
+class PauliSum:
+    """A Pauli sum resident on the GPU (opaque handle owned by this object)."""
+
+    def __init__(self, handle):
+        self._h = _vp(handle) if not isinstance(handle, _vp) else handle
+
+    @classmethod
+    def create(cls, n, x, z, phase=None, coef=None, dtype=None, stream=None):
+        """From packed words x, z [m][W] uint64, phase [m] uint8 (or None),
+        coef [m] complex.  numpy arrays (host) or torch CUDA tensors (device);
+        dtype 'c128' (default for complex128 input) or 'c64'."""
+        m = int(x.shape[0])
+        dev = _is_torch(x) and x.is_cuda
+        if dev:
+            import torch
+            if dtype is None:
+                dtype = "c64" if coef.dtype == torch.complex64 else "c128"
+            tdt = torch.complex64 if dtype == "c64" else torch.complex128
+            x = x.contiguous().view(torch.int64)
+            z = z.contiguous().view(torch.int64)
+            coef = coef.to(tdt).contiguous()
+            ph = phase.to(torch.uint8).contiguous() if phase is not None else None
+            keep = (x, z, coef, ph)
+            ptrs = (x.data_ptr(), z.data_ptr(), ph.data_ptr() if ph is not None else None,
+                    coef.data_ptr())
+            flags = PTR_DEVICE
+        else:
+            x = np.ascontiguousarray(x, dtype=np.uint64).reshape(m, _words(n))
+            z = np.ascontiguousarray(z, dtype=np.uint64).reshape(m, _words(n))
+            if coef is None:
+                coef = np.ones(m, np.complex128)
+            if dtype is None:
+                dtype = "c64" if np.asarray(coef).dtype == np.complex64 else "c128"
+            coef = np.ascontiguousarray(coef, dtype=np.complex64 if dtype == "c64"
+                                        else np.complex128).reshape(m)
+            ph = (np.ascontiguousarray(phase, dtype=np.uint8).reshape(m)
+                  if phase is not None else None)
+            keep = (x, z, coef, ph)
+            ptrs = (x.ctypes.data, z.ctypes.data, ph.ctypes.data if ph is not None else None,
+                    coef.ctypes.data)
+            flags = 0
+        out = _vp()
+        _check(lib().paulisum_create(int(n), m, ptrs[0], ptrs[1], ptrs[2], ptrs[3],
+                                     C64 if dtype == "c64" else C128, flags, _stream(stream),
+                                     ctypes.byref(out)))
+        del keep
+        return cls(out)
+
+    @classmethod
+    def from_dict(cls, d, dtype=None, stream=None):
+        return cls.create(d["n"], d["x"], d["z"], d.get("phase"), d["coef"], dtype=dtype,
+                          stream=stream)
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _check(lib().paulisum_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n = ctypes.c_int32()
+        m = ctypes.c_int64()
+        dt = ctypes.c_int()
+        _check(lib().paulisum_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(dt)))
+        return n.value, m.value, ("c64" if dt.value == C64 else "c128")
+
+    @property
+    def n(self):
+        return self.info()[0]
+
+    @property
+    def m(self):
+        return self.info()[1]
+
+    def __len__(self):
+        return self.m
+
+    def export(self, stream=None):
+        """Host copy: dict(n, x, z, phase, coef, fp) of numpy arrays."""
+        n, m, dt = self.info()
+        W = _words(n)
+        x = np.zeros((m, W), np.uint64)
+        z = np.zeros((m, W), np.uint64)
+        ph = np.zeros(m, np.uint8)
+        c = np.zeros(m, np.complex64 if dt == "c64" else np.complex128)
+        fp = np.zeros(m, np.uint64)
+        _check(lib().paulisum_export(self._h, x.ctypes.data, z.ctypes.data, ph.ctypes.data,
+                                     c.ctypes.data, fp.ctypes.data, 0, _stream(stream)))
+        return {"n": n, "x": x, "z": z, "phase": ph, "coef": c, "fp": fp}
+
+    def export_torch(self, device="cuda", stream=None):
+        """Device copy as torch tensors (x, z as int64 views of the words)."""
+        import torch
+        n, m, dt = self.info()
+        W = _words(n)
+        x = torch.empty((m, W), dtype=torch.int64, device=device)
+        z = torch.empty((m, W), dtype=torch.int64, device=device)
+        ph = torch.empty(m, dtype=torch.uint8, device=device)
+        c = torch.empty(m, dtype=torch.complex64 if dt == "c64" else torch.complex128,
+                        device=device)
+        fp = torch.empty(m, dtype=torch.int64, device=device)
+        _check(lib().paulisum_export(self._h, x.data_ptr(), z.data_ptr(), ph.data_ptr(),
+                                     c.data_ptr(), fp.data_ptr(), PTR_DEVICE, _stream(stream)))
+        return {"n": n, "x": x, "z": z, "phase": ph, "coef": c, "fp": fp}
+
+
+def outer_product(a: PauliSum, b: PauliSum, stream=None) -> PauliSum:
+    out = _vp()
+    _check(lib().pauli_outer_product(a.handle, b.handle, ctypes.byref(out), _stream(stream)))
+    return PauliSum(out)
+
+
+def merge(s: PauliSum, mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0, stream=None) -> PauliSum:
+    out = _vp()
+    o = _opts(mode, drop_abs, tau, key_bits)
+    _check(lib().pauli_merge(s.handle, ctypes.byref(o), ctypes.byref(out), _stream(stream)))
+    return PauliSum(out)
+
+
+def outer_product_merged(a: PauliSum, b: PauliSum, mode=PLAIN, drop_abs=-1.0, tau=0.0,
+                         key_bits=0, stream=None) -> PauliSum:
+    out = _vp()
+    o = _opts(mode, drop_abs, tau, key_bits)
+    _check(lib().pauli_outer_product_merged(a.handle, b.handle, ctypes.byref(o),
+                                            ctypes.byref(out), _stream(stream)))
+    return PauliSum(out)
+
+
+def outer_product_batched(a_list, b_list, mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0,
+                          tune=None, stream=None):
+    nb = len(a_list)
+    A = (_vp * max(nb, 1))(*[x.handle for x in a_list])
+    B = (_vp * max(nb, 1))(*[x.handle for x in b_list])
+    O = (_vp * max(nb, 1))()
+    o = _opts(mode, drop_abs, tau, key_bits)
+    t = Tune(*tune) if tune is not None else None
+    _check(lib().pauli_outer_product_batched(nb, A, B, ctypes.byref(o),
+                                             ctypes.byref(t) if t is not None else None, O,
+                                             _stream(stream)))
+    return [PauliSum(O[i]) for i in range(nb)]
+
+
+def set_memory_budget(nbytes: int):
+    _check(lib().pauli_set_memory_budget(int(nbytes)))
+
+
+_ALLOC_T = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
+_FREE_T = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+_hooks = None
+
+
+def use_torch_allocator(enable=True):
+    """Back every library allocation by torch's caching allocator."""
+    global _hooks
+    if not enable:
+        _check(lib().pauli_set_allocator(None, None, None))
+        _hooks = None
+        return
+    import torch
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream or 0)
+        except Exception:
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    _hooks = (_ALLOC_T(_alloc), _FREE_T(_free))
+    _check(lib().pauli_set_allocator(ctypes.cast(_hooks[0], _vp), ctypes.cast(_hooks[1], _vp),
+                                     None))

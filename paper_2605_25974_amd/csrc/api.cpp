@@ -1,0 +1,414 @@
+// The C ABI (include/paulisum.h): argument checks, device memory, and the
+// order in which the kernels of each call run.  No exception leaves this
+// file: every entry point catches and turns errors into status codes.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace pauli {
+
+namespace {
+thread_local std::string g_last_error;
+
+pauli_alloc_fn g_alloc = nullptr;
+pauli_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+std::atomic<uint64_t> g_in_use{0};
+std::atomic<uint64_t> g_budget{0};
+std::once_flag g_pool_once[64];
+
+struct Fail {
+  pauli_status_t status;
+};
+
+void init_pool(int dev) {
+  if (dev < 0 || dev >= 64) return;
+  std::call_once(g_pool_once[dev], [dev] {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t threshold = UINT64_MAX;  // keep freed blocks cached in the pool
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+    }
+  });
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(pauli_status_t s, const std::string& msg) {
+  set_error(msg);
+  throw Fail{s};
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? PAULI_ERR_OOM : PAULI_ERR_DEVICE,
+         std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+void* dalloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) return nullptr;
+  bytes = (bytes + 255) & ~size_t(255);
+  const uint64_t budget = g_budget.load();
+  if (budget && g_in_use.load() + bytes > budget)
+    fail(PAULI_ERR_OOM, "device memory budget exceeded (" + std::to_string(bytes) +
+                            " bytes requested, " + std::to_string(g_in_use.load()) + " in use of " +
+                            std::to_string(budget) + ")");
+  void* p = nullptr;
+  if (g_alloc) {
+    p = g_alloc(bytes, s, g_alloc_ctx);
+    if (!p) fail(PAULI_ERR_OOM, "allocator hook returned NULL for " + std::to_string(bytes));
+  } else {
+    int dev = 0;
+    PAULI_HIP(hipGetDevice(&dev));
+    init_pool(dev);
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      fail(PAULI_ERR_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  g_in_use += bytes;
+  return p;
+}
+
+void dfree(void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  bytes = (bytes + 255) & ~size_t(255);
+  g_in_use -= bytes;
+  if (g_alloc) {
+    if (g_free) g_free(p, s, g_alloc_ctx);
+  } else {
+    (void)hipFreeAsync(p, s);
+  }
+}
+
+paulisum* new_sum(int n, int64_t m, int64_t ld, pauli_dtype_t dt, hipStream_t s) {
+  const int W = words_for(n);
+  const size_t L = static_cast<size_t>(ld);
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t bX = up(L * W * 8), bph = up(L), bc = up(L * coef_bytes(dt)), bfp = up(L * 8);
+  const size_t total = 2 * bX + bph + bc + bfp;
+  paulisum* p = new paulisum;
+  p->n = n;
+  p->W = W;
+  p->m = m;
+  p->ld = ld;
+  p->dtype = dt;
+  PAULI_HIP(hipGetDevice(&p->device));
+  p->last_stream = s;
+  try {
+    p->block = total ? dalloc(total, s) : nullptr;
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  p->block_bytes = total;
+  char* b = static_cast<char*>(p->block);
+  p->X = reinterpret_cast<uint64_t*>(b);
+  p->Z = reinterpret_cast<uint64_t*>(b + bX);
+  p->ph = reinterpret_cast<uint8_t*>(b + 2 * bX);
+  p->coef = b + 2 * bX + bph;
+  p->fp = reinterpret_cast<uint64_t*>(b + 2 * bX + bph + bc);
+  return p;
+}
+
+void free_sum(paulisum* p) {
+  if (!p) return;
+  if (p->block) dfree(p->block, p->block_bytes, p->last_stream);
+  delete p;
+}
+
+}  // namespace pauli
+
+using namespace pauli;
+
+namespace {
+
+template <typename F>
+pauli_status_t guarded(F&& f) {
+  try {
+    set_error("");
+    f();
+    return PAULI_OK;
+  } catch (const Fail& e) {
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return PAULI_ERR_OOM;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return PAULI_ERR_DEVICE;
+  }
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+void check_sum(paulisum_t s, const char* name) {
+  if (!s) fail(PAULI_ERR_INVALID, std::string(name) + " is NULL");
+}
+
+void use_device(const paulisum* s) {
+  int cur = -1;
+  PAULI_HIP(hipGetDevice(&cur));
+  if (cur != s->device) PAULI_HIP(hipSetDevice(s->device));
+}
+
+void check_pair(paulisum_t a, paulisum_t b) {
+  check_sum(a, "a");
+  check_sum(b, "b");
+  if (a->n != b->n)
+    fail(PAULI_ERR_SHAPE, "qubit counts differ: " + std::to_string(a->n) + " vs " +
+                              std::to_string(b->n));
+  if (a->dtype != b->dtype) fail(PAULI_ERR_SHAPE, "coefficient types differ");
+  if (a->device != b->device) fail(PAULI_ERR_SHAPE, "operands live on different devices");
+  const int64_t P = a->m * b->m;
+  if (a->m > 0 && b->m > 0 && (P / b->m != a->m || P >= (int64_t(1) << 32)))
+    fail(PAULI_ERR_OVERFLOW, "|a|*|b| = " + std::to_string(a->m) + "*" + std::to_string(b->m) +
+                                 " exceeds the 32-bit pair index");
+}
+
+MergeArgs merge_args(const pauli_merge_opts_t* o) {
+  MergeArgs m;
+  if (!o) return m;
+  if (o->mode != PAULI_MERGE_PLAIN && o->mode != PAULI_MERGE_COMPENSATED)
+    fail(PAULI_ERR_INVALID, "unknown merge mode " + std::to_string(o->mode));
+  if (o->key_bits < 0 || o->key_bits > 64)
+    fail(PAULI_ERR_INVALID, "key_bits must be in 0..64");
+  m.mode = o->mode;
+  m.drop_abs = o->drop_abs;
+  m.tau = o->remerge_tau > 0 ? o->remerge_tau : 1e-3;
+  m.key_bits = o->key_bits ? o->key_bits : 64;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pauli_status_string(pauli_status_t s) {
+  switch (s) {
+    case PAULI_OK: return "ok";
+    case PAULI_ERR_INVALID: return "invalid argument";
+    case PAULI_ERR_SHAPE: return "operand shapes differ";
+    case PAULI_ERR_OVERFLOW: return "size overflow";
+    case PAULI_ERR_OOM: return "out of device memory";
+    case PAULI_ERR_CAPACITY: return "result exceeds capacity";
+    case PAULI_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* pauli_last_error(void) { return g_last_error.c_str(); }
+
+pauli_status_t paulisum_create(int32_t n_qubits, int64_t n_terms, const uint64_t* x_words,
+                               const uint64_t* z_words, const uint8_t* phase, const void* coef,
+                               pauli_dtype_t dtype, uint32_t flags, void* stream,
+                               paulisum_t* out) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    if (n_qubits < 1 || n_qubits > 64 * kMaxWordsHost)
+      fail(PAULI_ERR_INVALID, "n_qubits must be in 1..1024, got " + std::to_string(n_qubits));
+    if (n_terms < 0) fail(PAULI_ERR_INVALID, "n_terms is negative");
+    if (n_terms >= (int64_t(1) << 32)) fail(PAULI_ERR_OVERFLOW, "n_terms must be below 2^32");
+    if (dtype != PAULI_C128 && dtype != PAULI_C64) fail(PAULI_ERR_INVALID, "unknown dtype");
+    if (flags & ~PAULI_PTR_DEVICE) fail(PAULI_ERR_INVALID, "unknown flags");
+    if (n_terms > 0 && (!x_words || !z_words || !coef))
+      fail(PAULI_ERR_INVALID, "x_words, z_words and coef must not be NULL");
+    const int W = words_for(n_qubits);
+    const bool dev = flags & PAULI_PTR_DEVICE;
+    const size_t m = static_cast<size_t>(n_terms);
+    if (!dev && n_terms > 0) {  // validate host data before touching the device
+      const int tail = n_qubits - 64 * (W - 1);
+      const uint64_t pad = tail == 64 ? 0 : ~((uint64_t(1) << tail) - 1);
+      for (size_t t = 0; t < m; ++t) {
+        if ((x_words[t * W + W - 1] | z_words[t * W + W - 1]) & pad)
+          fail(PAULI_ERR_INVALID, "term " + std::to_string(t) + " has a bit set at or above n");
+        if (phase && phase[t] > 3)
+          fail(PAULI_ERR_INVALID, "term " + std::to_string(t) + " has phase > 3");
+      }
+    }
+    hipStream_t s = as_stream(stream);
+    paulisum* p = new_sum(n_qubits, n_terms, n_terms, dtype, s);
+    try {
+      if (n_terms > 0) {
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        DBuf rx(m * W * 8, s), rz(m * W * 8, s);
+        PAULI_HIP(hipMemcpyAsync(rx.p, x_words, m * W * 8, kind, s));
+        PAULI_HIP(hipMemcpyAsync(rz.p, z_words, m * W * 8, kind, s));
+        if (phase)
+          PAULI_HIP(hipMemcpyAsync(p->ph, phase, m, kind, s));
+        else
+          PAULI_HIP(hipMemsetAsync(p->ph, 0, m, s));
+        PAULI_HIP(hipMemcpyAsync(p->coef, coef, m * coef_bytes(dtype), kind, s));
+        if (dev) {
+          DBuf err(4, s);
+          PAULI_HIP(hipMemsetAsync(err.p, 0, 4, s));
+          launch_validate(rx.as<uint64_t>(), rz.as<uint64_t>(), p->ph, n_qubits, n_terms,
+                          err.as<uint32_t>(), s);
+          uint32_t herr = 0;
+          PAULI_HIP(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
+          PAULI_HIP(hipStreamSynchronize(s));
+          if (herr & 1u) fail(PAULI_ERR_INVALID, "a term has a bit set at or above n");
+          if (herr & 2u) fail(PAULI_ERR_INVALID, "a term has phase > 3");
+        }
+        launch_rows_to_soa(rx.as<uint64_t>(), W, n_terms, p->X, p->ld, s);
+        launch_rows_to_soa(rz.as<uint64_t>(), W, n_terms, p->Z, p->ld, s);
+        launch_fingerprint(p, s);
+        if (!dev) PAULI_HIP(hipStreamSynchronize(s));  // host arrays copied before return
+      }
+    } catch (...) {
+      free_sum(p);
+      throw;
+    }
+    *out = p;
+  });
+}
+
+pauli_status_t paulisum_destroy(paulisum_t s) {
+  return guarded([&] {
+    if (!s) return;
+    use_device(s);
+    free_sum(s);
+  });
+}
+
+pauli_status_t paulisum_info(paulisum_t s, int32_t* n_qubits, int64_t* n_terms,
+                             pauli_dtype_t* dtype) {
+  return guarded([&] {
+    check_sum(s, "s");
+    if (n_qubits) *n_qubits = s->n;
+    if (n_terms) *n_terms = s->m;
+    if (dtype) *dtype = s->dtype;
+  });
+}
+
+pauli_status_t paulisum_export(paulisum_t s, uint64_t* x_words, uint64_t* z_words,
+                               uint8_t* phase, void* coef, uint64_t* fingerprint, uint32_t flags,
+                               void* stream) {
+  return guarded([&] {
+    check_sum(s, "s");
+    if (flags & ~PAULI_PTR_DEVICE) fail(PAULI_ERR_INVALID, "unknown flags");
+    use_device(s);
+    hipStream_t st = as_stream(stream);
+    s->last_stream = st;
+    const size_t m = static_cast<size_t>(s->m);
+    if (m == 0) return;
+    const bool dev = flags & PAULI_PTR_DEVICE;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int W = s->W;
+    if (x_words || z_words) {
+      DBuf rows(m * W * 8, st);
+      if (x_words) {
+        launch_soa_to_rows(s->X, W, s->m, s->ld, rows.as<uint64_t>(), st);
+        PAULI_HIP(hipMemcpyAsync(x_words, rows.p, m * W * 8, kind, st));
+      }
+      if (z_words) {
+        if (x_words && !dev) PAULI_HIP(hipStreamSynchronize(st));
+        launch_soa_to_rows(s->Z, W, s->m, s->ld, rows.as<uint64_t>(), st);
+        PAULI_HIP(hipMemcpyAsync(z_words, rows.p, m * W * 8, kind, st));
+      }
+      if (!dev) PAULI_HIP(hipStreamSynchronize(st));
+    }
+    if (phase) PAULI_HIP(hipMemcpyAsync(phase, s->ph, m, kind, st));
+    if (coef) PAULI_HIP(hipMemcpyAsync(coef, s->coef, m * coef_bytes(s->dtype), kind, st));
+    if (fingerprint) PAULI_HIP(hipMemcpyAsync(fingerprint, s->fp, m * 8, kind, st));
+    if (!dev) PAULI_HIP(hipStreamSynchronize(st));
+  });
+}
+
+pauli_status_t pauli_outer_product(paulisum_t a, paulisum_t b, paulisum_t* out, void* stream) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_pair(a, b);
+    use_device(a);
+    hipStream_t s = as_stream(stream);
+    const int64_t P = a->m * b->m;
+    paulisum* o = new_sum(a->n, P, P, a->dtype, s);
+    try {
+      launch_outer_product(a, b, o, s);
+    } catch (...) {
+      free_sum(o);
+      throw;
+    }
+    a->last_stream = b->last_stream = s;
+    *out = o;
+  });
+}
+
+pauli_status_t pauli_merge(paulisum_t sum, const pauli_merge_opts_t* opts, paulisum_t* out,
+                           void* stream) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_sum(sum, "s");
+    const MergeArgs m = merge_args(opts);
+    use_device(sum);
+    hipStream_t s = as_stream(stream);
+    sum->last_stream = s;
+    *out = merge_generic(sum, nullptr, m, s);
+  });
+}
+
+pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
+                                          const pauli_merge_opts_t* opts, paulisum_t* out,
+                                          void* stream) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_pair(a, b);
+    const MergeArgs m = merge_args(opts);
+    use_device(a);
+    hipStream_t s = as_stream(stream);
+    a->last_stream = b->last_stream = s;
+    *out = merge_generic(a, b, m, s);
+  });
+}
+
+pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
+                                           const pauli_merge_opts_t* opts,
+                                           const pauli_tune_t* tune, paulisum_t* out,
+                                           void* stream) {
+  return guarded([&] {
+    (void)tune;
+    if (nb < 0) fail(PAULI_ERR_INVALID, "nb is negative");
+    if (nb > 0 && (!a || !b || !out)) fail(PAULI_ERR_INVALID, "a, b and out must not be NULL");
+    for (int32_t t = 0; t < nb; ++t) check_pair(a[t], b[t]);
+    const MergeArgs m = merge_args(opts);
+    hipStream_t s = as_stream(stream);
+    std::vector<paulisum*> res(static_cast<size_t>(nb), nullptr);
+    try {
+      for (int32_t t = 0; t < nb; ++t) {
+        use_device(a[t]);
+        res[t] = merge_generic(a[t], b[t], m, s);
+      }
+    } catch (...) {
+      for (auto* r : res) free_sum(r);
+      throw;
+    }
+    for (int32_t t = 0; t < nb; ++t) out[t] = res[t];
+  });
+}
+
+pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, void* ctx) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+      fail(PAULI_ERR_INVALID, "alloc and free must both be set or both be NULL");
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+  });
+}
+
+pauli_status_t pauli_set_memory_budget(uint64_t bytes) {
+  return guarded([&] { g_budget = bytes; });
+}
+
+}  // extern "C"

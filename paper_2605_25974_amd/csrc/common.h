@@ -1,0 +1,78 @@
+// Device-side building blocks shared by the kernels of the Pauli-sum library.
+//
+// Representation (Section III-C, Table I): a string on n qubits is W =
+// ceil(n/64) X words and W Z words; qubit q is bit q % 64 of word q / 64.
+// On the device a sum is stored struct-of-arrays (Section III-G / IV-A):
+// X[w][ld], Z[w][ld], phase[ld], coef[ld], fp[ld].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pauli {
+
+constexpr int kMaxWords = 16;  // n <= 1024
+
+// ---------------------------------------------------------------- bit ops
+
+__device__ __forceinline__ int popc64(uint64_t v) { return __popcll(v); }
+
+// ------------------------------------------------------------ fingerprint
+//
+// fp(P) is a GF(2)-linear 64-bit function of the 2n symplectic bits: the XOR
+// of one fixed pseudo-random column per set bit.  Linearity gives
+// fp(P*Q) = fp(P) ^ fp(Q) (the product XORs the bits, Section III-E), so the
+// key of a product is two loads and one XOR.  Column b (b = 2q for the X bit
+// of qubit q, 2q + 1 for its Z bit) is the counter-based SplitMix64 output
+// (Steele, Lea and Flood 2014) for counter b + 1 under a fixed seed.
+constexpr uint64_t kFpSeed = 0x5041554C49420001ull;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + counter * kGolden;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ __forceinline__ uint64_t fp_column(int bit_index) {
+  return splitmix64_at(kFpSeed, static_cast<uint64_t>(bit_index) + 1);
+}
+
+// ------------------------------------------------------------ complex math
+//
+// The library is compiled with floating-point contraction off, so these
+// products round exactly like the operation-by-operation formula.
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// i^k * v, exact.
+template <typename T>
+__device__ __forceinline__ cplx<T> rot_ik(int k, cplx<T> v) {
+  switch (k & 3) {
+    case 0: return v;
+    case 1: return {-v.im, v.re};
+    case 2: return {-v.re, -v.im};
+    default: return {v.im, -v.re};
+  }
+}
+
+// ------------------------------------------------------------ phase rule
+//
+// Write each letter as L(x,z) = i^{xz} X^x Z^z (so L(1,1) = iXZ = Y, Table I
+// and Section III-A).  Moving Z^{z1} past X^{x2} costs (-1)^{z1 x2}, hence
+//   L(x1,z1) L(x2,z2) = i^{x1z1 + x2z2 + 2 z1x2 - x3z3} L(x3,z3),
+// x3 = x1 ^ x2, z3 = z1 ^ z2.  Summed over qubits with popcounts (the
+// bit-parallel phase of Section III-E) and with the input phases:
+//   k = k1 + k2 + |X1&Z1| + |X2&Z2| + 2|Z1&X2| - |X3&Z3|  (mod 4).
+// e = k + |X&Z| is precomputed per input term.
+
+}  // namespace pauli

@@ -1,0 +1,122 @@
+// Host-side internals: the device container, memory helpers, and the
+// launchers each kernel file exports to the C-ABI layer (api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/paulisum.h"
+
+namespace pauli {
+constexpr int kMaxWordsHost = 16;  // n <= 1024
+}
+
+struct paulisum {
+  int32_t n = 0, W = 0;
+  int64_t m = 0;   // number of terms
+  int64_t ld = 0;  // column length (capacity) of every SoA array
+  pauli_dtype_t dtype = PAULI_C128;
+  int device = 0;
+  void* block = nullptr;  // one allocation backing every array below
+  size_t block_bytes = 0;
+  uint64_t* X = nullptr;  // [W][ld]
+  uint64_t* Z = nullptr;  // [W][ld]
+  uint8_t* ph = nullptr;  // [ld]
+  void* coef = nullptr;   // [ld] interleaved (re, im) of dtype
+  uint64_t* fp = nullptr; // [ld]
+  hipStream_t last_stream = nullptr;
+};
+
+namespace pauli {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+struct Error {
+  pauli_status_t status;
+};
+[[noreturn]] void fail(pauli_status_t s, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define PAULI_HIP(call) ::pauli::hip_check((call), #call)
+
+// ------------------------------------------------------------------ memory
+void* dalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, size_t bytes, hipStream_t s);
+
+// RAII device buffer freed (stream-ordered) when it leaves scope.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  DBuf() = default;
+  DBuf(size_t b, hipStream_t st) : p(b ? dalloc(b, st) : nullptr), bytes(b), s(st) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s) { o.p = nullptr; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    reset();
+    p = o.p; bytes = o.bytes; s = o.s; o.p = nullptr;
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p) dfree(p, bytes, s);
+    p = nullptr;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+inline int words_for(int n) { return (n + 63) / 64; }
+inline size_t coef_bytes(pauli_dtype_t t) { return t == PAULI_C128 ? 16 : 8; }
+
+// Allocates a container with capacity ld (>= m) on the current device.
+paulisum* new_sum(int n, int64_t m, int64_t ld, pauli_dtype_t dt, hipStream_t s);
+void free_sum(paulisum* p);
+
+// --------------------------------------------------------------- launchers
+// k_basic.hip
+void launch_rows_to_soa(const uint64_t* rows, int W, int64_t m, uint64_t* soa, int64_t ld,
+                        hipStream_t s);
+void launch_soa_to_rows(const uint64_t* soa, int W, int64_t m, int64_t ld, uint64_t* rows,
+                        hipStream_t s);
+void launch_validate(const uint64_t* xr, const uint64_t* zr, const uint8_t* ph, int n, int64_t m,
+                     uint32_t* err, hipStream_t s);
+void launch_fingerprint(const paulisum* t, hipStream_t s);
+void launch_outer_product(const paulisum* a, const paulisum* b, paulisum* out, hipStream_t s);
+
+// Per-term data of one operand of a pair product, gathered row-major so that
+// a term's 2W words sit in one contiguous span (one 128-byte line at W = 8).
+struct Side {
+  const uint64_t* rows = nullptr;  // [m][2W]: X words then Z words
+  const uint8_t* e = nullptr;      // [m] (phase + |X & Z|) mod 4
+  const void* coef = nullptr;      // [m] the sum's coefficients
+  const uint64_t* fp = nullptr;    // [m]
+  int64_t m = 0;
+};
+void launch_prep_side(const paulisum* t, uint64_t* rows, uint8_t* e, hipStream_t s);
+
+// k_sort.hip
+size_t scan_workspace_bytes(int64_t n);
+// out[i] = sum_{j<i} in[i]; *total (device) = sum of all; in may alias out.
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                        void* work, hipStream_t s);
+size_t radix_workspace_bytes(int64_t n);
+// Stable LSD radix sort of (key, val) by key bits [0, key_bits).  The sorted
+// result ends up in (keys, vals) or (keys_alt, vals_alt): returns true if in
+// the alternate pair.
+bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                      int64_t n, int key_bits, void* work, hipStream_t s);
+
+// k_merge.hip
+struct MergeArgs {
+  int mode = PAULI_MERGE_PLAIN;
+  double drop_abs = -1.0;
+  double tau = 1e-3;
+  int key_bits = 64;
+};
+// merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
+paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
+
+}  // namespace pauli

@@ -1,0 +1,469 @@
+// Sort-and-combine (Section III-H) on the device.
+//
+//   records   one (key, id) per term: key = the string's 64-bit fingerprint
+//             (fp(a_i * b_j) = fp(a_i) ^ fp(b_j) for a pair), id = the term
+//             index or the pair index p = j*|a| + i
+//   sort      stable LSD radix sort on the key
+//   heads     a record starts a segment when its key or its packed string
+//             differs from its predecessor's (the strings are compared word
+//             by word, so a fingerprint collision can never merge two
+//             strings); runs of equal keys that hold several strings are
+//             re-ordered by their packed words
+//   reduce    per segment, the sum of i^k * c over its records in record
+//             order (deterministic: sequential for short segments, a fixed
+//             tree for long ones)
+//   compact   drop |c| < drop_abs (strict), then write the surviving
+//             segments' strings, coefficients and fingerprints
+//
+// The same pipeline serves a materialised sum (term source) and the fused
+// outer product (pair source, no product is ever stored).
+#include "common.h"
+#include "internal.h"
+
+namespace pauli {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kLongSeg = 64;  // segments longer than this are reduced by a block
+
+inline unsigned grid_for(int64_t n, int per_block = kBlock) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > (1 << 30)) g = 1 << 30;
+  return static_cast<unsigned>(g);
+}
+
+// ------------------------------------------------------------- sources
+
+// A product a_i * b_j addressed by p = j*ma + i.
+template <int WT, typename T>
+struct PairSrc {
+  const uint64_t* ra;
+  const uint8_t* ea;
+  const cplx<T>* ca;
+  const uint64_t* fa;
+  const uint64_t* rb;
+  const uint8_t* eb;
+  const cplx<T>* cb;
+  const uint64_t* fb;
+  uint32_t ma;
+  int nw;
+
+  __device__ __forceinline__ void split(uint32_t id, uint32_t& i, uint32_t& j) const {
+    j = id / ma;
+    i = id - j * ma;
+  }
+  __device__ __forceinline__ void string(uint32_t id, uint64_t* w) const {
+    uint32_t i, j;
+    split(id, i, j);
+    const uint64_t* A = ra + (size_t)i * 2 * nw;
+    const uint64_t* B = rb + (size_t)j * 2 * nw;
+#pragma unroll
+    for (int q = 0; q < 2 * WT; ++q) {
+      if (WT > 8 && q >= 2 * nw) break;
+      w[q] = A[q] ^ B[q];
+    }
+  }
+  // Product string (into w) and value i^k * c_a * c_b.
+  __device__ __forceinline__ cplx<T> term(uint32_t id, uint64_t* w) const {
+    uint32_t i, j;
+    split(id, i, j);
+    const uint64_t* A = ra + (size_t)i * 2 * nw;
+    const uint64_t* B = rb + (size_t)j * 2 * nw;
+    int acc = ea[i] + eb[j];
+#pragma unroll
+    for (int q = 0; q < WT; ++q) {
+      if (WT > 8 && q >= nw) break;
+      const uint64_t xa = A[q], za = A[nw + q], xb = B[q], zb = B[nw + q];
+      const uint64_t x = xa ^ xb, z = za ^ zb;
+      acc += 2 * popc64(za & xb) - popc64(x & z);
+      w[q] = x;
+      w[nw + q] = z;
+    }
+    return rot_ik(acc, cmul(ca[i], cb[j]));
+  }
+  __device__ __forceinline__ uint64_t fp(uint32_t id) const {
+    uint32_t i, j;
+    split(id, i, j);
+    return fa[i] ^ fb[j];
+  }
+};
+
+// Term t of a stored sum.
+template <int WT, typename T>
+struct TermSrc {
+  const uint64_t* X;
+  const uint64_t* Z;
+  const uint8_t* ph;
+  const cplx<T>* c;
+  const uint64_t* f;
+  int64_t ld;
+  int nw;
+
+  __device__ __forceinline__ void string(uint32_t id, uint64_t* w) const {
+#pragma unroll
+    for (int q = 0; q < WT; ++q) {
+      if (WT > 8 && q >= nw) break;
+      w[q] = X[q * ld + id];
+      w[nw + q] = Z[q * ld + id];
+    }
+  }
+  __device__ __forceinline__ cplx<T> term(uint32_t id, uint64_t* w) const {
+    string(id, w);
+    return rot_ik(ph[id], c[id]);
+  }
+  __device__ __forceinline__ uint64_t fp(uint32_t id) const { return f[id]; }
+};
+
+template <int WT>
+__device__ __forceinline__ bool words_equal(const uint64_t* a, const uint64_t* b, int nw) {
+  uint64_t d = 0;
+#pragma unroll
+  for (int q = 0; q < 2 * WT; ++q) {
+    if (WT > 8 && q >= 2 * nw) break;
+    d |= a[q] ^ b[q];
+  }
+  return d == 0;
+}
+
+// Packed-word order used to break fingerprint ties: X words from the most
+// significant word down, then Z words likewise.
+template <int WT>
+__device__ __forceinline__ int words_cmp(const uint64_t* a, const uint64_t* b, int nw) {
+  for (int q = nw - 1; q >= 0; --q)
+    if (a[q] != b[q]) return a[q] < b[q] ? -1 : 1;
+  for (int q = nw - 1; q >= 0; --q)
+    if (a[nw + q] != b[nw + q]) return a[nw + q] < b[nw + q] ? -1 : 1;
+  return 0;
+}
+
+// --------------------------------------------------------------- kernels
+
+__global__ void k_pair_records(const uint64_t* __restrict__ fa, const uint64_t* __restrict__ fb,
+                               uint32_t ma, int64_t P, int kshift, uint64_t* __restrict__ keys,
+                               uint32_t* __restrict__ vals) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = static_cast<uint32_t>(p) / ma;
+    const uint32_t i = static_cast<uint32_t>(p) - j * ma;
+    keys[p] = (fa[i] ^ fb[j]) >> kshift;
+    vals[p] = static_cast<uint32_t>(p);
+  }
+}
+
+__global__ void k_term_records(const uint64_t* __restrict__ f, int64_t m, int kshift,
+                               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    keys[t] = f[t] >> kshift;
+    vals[t] = static_cast<uint32_t>(t);
+  }
+}
+
+// head[r] in {0, 1}; v[r] = value of record r; *dirty |= 1 when a key run
+// holds more than one string.  second_pass: only run if *dirty, and do not
+// raise it again.
+template <int WT, typename T, typename Src>
+__global__ void __launch_bounds__(kBlock)
+k_heads(Src src, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t N,
+        uint32_t* __restrict__ head, cplx<T>* __restrict__ v, uint32_t* __restrict__ dirty,
+        int second_pass) {
+  if (second_pass && *dirty == 0) return;
+  uint64_t w[2 * WT], pw[2 * WT];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t id = vals[r];
+    v[r] = src.term(id, w);
+    uint32_t h = 1;
+    if (r > 0 && keys[r] == keys[r - 1]) {
+      src.string(vals[r - 1], pw);
+      if (words_equal<WT>(w, pw, src.nw))
+        h = 0;
+      else if (!second_pass)
+        atomicOr(dirty, 1u);
+    }
+    head[r] = h;
+  }
+}
+
+// Re-orders every key run that holds several strings by (packed words, id),
+// so that equal strings become adjacent.  One thread per run, insertion sort
+// in place: runs with fingerprint ties are rare and short.
+template <int WT, typename Src>
+__global__ void k_fix_runs(Src src, const uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                           const uint32_t* __restrict__ head, int64_t N,
+                           const uint32_t* __restrict__ dirty) {
+  if (*dirty == 0) return;
+  uint64_t a[2 * WT], b[2 * WT];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    if (r > 0 && keys[r] == keys[r - 1]) continue;  // not a run start
+    int64_t e = r + 1;
+    bool mixed = false;
+    while (e < N && keys[e] == keys[r]) {
+      mixed |= head[e] != 0;
+      ++e;
+    }
+    if (!mixed) continue;
+    for (int64_t x = r + 1; x < e; ++x) {
+      const uint32_t idx = vals[x];
+      src.string(idx, a);
+      int64_t y = x - 1;
+      while (y >= r) {
+        const uint32_t idy = vals[y];
+        src.string(idy, b);
+        const int c = words_cmp<WT>(b, a, src.nw);
+        if (c < 0 || (c == 0 && idy < idx)) break;
+        vals[y + 1] = idy;
+        --y;
+      }
+      vals[y + 1] = idx;
+    }
+  }
+}
+
+__global__ void k_seg_starts(const uint32_t* __restrict__ head, const uint32_t* __restrict__ segid,
+                             int64_t N, const uint32_t* __restrict__ nseg,
+                             uint32_t* __restrict__ seg_start) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * blockDim.x)
+    if (head[r]) seg_start[segid[r]] = static_cast<uint32_t>(r);
+  if (blockIdx.x == 0 && threadIdx.x == 0) seg_start[*nseg] = static_cast<uint32_t>(N);
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
+}
+
+__global__ void k_count_kept(const uint32_t* __restrict__ keep, const uint32_t* __restrict__ outidx,
+                             const uint32_t* __restrict__ nseg, uint32_t* __restrict__ nkept) {
+  const uint32_t U = *nseg;
+  *nkept = U ? outidx[U - 1] + keep[U - 1] : 0u;
+}
+
+template <typename T>
+__device__ __forceinline__ bool keep_value(cplx<T> c, double drop2) {
+  if (drop2 < 0.0) return true;
+  const double re = c.re, im = c.im;
+  return !(re * re + im * im < drop2);
+}
+
+// Short segments: one thread adds its records in order.
+template <typename T>
+__global__ void k_seg_reduce(const cplx<T>* __restrict__ v, const uint32_t* __restrict__ seg_start,
+                             const uint32_t* __restrict__ nseg, cplx<T>* __restrict__ coef,
+                             uint32_t* __restrict__ keep, uint32_t* __restrict__ long_list,
+                             uint32_t* __restrict__ nlong, double drop2) {
+  const uint32_t U = *nseg;
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < U;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t s0 = seg_start[u], s1 = seg_start[u + 1];
+    if (s1 - s0 > kLongSeg) {
+      long_list[atomicAdd(nlong, 1u)] = static_cast<uint32_t>(u);
+      continue;
+    }
+    cplx<T> acc = v[s0];
+    for (uint32_t r = s0 + 1; r < s1; ++r) {
+      acc.re += v[r].re;
+      acc.im += v[r].im;
+    }
+    coef[u] = acc;
+    keep[u] = keep_value(acc, drop2) ? 1u : 0u;
+  }
+}
+
+// Long segments: one block each; thread t adds records t, t+256, ... in
+// order, then a fixed pairwise tree combines the 256 partial sums.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_seg_reduce_long(const cplx<T>* __restrict__ v, const uint32_t* __restrict__ seg_start,
+                  const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ nlong,
+                  cplx<T>* __restrict__ coef, uint32_t* __restrict__ keep, double drop2) {
+  __shared__ T s_re[kBlock], s_im[kBlock];
+  const uint32_t L = *nlong;
+  for (uint32_t b = blockIdx.x; b < L; b += gridDim.x) {
+    const uint32_t u = long_list[b];
+    const uint32_t s0 = seg_start[u], s1 = seg_start[u + 1];
+    T re = 0, im = 0;
+    for (uint32_t r = s0 + threadIdx.x; r < s1; r += kBlock) {
+      re += v[r].re;
+      im += v[r].im;
+    }
+    s_re[threadIdx.x] = re;
+    s_im[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) {
+        s_re[threadIdx.x] += s_re[threadIdx.x + h];
+        s_im[threadIdx.x] += s_im[threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      cplx<T> c{s_re[0], s_im[0]};
+      coef[u] = c;
+      keep[u] = keep_value(c, drop2) ? 1u : 0u;
+    }
+    __syncthreads();
+  }
+}
+
+template <int WT, typename T, typename Src>
+__global__ void __launch_bounds__(kBlock)
+k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ seg_start,
+               const uint32_t* __restrict__ nseg, const uint32_t* __restrict__ keep,
+               const uint32_t* __restrict__ outidx, const cplx<T>* __restrict__ coef,
+               uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ, uint8_t* __restrict__ Oph,
+               cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp, int64_t ldo) {
+  const uint32_t U = *nseg;
+  uint64_t w[2 * WT];
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < U;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    if (!keep[u]) continue;
+    const int64_t o = outidx[u];
+    const uint32_t id = vals[seg_start[u]];
+    src.string(id, w);
+#pragma unroll
+    for (int q = 0; q < WT; ++q) {
+      if (WT > 8 && q >= src.nw) break;
+      OX[q * ldo + o] = w[q];
+      OZ[q * ldo + o] = w[src.nw + q];
+    }
+    Oph[o] = 0;
+    Oc[o] = coef[u];
+    Ofp[o] = src.fp(id);
+  }
+}
+
+// -------------------------------------------------------------- pipeline
+
+template <int WT, typename T, typename Src>
+paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf& keys_buf,
+                       DBuf& vals_buf, const MergeArgs& o, hipStream_t s) {
+  uint64_t* keys = keys_buf.as<uint64_t>();
+  uint32_t* vals = vals_buf.as<uint32_t>();
+  DBuf keys_alt(N * sizeof(uint64_t), s), vals_alt(N * sizeof(uint32_t), s);
+  DBuf rwork(radix_workspace_bytes(N), s);
+  if (radix_sort_pairs(keys, vals, keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(), N,
+                       o.key_bits, rwork.p, s)) {
+    keys = keys_alt.as<uint64_t>();
+    vals = vals_alt.as<uint32_t>();
+  }
+  rwork.reset();
+
+  // counters: [0] dirty, [1] segments, [2] kept, [3] long segments
+  DBuf ctr_buf(64, s);
+  uint32_t* ctr = ctr_buf.as<uint32_t>();
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ctr, 16);
+  DBuf head_buf(N * sizeof(uint32_t), s), segid_buf(N * sizeof(uint32_t), s);
+  DBuf v_buf(N * sizeof(cplx<T>), s);
+  uint32_t* head = head_buf.as<uint32_t>();
+  uint32_t* segid = segid_buf.as<uint32_t>();
+  cplx<T>* v = v_buf.as<cplx<T>>();
+
+  const unsigned g = grid_for(N);
+  hipLaunchKernelGGL((k_heads<WT, T, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
+                     v, ctr + 0, 0);
+  hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, head, N,
+                     ctr + 0);
+  hipLaunchKernelGGL((k_heads<WT, T, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
+                     v, ctr + 0, 1);
+  PAULI_HIP(hipGetLastError());
+
+  DBuf swork(scan_workspace_bytes(N), s);
+  scan_exclusive_u32(head, segid, N, ctr + 1, swork.p, s);
+  DBuf seg_buf((N + 1) * sizeof(uint32_t), s);
+  uint32_t* seg_start = seg_buf.as<uint32_t>();
+  hipLaunchKernelGGL(k_seg_starts, dim3(g), dim3(kBlock), 0, s, head, segid, N, ctr + 1, seg_start);
+  head_buf.reset();
+
+  DBuf coef_buf(N * sizeof(cplx<T>), s);
+  cplx<T>* coef = coef_buf.as<cplx<T>>();
+  uint32_t* keep = segid;  // segid is dead after k_seg_starts
+  DBuf long_buf(N * sizeof(uint32_t), s);
+  uint32_t* long_list = long_buf.as<uint32_t>();
+  const double drop2 = o.drop_abs < 0.0 ? -1.0 : o.drop_abs * o.drop_abs;
+  hipLaunchKernelGGL((k_seg_reduce<T>), dim3(g), dim3(kBlock), 0, s, v, seg_start, ctr + 1, coef,
+                     keep, long_list, ctr + 3, drop2);
+  hipLaunchKernelGGL((k_seg_reduce_long<T>), dim3(1024), dim3(kBlock), 0, s, v, seg_start,
+                     long_list, ctr + 3, coef, keep, drop2);
+  PAULI_HIP(hipGetLastError());
+  v_buf.reset();
+  long_buf.reset();
+
+  // keep[u] is defined for u < #segments only; entries past it do not
+  // affect outidx[u] for u < #segments (an exclusive scan looks backwards).
+  DBuf outidx_buf(N * sizeof(uint32_t), s);
+  uint32_t* outidx = outidx_buf.as<uint32_t>();
+  scan_exclusive_u32(keep, outidx, N, nullptr, swork.p, s);
+  hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(1), 0, s, keep, outidx, ctr + 1, ctr + 2);
+
+  uint32_t host_ctr[4];
+  PAULI_HIP(hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipStreamSynchronize(s));
+  const uint32_t nseg = host_ctr[1];
+  const int64_t U = host_ctr[2];
+
+  paulisum* out = new_sum(n, U, U, dt, s);
+  if (U > 0) {
+    hipLaunchKernelGGL((k_write_output<WT, T, Src>), dim3(grid_for(nseg)), dim3(kBlock), 0, s, src,
+                       vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z, out->ph,
+                       static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
+    PAULI_HIP(hipGetLastError());
+  }
+  return out;
+}
+
+template <int WT, typename T>
+paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  const int kshift = 64 - o.key_bits;
+  if (b == nullptr) {
+    const int64_t N = a->m;
+    DBuf keys(N * sizeof(uint64_t), s), vals(N * sizeof(uint32_t), s);
+    hipLaunchKernelGGL(k_term_records, dim3(grid_for(N)), dim3(kBlock), 0, s, a->fp, N, kshift,
+                       keys.as<uint64_t>(), vals.as<uint32_t>());
+    PAULI_HIP(hipGetLastError());
+    TermSrc<WT, T> src{a->X, a->Z, a->ph, static_cast<const cplx<T>*>(a->coef), a->fp, a->ld, a->W};
+    return run_pipeline<WT, T>(src, a->n, N, a->dtype, keys, vals, o, s);
+  }
+  const int64_t N = a->m * b->m;
+  const int W = a->W;
+  DBuf ra(a->m * 2 * W * sizeof(uint64_t), s), ea(a->m, s);
+  DBuf rb(b->m * 2 * W * sizeof(uint64_t), s), eb(b->m, s);
+  launch_prep_side(a, ra.as<uint64_t>(), ea.as<uint8_t>(), s);
+  launch_prep_side(b, rb.as<uint64_t>(), eb.as<uint8_t>(), s);
+  DBuf keys(N * sizeof(uint64_t), s), vals(N * sizeof(uint32_t), s);
+  hipLaunchKernelGGL(k_pair_records, dim3(grid_for(N)), dim3(kBlock), 0, s, a->fp, b->fp,
+                     static_cast<uint32_t>(a->m), N, kshift, keys.as<uint64_t>(),
+                     vals.as<uint32_t>());
+  PAULI_HIP(hipGetLastError());
+  PairSrc<WT, T> src{ra.as<uint64_t>(), ea.as<uint8_t>(), static_cast<const cplx<T>*>(a->coef),
+                     a->fp, rb.as<uint64_t>(), eb.as<uint8_t>(),
+                     static_cast<const cplx<T>*>(b->coef), b->fp, static_cast<uint32_t>(a->m), W};
+  return run_pipeline<WT, T>(src, a->n, N, a->dtype, keys, vals, o, s);
+}
+
+template <typename T>
+paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  switch (a->W) {
+    case 1: return merge_t<1, T>(a, b, o, s);
+    case 2: return merge_t<2, T>(a, b, o, s);
+    case 3: return merge_t<3, T>(a, b, o, s);
+    case 4: return merge_t<4, T>(a, b, o, s);
+    case 5: return merge_t<5, T>(a, b, o, s);
+    case 6: return merge_t<6, T>(a, b, o, s);
+    case 7: return merge_t<7, T>(a, b, o, s);
+    case 8: return merge_t<8, T>(a, b, o, s);
+    default: return merge_t<kMaxWords, T>(a, b, o, s);
+  }
+}
+
+}  // namespace
+
+paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  if (a->dtype == PAULI_C128) return merge_w<double>(a, b, o, s);
+  return merge_w<float>(a, b, o, s);
+}
+
+}  // namespace pauli

@@ -1,0 +1,263 @@
+// Device-wide exclusive scan and a stable LSD radix sort of (64-bit key,
+// 32-bit value) records.  The sort is the "sort an index array by a
+// fixed-width key" step of sort-and-combine (Section III-H), done as radix
+// passes of 8-bit digits: per-tile digit counts, one scan of the counts,
+// then a stable in-tile rank (wave ballots) and a coalesced scatter through
+// LDS.
+#include "common.h"
+#include "internal.h"
+
+namespace pauli {
+
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+constexpr int kRsBlock = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsBlock * kRsItems;
+constexpr int kRsWaves = kRsBlock / 64;
+
+// Inclusive scan across one wave64.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan across a block of kScanBlock threads; *total gets the sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* total) {
+  __shared__ T s_w[kScanBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T inc = wave_inclusive_scan(v);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  T base = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kScanBlock / 64; ++w) {
+    if (w < wave) base += s_w[w];
+    all += s_w[w];
+  }
+  __syncthreads();
+  if (total) *total = all;
+  return base + inc - v;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ partial) {
+  const int64_t base = blockIdx.x * (int64_t)kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r * kScanBlock + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t tot;
+  block_exclusive_scan<uint32_t>(s, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_partials(uint32_t* __restrict__ partial, int64_t nb, uint32_t* __restrict__ total) {
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanBlock) {
+    int64_t b = b0 + threadIdx.x;
+    uint32_t v = b < nb ? partial[b] : 0;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan<uint32_t>(v, &tot);
+    if (b < nb) partial[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __restrict__ partial) {
+  const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r;
+    v[r] = i < n ? in[i] : 0;
+    s += v[r];
+  }
+  uint32_t run = partial[blockIdx.x] + block_exclusive_scan<uint32_t>(s, nullptr);
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r;
+    if (i < n) out[i] = run;
+    run += v[r];
+  }
+}
+
+// ----------------------------------------------------------------- radix
+
+__global__ void __launch_bounds__(kRsBlock)
+k_rs_count(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ counts,
+           int64_t ntiles) {
+  __shared__ uint32_t hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * (int64_t)kRsTile;
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    int64_t i = base + r * kRsBlock + threadIdx.x;
+    if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  counts[threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Stable scatter of one tile.  Records are visited in rounds of 256
+// consecutive positions; inside a round each wave finds the lanes holding the
+// same digit with eight ballots, so the rank of a record among equal digits
+// is (earlier rounds) + (earlier waves of this round) + (earlier lanes of its
+// wave): exactly its order in the input.  Records are first placed in LDS
+// grouped by digit, then written out in LDS order so that each digit's run
+// is stored contiguously.
+__global__ void __launch_bounds__(kRsBlock)
+k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
+             const uint32_t* __restrict__ offsets, int64_t ntiles) {
+  __shared__ uint64_t s_k[kRsTile];
+  __shared__ uint32_t s_v[kRsTile];
+  __shared__ uint32_t s_hist[256], s_start[256], s_run[256], s_goff[256];
+  __shared__ uint32_t s_wc[kRsWaves][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = blockIdx.x * (int64_t)kRsTile;
+  s_hist[tid] = 0;
+  s_run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kRsWaves; ++w) s_wc[w][tid] = 0;
+  s_goff[tid] = offsets[tid * ntiles + blockIdx.x];
+  __syncthreads();
+
+  uint64_t k[kRsItems];
+  uint32_t v[kRsItems];
+  int d[kRsItems];
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    int64_t i = base + r * kRsBlock + tid;
+    if (i < n) {
+      k[r] = kin[i];
+      v[r] = vin[i];
+      d[r] = static_cast<int>((k[r] >> shift) & 255);
+      atomicAdd(&s_hist[d[r]], 1u);
+    } else {
+      k[r] = 0;
+      v[r] = 0;
+      d[r] = -1;
+    }
+  }
+  __syncthreads();
+  {
+    uint32_t h = s_hist[tid];
+    uint32_t ex = block_exclusive_scan<uint32_t>(h, nullptr);
+    s_start[tid] = ex;
+  }
+  __syncthreads();
+
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < kRsItems; ++r) {
+    const bool valid = d[r] >= 0;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = valid && ((d[r] >> b) & 1);
+      const uint64_t bm = __ballot(bit);
+      peers &= bit ? bm : ~bm;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) s_wc[wave][d[r]] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t off = s_start[d[r]] + s_run[d[r]];
+      for (int w = 0; w < wave; ++w) off += s_wc[w][d[r]];
+      off += rank;
+      s_k[off] = k[r];
+      s_v[off] = v[r];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kRsWaves; ++w) {
+      add += s_wc[w][tid];
+      s_wc[w][tid] = 0;
+    }
+    s_run[tid] += add;
+    __syncthreads();
+  }
+
+  const int64_t cnt = (n - base) < kRsTile ? (n - base) : kRsTile;
+  for (int e = tid; e < cnt; e += kRsBlock) {
+    const uint64_t kk = s_k[e];
+    const int dd = static_cast<int>((kk >> shift) & 255);
+    const int64_t g = static_cast<int64_t>(s_goff[dd]) + (e - static_cast<int64_t>(s_start[dd]));
+    kout[g] = kk;
+    vout[g] = s_v[e];
+  }
+}
+
+}  // namespace
+
+size_t scan_workspace_bytes(int64_t n) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  return static_cast<size_t>(nb + 1) * sizeof(uint32_t) + 256;
+}
+
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                        void* work, hipStream_t s) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  uint32_t* partial = static_cast<uint32_t*>(work);
+  if (n > 0)
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, partial);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBlock), 0, s, partial, nb, total);
+  if (n > 0)
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
+                       partial);
+  PAULI_HIP(hipGetLastError());
+}
+
+size_t radix_workspace_bytes(int64_t n) {
+  int64_t ntiles = (n + kRsTile - 1) / kRsTile;
+  if (ntiles < 1) ntiles = 1;
+  size_t counts = static_cast<size_t>(256 * ntiles + 1) * sizeof(uint32_t);
+  counts = (counts + 255) & ~size_t(255);
+  return counts + scan_workspace_bytes(256 * ntiles);
+}
+
+bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                      int64_t n, int key_bits, void* work, hipStream_t s) {
+  if (n <= 1 || key_bits <= 0) return false;
+  int64_t ntiles = (n + kRsTile - 1) / kRsTile;
+  uint32_t* counts = static_cast<uint32_t*>(work);
+  size_t cbytes = (static_cast<size_t>(256 * ntiles + 1) * sizeof(uint32_t) + 255) & ~size_t(255);
+  void* scan_work = static_cast<char*>(work) + cbytes;
+  bool alt = false;
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    const uint64_t* kin = alt ? keys_alt : keys;
+    const uint32_t* vin = alt ? vals_alt : vals;
+    uint64_t* kout = alt ? keys : keys_alt;
+    uint32_t* vout = alt ? vals : vals_alt;
+    hipLaunchKernelGGL(k_rs_count, dim3((unsigned)ntiles), dim3(kRsBlock), 0, s, kin, n, shift,
+                       counts, ntiles);
+    PAULI_HIP(hipGetLastError());
+    scan_exclusive_u32(counts, counts, 256 * ntiles, nullptr, scan_work, s);
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsBlock), 0, s, kin, vin,
+                       kout, vout, n, shift, counts, ntiles);
+    PAULI_HIP(hipGetLastError());
+    alt = !alt;
+  }
+  return alt;
+}
+
+}  // namespace pauli
