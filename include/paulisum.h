@@ -173,6 +173,27 @@ pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, 
  * and results made by later calls (0 = no limit).  Exceeding it gives OOM. */
 pauli_status_t pauli_set_memory_budget(uint64_t bytes);
 
+/* Diagnostics: device time of each stage, measured with HIP events recorded
+ * on the stream of the call that launched it, and the algorithmic bytes the
+ * stage moves (its compulsory HBM reads and writes, a per-record or per-term
+ * figure times the records or terms it processed).
+ *   pauli_profile_enable(1) clears the totals and starts recording;
+ *   pauli_profile_enable(0) stops.  pauli_profile_read waits for the events
+ *   of finished calls and returns the totals of one stage (NULL pointers are
+ *   skipped).  Recording adds two event records per kernel launch. */
+typedef enum {
+  PAULI_STAGE_OUTER_PRODUCT = 0, /* materialised product kernel */
+  PAULI_STAGE_PREP = 1,          /* operand preparation and record generation */
+  PAULI_STAGE_SORT = 2,          /* global radix passes */
+  PAULI_STAGE_SEGMENT = 3,       /* segment heads and segmented reduction */
+  PAULI_STAGE_WRITE = 4,         /* output of the merged terms */
+  PAULI_STAGE_BUCKET = 5,        /* fused partition-sort-merge kernel */
+  PAULI_STAGE_COUNT = 6
+} pauli_stage_t;
+pauli_status_t pauli_profile_enable(int32_t on);
+pauli_status_t pauli_profile_read(int32_t stage, double* total_ms, int64_t* launches,
+                                  double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

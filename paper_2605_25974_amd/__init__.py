@@ -28,8 +28,9 @@ EXPORTS = (
     "pauli_status_string", "pauli_last_error", "paulisum_create", "paulisum_destroy",
     "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
-    "pauli_set_memory_budget",
+    "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read",
 )
+STAGES = ("outer_product", "prep", "sort", "segment", "write", "bucket")
 
 
 class PauliLibraryMissing(RuntimeError):
@@ -65,6 +66,12 @@ def lib():
         raise PauliLibraryMissing(
             "libpaulisum.so is not built (run __graft_entry__.build() or "
             "python paper_2605_25974_amd/build.py); there is no CPU fallback")
+    # Load torch's HIP runtime first so that the library and torch share one
+    # runtime (both link libamdhip64.so.7 by soname).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     st = ctypes.c_int
     L.pauli_status_string.restype = ctypes.c_char_p
@@ -96,6 +103,12 @@ def lib():
     L.pauli_set_allocator.argtypes = [_vp, _vp, _vp]
     L.pauli_set_memory_budget.restype = st
     L.pauli_set_memory_budget.argtypes = [ctypes.c_uint64]
+    L.pauli_profile_enable.restype = st
+    L.pauli_profile_enable.argtypes = [ctypes.c_int32]
+    L.pauli_profile_read.restype = st
+    L.pauli_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
 
@@ -307,3 +320,21 @@ def use_torch_allocator(enable=True):
     _hooks = (_ALLOC_T(_alloc), _FREE_T(_free))
     _check(lib().pauli_set_allocator(ctypes.cast(_hooks[0], _vp), ctypes.cast(_hooks[1], _vp),
                                      None))
+
+
+def profile_enable(on=True):
+    """Start (clearing totals) or stop per-stage HIP-event timing."""
+    _check(lib().pauli_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """{stage: (total_ms, launches, algorithmic_bytes)} for stages that ran."""
+    out = {}
+    for i, name in enumerate(STAGES):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        by = ctypes.c_double()
+        _check(lib().pauli_profile_read(i, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        if n.value:
+            out[name] = (ms.value, n.value, by.value)
+    return out

@@ -75,6 +75,17 @@ inline size_t coef_bytes(pauli_dtype_t t) { return t == PAULI_C128 ? 16 : 8; }
 paulisum* new_sum(int n, int64_t m, int64_t ld, pauli_dtype_t dt, hipStream_t s);
 void free_sum(paulisum* p);
 
+// ---------------------------------------------------------------- profiling
+// Records HIP events around a stage on its stream while profiling is on.
+struct StageScope {
+  StageScope(int stage, hipStream_t s, double bytes);
+  ~StageScope();
+  int stage;
+  hipStream_t s;
+  double bytes;
+  hipEvent_t a = nullptr;
+};
+
 // --------------------------------------------------------------- launchers
 // k_basic.hip
 void launch_rows_to_soa(const uint64_t* rows, int W, int64_t m, uint64_t* soa, int64_t ld,

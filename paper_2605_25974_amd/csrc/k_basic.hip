@@ -127,6 +127,10 @@ void outer_product_t(const paulisum* a, const paulisum* b, paulisum* o, hipStrea
   const int64_t P = a->m * b->m;
   if (P == 0) return;
   const unsigned g = grid_for(P);
+  // compulsory traffic: the P products written (2W words, phase, coefficient,
+  // fingerprint); the operands are read once from HBM and then from cache
+  const double per = 16.0 * a->W + sizeof(cplx<T>) + 1 + 8;
+  StageScope sc(PAULI_STAGE_OUTER_PRODUCT, s, per * P);
   auto Ac = static_cast<const cplx<T>*>(a->coef);
   auto Bc = static_cast<const cplx<T>*>(b->coef);
   auto Oc = static_cast<cplx<T>*>(o->coef);

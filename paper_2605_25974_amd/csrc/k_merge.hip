@@ -17,6 +17,8 @@
 //
 // The same pipeline serves a materialised sum (term source) and the fused
 // outer product (pair source, no product is ever stored).
+#include <memory>
+
 #include "common.h"
 #include "internal.h"
 
@@ -363,6 +365,8 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf&
   cplx<T>* v = v_buf.as<cplx<T>>();
 
   const unsigned g = grid_for(N);
+  auto sc_seg = std::make_unique<StageScope>(PAULI_STAGE_SEGMENT, s,
+                                             N * (12.0 + 4.0 + sizeof(cplx<T>)));
   hipLaunchKernelGGL((k_heads<WT, T, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
                      v, ctr + 0, 0);
   hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, head, N,
@@ -389,6 +393,7 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf&
   hipLaunchKernelGGL((k_seg_reduce_long<T>), dim3(1024), dim3(kBlock), 0, s, v, seg_start,
                      long_list, ctr + 3, coef, keep, drop2);
   PAULI_HIP(hipGetLastError());
+  sc_seg.reset();
   v_buf.reset();
   long_buf.reset();
 
@@ -407,6 +412,7 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf&
 
   paulisum* out = new_sum(n, U, U, dt, s);
   if (U > 0) {
+    StageScope sc_w(PAULI_STAGE_WRITE, s, U * (16.0 * src.nw + sizeof(cplx<T>) + 1 + 8));
     hipLaunchKernelGGL((k_write_output<WT, T, Src>), dim3(grid_for(nseg)), dim3(kBlock), 0, s, src,
                        vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z, out->ph,
                        static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
@@ -421,6 +427,7 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   if (b == nullptr) {
     const int64_t N = a->m;
     DBuf keys(N * sizeof(uint64_t), s), vals(N * sizeof(uint32_t), s);
+    StageScope sc(PAULI_STAGE_PREP, s, N * 20.0);
     hipLaunchKernelGGL(k_term_records, dim3(grid_for(N)), dim3(kBlock), 0, s, a->fp, N, kshift,
                        keys.as<uint64_t>(), vals.as<uint32_t>());
     PAULI_HIP(hipGetLastError());
@@ -434,6 +441,7 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   launch_prep_side(a, ra.as<uint64_t>(), ea.as<uint8_t>(), s);
   launch_prep_side(b, rb.as<uint64_t>(), eb.as<uint8_t>(), s);
   DBuf keys(N * sizeof(uint64_t), s), vals(N * sizeof(uint32_t), s);
+  StageScope sc(PAULI_STAGE_PREP, s, N * 12.0);
   hipLaunchKernelGGL(k_pair_records, dim3(grid_for(N)), dim3(kBlock), 0, s, a->fp, b->fp,
                      static_cast<uint32_t>(a->m), N, kshift, keys.as<uint64_t>(),
                      vals.as<uint32_t>());

@@ -248,6 +248,9 @@ bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32
     const uint32_t* vin = alt ? vals_alt : vals;
     uint64_t* kout = alt ? keys : keys_alt;
     uint32_t* vout = alt ? vals : vals_alt;
+    // one pass reads the keys for the counts, then reads and writes the
+    // 12-byte records
+    StageScope sc(PAULI_STAGE_SORT, s, 32.0 * n);
     hipLaunchKernelGGL(k_rs_count, dim3((unsigned)ntiles), dim3(kRsBlock), 0, s, kin, n, shift,
                        counts, ntiles);
     PAULI_HIP(hipGetLastError());
