@@ -80,10 +80,12 @@ void free_sum(paulisum* p);
 struct StageScope {
   StageScope(int stage, hipStream_t s, double bytes);
   ~StageScope();
+  void stop();  // records the end event now (else at destruction)
   int stage;
   hipStream_t s;
   double bytes;
   hipEvent_t a = nullptr;
+  hipEvent_t b = nullptr;
 };
 
 // --------------------------------------------------------------- launchers
@@ -129,5 +131,9 @@ struct MergeArgs {
 };
 // merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
+
+// k_bucket.hip: merge(a*b) by the fused bucket kernel; nullptr when a
+// fingerprint collision or a bucket overflow asks for merge_generic instead.
+paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
 
 }  // namespace pauli

@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "sources.h"
 
 namespace pauli {
 
@@ -34,110 +35,6 @@ inline unsigned grid_for(int64_t n, int per_block = kBlock) {
   if (g < 1) g = 1;
   if (g > (1 << 30)) g = 1 << 30;
   return static_cast<unsigned>(g);
-}
-
-// ------------------------------------------------------------- sources
-
-// A product a_i * b_j addressed by p = j*ma + i.
-template <int WT, typename T>
-struct PairSrc {
-  const uint64_t* ra;
-  const uint8_t* ea;
-  const cplx<T>* ca;
-  const uint64_t* fa;
-  const uint64_t* rb;
-  const uint8_t* eb;
-  const cplx<T>* cb;
-  const uint64_t* fb;
-  uint32_t ma;
-  int nw;
-
-  __device__ __forceinline__ void split(uint32_t id, uint32_t& i, uint32_t& j) const {
-    j = id / ma;
-    i = id - j * ma;
-  }
-  __device__ __forceinline__ void string(uint32_t id, uint64_t* w) const {
-    uint32_t i, j;
-    split(id, i, j);
-    const uint64_t* A = ra + (size_t)i * 2 * nw;
-    const uint64_t* B = rb + (size_t)j * 2 * nw;
-#pragma unroll
-    for (int q = 0; q < 2 * WT; ++q) {
-      if (WT > 8 && q >= 2 * nw) break;
-      w[q] = A[q] ^ B[q];
-    }
-  }
-  // Product string (into w) and value i^k * c_a * c_b.
-  __device__ __forceinline__ cplx<T> term(uint32_t id, uint64_t* w) const {
-    uint32_t i, j;
-    split(id, i, j);
-    const uint64_t* A = ra + (size_t)i * 2 * nw;
-    const uint64_t* B = rb + (size_t)j * 2 * nw;
-    int acc = ea[i] + eb[j];
-#pragma unroll
-    for (int q = 0; q < WT; ++q) {
-      if (WT > 8 && q >= nw) break;
-      const uint64_t xa = A[q], za = A[nw + q], xb = B[q], zb = B[nw + q];
-      const uint64_t x = xa ^ xb, z = za ^ zb;
-      acc += 2 * popc64(za & xb) - popc64(x & z);
-      w[q] = x;
-      w[nw + q] = z;
-    }
-    return rot_ik(acc, cmul(ca[i], cb[j]));
-  }
-  __device__ __forceinline__ uint64_t fp(uint32_t id) const {
-    uint32_t i, j;
-    split(id, i, j);
-    return fa[i] ^ fb[j];
-  }
-};
-
-// Term t of a stored sum.
-template <int WT, typename T>
-struct TermSrc {
-  const uint64_t* X;
-  const uint64_t* Z;
-  const uint8_t* ph;
-  const cplx<T>* c;
-  const uint64_t* f;
-  int64_t ld;
-  int nw;
-
-  __device__ __forceinline__ void string(uint32_t id, uint64_t* w) const {
-#pragma unroll
-    for (int q = 0; q < WT; ++q) {
-      if (WT > 8 && q >= nw) break;
-      w[q] = X[q * ld + id];
-      w[nw + q] = Z[q * ld + id];
-    }
-  }
-  __device__ __forceinline__ cplx<T> term(uint32_t id, uint64_t* w) const {
-    string(id, w);
-    return rot_ik(ph[id], c[id]);
-  }
-  __device__ __forceinline__ uint64_t fp(uint32_t id) const { return f[id]; }
-};
-
-template <int WT>
-__device__ __forceinline__ bool words_equal(const uint64_t* a, const uint64_t* b, int nw) {
-  uint64_t d = 0;
-#pragma unroll
-  for (int q = 0; q < 2 * WT; ++q) {
-    if (WT > 8 && q >= 2 * nw) break;
-    d |= a[q] ^ b[q];
-  }
-  return d == 0;
-}
-
-// Packed-word order used to break fingerprint ties: X words from the most
-// significant word down, then Z words likewise.
-template <int WT>
-__device__ __forceinline__ int words_cmp(const uint64_t* a, const uint64_t* b, int nw) {
-  for (int q = nw - 1; q >= 0; --q)
-    if (a[q] != b[q]) return a[q] < b[q] ? -1 : 1;
-  for (int q = nw - 1; q >= 0; --q)
-    if (a[nw + q] != b[nw + q]) return a[nw + q] < b[nw + q] ? -1 : 1;
-  return 0;
 }
 
 // --------------------------------------------------------------- kernels

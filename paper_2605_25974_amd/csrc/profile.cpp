@@ -55,14 +55,27 @@ StageScope::StageScope(int st, hipStream_t str, double by) : stage(st), s(str), 
   PAULI_HIP(hipEventRecord(a, s));
 }
 
-StageScope::~StageScope() {
-  if (!a) return;
+void StageScope::stop() {
+  if (!a || b) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  hipEvent_t b = take_event();
+  b = take_event();
   if (hipEventRecord(b, s) != hipSuccess) {
     (void)hipGetLastError();
+    g_pool.push_back(b);
+    g_pool.push_back(a);
+    a = b = nullptr;
+  }
+}
+
+StageScope::~StageScope() {
+  if (!a) return;
+  try {
+    stop();
+  } catch (...) {
     return;
   }
+  if (!a || !b) return;
+  std::lock_guard<std::mutex> lk(g_mu);
   g_pending.push_back({stage, a, b, bytes});
 }
 
