@@ -7,7 +7,7 @@
 
 #include <string>
 
-#include "../../include/paulisum.h"
+#include "paulisum.h"
 
 namespace pauli {
 constexpr int kMaxWordsHost = 16;  // n <= 1024

@@ -41,21 +41,33 @@ constexpr int kWaves = kNT / 64;          // 8
 constexpr int kCapF = 2048;               // fresh records per chunk
 constexpr int kCapR = 1024;               // running entries carried between chunks
 constexpr int kCapE = kCapF + kCapR;      // entries per chunk
-constexpr int kPerWave = kCapE / kWaves;  // contiguous positions owned by a wave
-constexpr int kRounds = kPerWave / 64;    // rounds of 64 positions per wave
-constexpr int kOItems = 4;                // O terms per thread per enumeration tile
+constexpr int kPerWave = kCapE / kWaves;  // most positions a wave can own
+constexpr int kRounds = kPerWave / 64;    // most rounds of 64 positions per wave
+constexpr int kOItems = 8;                // O terms per thread per enumeration tile
 constexpr int kOTile = kNT * kOItems;
+
+// Positions [0, N) are split into kWaves contiguous spans of whole rounds;
+// wave w owns [w*span, (w+1)*span).
+__device__ __forceinline__ uint32_t wave_span(uint32_t N) {
+  return ((N + 64 * kWaves - 1) / (64 * kWaves)) * 64;
+}
 constexpr double kTargetBucket = 1536.0;  // mean records per bucket
 
 enum : uint32_t { kErrCollision = 1u, kErrCapacity = 2u, kErrTimeout = 4u };
+
+struct IRec {
+  uint64_t key;
+  uint32_t idx;
+  uint32_t pad;
+};
 
 struct BucketArgs {
   const uint64_t* keyO;  // [mO] key of each O term
   const uint32_t* clsO;  // [mO] its top d key bits
   uint32_t mO;
-  const uint64_t* keyI;  // [mI] keys of the I terms, sorted by class
-  const uint32_t* idxI;  // [mI] their term index
+  const IRec* recI;      // [mI] (key, term index) of the I terms, sorted by class
   const uint2* rangeI;   // [2^d] (first sorted position, count) per class
+  const uint32_t* nzI;   // [2^d / 32] bit c set when class c of I is not empty
   int o_is_a;
   uint32_t ma;           // |a|, for the pair index p = j*|a| + i
   int sort_lo;           // lowest key bit of the in-bucket radix field
@@ -74,6 +86,7 @@ struct BucketArgs {
   void* Oc;
   uint64_t* Ofp;
   int64_t ldo;
+  void* scratch;  // kCapR running entries per block
 };
 
 template <typename T>
@@ -93,8 +106,18 @@ struct Smem {
   uint32_t dvalid[kWaves], did[kWaves], dseg[kWaves];
   uint64_t dkey[kWaves];
   T dre[kWaves], dim[kWaves];
+  uint32_t keep[kCapE / 32];
+  uint32_t kpre[kCapE / 32];
   uint32_t bcast[4];
   unsigned long long out_base;
+};
+
+template <typename T>
+struct RunEntry {
+  uint64_t key;
+  uint32_t id;
+  uint32_t pad;
+  T re, im;
 };
 
 __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t v) {
@@ -127,7 +150,10 @@ __device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t* total, uint
 
 // Appends up to kCapF records of bucket b at entries [base, base + nf).
 // (o_tile, skip) is where the previous chunk stopped; all threads keep the
-// same copy of the state.
+// same copy of the state.  Each thread looks at kOItems consecutive O terms
+// per tile; a class bitmap (small, cache-resident) rejects the terms whose
+// partner class is empty before any range lookup, and all loads of a tile
+// are issued before their results are used.
 template <typename T>
 __device__ uint32_t enumerate_chunk(const BucketArgs& A, uint32_t b, uint32_t base,
                                     uint32_t& o_tile, uint32_t& skip, bool& last, Smem<T>& S) {
@@ -140,42 +166,60 @@ __device__ uint32_t enumerate_chunk(const BucketArgs& A, uint32_t b, uint32_t ba
       break;
     }
     const uint32_t ob = o0 + threadIdx.x * kOItems;
+    uint32_t cls[kOItems];
+    if (ob + kOItems <= A.mO) {
+      const uint4* p = reinterpret_cast<const uint4*>(A.clsO + ob);
+#pragma unroll
+      for (int v = 0; v < kOItems / 4; ++v) {
+        const uint4 x = p[v];
+        cls[4 * v] = x.x;
+        cls[4 * v + 1] = x.y;
+        cls[4 * v + 2] = x.z;
+        cls[4 * v + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kOItems; ++u) cls[u] = ob + u < A.mO ? A.clsO[ob + u] : 0u;
+    }
+    uint32_t nzw[kOItems];
+#pragma unroll
+    for (int u = 0; u < kOItems; ++u) nzw[u] = A.nzI[(cls[u] ^ b) >> 5];
     uint32_t st[kOItems], cn[kOItems];
     uint32_t tsum = 0;
 #pragma unroll
     for (int u = 0; u < kOItems; ++u) {
-      st[u] = 0;
-      cn[u] = 0;
-      if (ob + u < A.mO) {
-        const uint2 r = A.rangeI[A.clsO[ob + u] ^ b];
-        st[u] = r.x;
-        cn[u] = r.y;
-      }
+      const uint32_t c = cls[u] ^ b;
+      const bool nz = ob + u < A.mO && ((nzw[u] >> (c & 31)) & 1u);
+      uint2 r = make_uint2(0u, 0u);
+      if (nz) r = A.rangeI[c];
+      st[u] = r.x;
+      cn[u] = r.y;
       tsum += cn[u];
     }
     uint32_t tile_total;
     uint32_t t0 = block_excl(tsum, &tile_total, S.scan);
     const uint32_t space = kCapF - nf;
     const uint32_t hi = skip + space;  // tile-local window [skip, hi)
+    if (tsum) {
 #pragma unroll
-    for (int u = 0; u < kOItems; ++u) {
-      if (cn[u]) {
-        const uint32_t ks = skip > t0 ? skip - t0 : 0;
-        uint32_t ke = hi > t0 ? hi - t0 : 0;
-        if (ke > cn[u]) ke = cn[u];
-        if (ks < ke) {
-          const uint32_t o = ob + u;
-          const uint64_t ko = A.keyO[o];
-          for (uint32_t k = ks; k < ke; ++k) {
-            const uint32_t ip = st[u] + k;
-            const uint32_t e = base + nf + (t0 + k - skip);
-            S.key[e] = ko ^ A.keyI[ip];
-            const uint32_t other = A.idxI[ip];
-            S.id[e] = A.o_is_a ? other * A.ma + o : o * A.ma + other;
+      for (int u = 0; u < kOItems; ++u) {
+        if (cn[u]) {
+          const uint32_t ks = skip > t0 ? skip - t0 : 0;
+          uint32_t ke = hi > t0 ? hi - t0 : 0;
+          if (ke > cn[u]) ke = cn[u];
+          if (ks < ke) {
+            const uint32_t o = ob + u;
+            const uint64_t ko = A.keyO[o];
+            for (uint32_t k = ks; k < ke; ++k) {
+              const IRec rec = A.recI[st[u] + k];
+              const uint32_t e = base + nf + (t0 + k - skip);
+              S.key[e] = ko ^ rec.key;
+              S.id[e] = A.o_is_a ? rec.idx * A.ma + o : o * A.ma + rec.idx;
+            }
           }
         }
+        t0 += cn[u];
       }
-      t0 += cn[u];
     }
     if (tile_total - skip <= space) {
       nf += tile_total - skip;
@@ -196,9 +240,9 @@ __device__ uint32_t enumerate_chunk(const BucketArgs& A, uint32_t b, uint32_t ba
 }
 
 // ord[0..N) = entries ordered stably by key bits [lo, lo + 8*passes).
-// Wave w owns positions [w*kPerWave, (w+1)*kPerWave), visited in rounds of
-// 64; the rank of an entry among equal digits is the count of equal digits
-// at earlier positions, obtained from eight ballots per round and per-wave
+// Wave w owns positions [w*span, (w+1)*span), visited in rounds of 64; the
+// rank of an entry among equal digits is the count of equal digits at
+// earlier positions, obtained from eight ballots per round and per-wave
 // digit counters.
 template <typename T>
 __device__ void sort_entries(uint32_t N, int lo, int passes, Smem<T>& S) {
@@ -206,6 +250,8 @@ __device__ void sort_entries(uint32_t N, int lo, int passes, Smem<T>& S) {
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t span = wave_span(N);
+  const int rounds = static_cast<int>(span / 64);
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = lo + 8 * pass;
     for (int i = threadIdx.x; i < kWaves * 256; i += kNT) (&S.cnt[0][0])[i] = 0;
@@ -215,7 +261,8 @@ __device__ void sort_entries(uint32_t N, int lo, int passes, Smem<T>& S) {
     int dg[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-      const uint32_t q = wave * kPerWave + r * 64 + lane;
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
       const bool valid = q < N;
       ent[r] = valid ? S.ord[q] : 0;
       dg[r] = valid ? static_cast<int>((S.key[ent[r]] >> shift) & 255) : 0;
@@ -250,12 +297,14 @@ __device__ void sort_entries(uint32_t N, int lo, int passes, Smem<T>& S) {
     uint32_t np[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-      const uint32_t q = wave * kPerWave + r * 64 + lane;
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
       np[r] = q < N ? S.cnt[wave][dg[r]] + rk[r] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-      const uint32_t q = wave * kPerWave + r * 64 + lane;
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
       if (q < N) S.ord[np[r]] = ent[r];
     }
     __syncthreads();
@@ -342,267 +391,261 @@ __device__ __forceinline__ void write_term(const BucketArgs& A, const PairSrc<WT
   A.Ofp[o] = src.fp(id);
 }
 
+// What a segment tail does with its finished sum.
+enum : int {
+  kEmitWrite = 0,      // write the merged term at out_base + segment index
+  kEmitRun = 1,        // store (key, id, sum) as running entry `segment index`
+  kEmitCount = 2,      // set the segment's keep bit (|sum|^2 >= t^2)
+  kEmitWriteKept = 3,  // write the term if its keep bit is set, packed
+};
+
+template <int WT, typename T, int MODE>
+__device__ __forceinline__ void emit(const BucketArgs& A, const PairSrc<WT, T>& src, Smem<T>& S,
+                                     RunEntry<T>* run, unsigned long long out_base, uint32_t seg,
+                                     const uint64_t* w, uint64_t key, uint32_t id, T re, T im) {
+  if (MODE == kEmitWrite) {
+    write_term<WT, T>(A, src, static_cast<int64_t>(out_base + seg), w, re, im, id);
+  } else if (MODE == kEmitRun) {
+    run[seg] = RunEntry<T>{key, id, 0u, re, im};
+  } else if (MODE == kEmitCount) {
+    const double dr = re, di = im;
+    if (!(dr * dr + di * di < A.drop2)) atomicOr(&S.keep[seg >> 5], 1u << (seg & 31));
+  } else {
+    const uint32_t bits = S.keep[seg >> 5];
+    if ((bits >> (seg & 31)) & 1u) {
+      const uint32_t o = S.kpre[seg >> 5] + __popc(bits & ((1u << (seg & 31)) - 1u));
+      write_term<WT, T>(A, src, static_cast<int64_t>(out_base + o), w, re, im, id);
+    }
+  }
+}
+
+// Segmented sums over positions [0, N) in position order: a wave scan inside
+// each round of 64, a carried partial across the rounds of a wave, and the
+// wave carries combined in wave order by one thread, so the additions happen
+// in a fixed order.  Each segment's tail ends with the segment's sum and
+// emits it (MODE).  The tail of the segment already open when a wave's span
+// begins is finished after the wave carries are known.
+template <int WT, typename T, int MODE>
+__device__ void segment_pass(const BucketArgs& A, const PairSrc<WT, T>& src, uint32_t N,
+                             uint32_t nR, uint32_t wbase, unsigned long long out_base, Smem<T>& S,
+                             RunEntry<T>* run) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t span = wave_span(N);
+  const int rounds = static_cast<int>(span / 64);
+  if (lane == 0) S.dvalid[wave] = 0;
+  T cre = 0, cim = 0;
+  bool copen = false;
+  uint32_t hrun = wbase;
+#pragma unroll 1
+  for (int r = 0; r < rounds; ++r) {
+    const uint32_t q = wave * span + r * 64 + lane;
+    const bool valid = q < N;
+    uint32_t e = 0, id = 0;
+    uint64_t k = 0;
+    bool head = false, tail = false;
+    uint64_t w[2 * WT];
+    T vre = 0, vim = 0;
+    if (valid) {
+      e = S.ord[q];
+      k = S.key[e];
+      id = S.id[e];
+      head = q == 0 || S.key[S.ord[q - 1]] != k;
+      tail = q + 1 >= N || S.key[S.ord[q + 1]] != k;
+      const cplx<T> pv = src.term(id, w);
+      if (e < nR) {
+        vre = S.rv[e].re;
+        vim = S.rv[e].im;
+      } else {
+        vre = pv.re;
+        vim = pv.im;
+      }
+    }
+    // equal keys must be equal strings
+    const bool keq = valid && !head;
+    if (__ballot(keq)) {
+      // the predecessor's string: from lane - 1, or rebuilt for lane 0
+      const uint32_t pid = (lane == 0 && keq) ? S.id[S.ord[q - 1]] : 0u;
+      uint64_t diff = 0;
+#pragma unroll
+      for (int t = 0; t < 2 * WT; ++t) {
+        if (WT > 8 && t >= 2 * src.nw) break;
+        uint64_t pw = __shfl_up(w[t], 1, 64);
+        if (lane == 0 && keq) pw = src.word(pid, t);
+        diff |= pw ^ w[t];
+      }
+      if (keq && diff) atomicOr(A.err, kErrCollision);
+    }
+    // segmented inclusive scan within the round
+    bool f = head;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const T ore = __shfl_up(vre, d, 64), oim = __shfl_up(vim, d, 64);
+      const bool of = __shfl_up(static_cast<int>(f), d, 64) != 0;
+      if (lane >= d) {
+        if (!f) {
+          vre = ore + vre;
+          vim = oim + vim;
+        }
+        f = f || of;
+      }
+    }
+    if (!f) {
+      vre = cre + vre;
+      vim = cim + vim;
+    }
+    const bool inwave = f || copen;
+    const uint64_t hb = __ballot(head);
+    const uint32_t seg = hrun + static_cast<uint32_t>(__popcll(hb & (lt | (1ull << lane)))) - 1;
+    if (tail) {
+      if (inwave) {
+        emit<WT, T, MODE>(A, src, S, run, out_base, seg, w, k, id, vre, vim);
+      } else {  // segment open since an earlier wave: finished below
+        S.dvalid[wave] = 1;
+        S.did[wave] = id;
+        S.dseg[wave] = seg;
+        S.dkey[wave] = k;
+        S.dre[wave] = vre;
+        S.dim[wave] = vim;
+      }
+    }
+    cre = __shfl(vre, 63, 64);
+    cim = __shfl(vim, 63, 64);
+    copen = __shfl(static_cast<int>(inwave), 63, 64) != 0;
+    hrun += static_cast<uint32_t>(__popcll(hb));
+  }
+  if (lane == 0) {
+    S.whead[wave] = copen ? 1u : 0u;
+    S.wre[wave] = cre;
+    S.wim[wave] = cim;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T c_re = 0, c_im = 0;
+    for (int v = 0; v < kWaves; ++v) {
+      S.cin_re[v] = c_re;
+      S.cin_im[v] = c_im;
+      if (S.whead[v]) {
+        c_re = S.wre[v];
+        c_im = S.wim[v];
+      } else {
+        c_re = c_re + S.wre[v];
+        c_im = c_im + S.wim[v];
+      }
+    }
+    for (int v = 0; v < kWaves; ++v)
+      if (S.dvalid[v]) {
+        S.dre[v] = S.cin_re[v] + S.dre[v];
+        S.dim[v] = S.cin_im[v] + S.dim[v];
+      }
+  }
+  __syncthreads();
+  if (lane == 0 && S.dvalid[wave]) {
+    uint64_t w[2 * WT];
+    const uint32_t id = S.did[wave];
+    if (MODE == kEmitWrite || MODE == kEmitWriteKept) src.string(id, w);
+    emit<WT, T, MODE>(A, src, S, run, out_base, S.dseg[wave], w, S.dkey[wave], id, S.dre[wave],
+                      S.dim[wave]);
+  }
+  __syncthreads();
+}
+
+// One block per resident slot; each takes buckets by ticket until none are
+// left.  Taking tickets in order keeps the look-back free of deadlock: a
+// bucket only waits for buckets whose tickets were taken by running blocks.
 template <int WT, typename T>
-__global__ void __launch_bounds__(kNT)
+__global__ void __launch_bounds__(kNT, 4)
 k_bucket_merge(BucketArgs A, PairSrc<WT, T> src) {
   __shared__ Smem<T> S;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t lt = (1ull << lane) - 1ull;
-  if (threadIdx.x == 0) S.bcast[0] = atomicAdd(A.ticket, 1u);
-  __syncthreads();
-  const uint32_t b = S.bcast[0];
-  if (b >= A.nbuckets) return;
-
-  uint32_t nR = 0, o_tile = 0, skip = 0;
-  bool last = false;
-  bool published = false;
+  RunEntry<T>* run = static_cast<RunEntry<T>*>(A.scratch) + static_cast<size_t>(blockIdx.x) * kCapR;
   for (;;) {
-    const uint32_t nf = enumerate_chunk(A, b, nR, o_tile, skip, last, S);
-    const uint32_t N = nR + nf;
-    sort_entries(N, A.sort_lo, A.sort_passes, S);
-    fix_runs(N, A.sort_lo, A.field_mask, S);
-
-    // segment heads: count per wave, then the block prefix
-    uint32_t hc = 0;
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const uint32_t q = wave * kPerWave + r * 64 + lane;
-      bool head = false;
-      if (q < N) head = q == 0 || S.key[S.ord[q - 1]] != S.key[S.ord[q]];
-      hc += static_cast<uint32_t>(__popcll(__ballot(head)));
-    }
-    if (lane == 0) S.wcount[wave] = hc;
+    if (threadIdx.x == 0) S.bcast[0] = atomicAdd(A.ticket, 1u);
     __syncthreads();
-    uint32_t wbase = 0, nseg = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = S.wcount[w];
-      if (w < wave) wbase += c;
-      nseg += c;
-    }
-    const bool write_now = last && !A.drop;
-    if (write_now) {
+    const uint32_t b = S.bcast[0];
+    __syncthreads();
+    if (b >= A.nbuckets) return;
+
+    uint32_t nR = 0, o_tile = 0, skip = 0;
+    bool last = false;
+    bool published = false;
+    for (;;) {
+      const uint32_t nf = enumerate_chunk(A, b, nR, o_tile, skip, last, S);
+      const uint32_t N = nR + nf;
+      sort_entries(N, A.sort_lo, A.sort_passes, S);
+      fix_runs(N, A.sort_lo, A.field_mask, S);
+
+      // segment heads: count per wave, then the block prefix
+      const uint32_t span = wave_span(N);
+      uint32_t hc = 0;
+      for (uint32_t r = 0; r * 64 < span; ++r) {
+        const uint32_t q = wave * span + r * 64 + lane;
+        bool head = false;
+        if (q < N) head = q == 0 || S.key[S.ord[q - 1]] != S.key[S.ord[q]];
+        hc += static_cast<uint32_t>(__popcll(__ballot(head)));
+      }
+      if (lane == 0) S.wcount[wave] = hc;
+      __syncthreads();
+      uint32_t wbase = 0, nseg = 0;
+      for (int v = 0; v < kWaves; ++v) {
+        const uint32_t c = S.wcount[v];
+        if (v < wave) wbase += c;
+        nseg += c;
+      }
+
+      if (!last) {
+        // the chunk's segments become the running entries of the next chunk
+        if (nseg > static_cast<uint32_t>(kCapR)) {
+          if (threadIdx.x == 0) atomicOr(A.err, kErrCapacity);
+          break;
+        }
+        segment_pass<WT, T, kEmitRun>(A, src, N, nR, wbase, 0ull, S, run);
+        for (uint32_t t = threadIdx.x; t < nseg; t += kNT) {
+          const RunEntry<T> x = run[t];
+          S.key[t] = x.key;
+          S.id[t] = x.id;
+          S.rv[t] = cplx<T>{x.re, x.im};
+        }
+        __syncthreads();
+        nR = nseg;
+        continue;
+      }
+
+      if (!A.drop) {
+        // the merged count of this bucket is known: take the output range now
+        // and let each tail write its term as soon as its sum is complete
+        if (threadIdx.x == 0) {
+          S.out_base = lookback(A, b, nseg);
+          atomicAdd(A.total, static_cast<unsigned long long>(nseg));
+        }
+        published = true;
+        __syncthreads();
+        segment_pass<WT, T, kEmitWrite>(A, src, N, nR, wbase, S.out_base, S, run);
+        break;
+      }
+
+      // drop threshold: a first pass marks the kept segments, then the
+      // output range is taken and a second pass writes the kept terms
+      for (uint32_t t = threadIdx.x; t < (N + 31) / 32; t += kNT) S.keep[t] = 0;
+      __syncthreads();
+      segment_pass<WT, T, kEmitCount>(A, src, N, nR, wbase, 0ull, S, run);
       if (threadIdx.x == 0) {
-        S.out_base = lookback(A, b, nseg);
-        atomicAdd(A.total, static_cast<unsigned long long>(nseg));
+        uint32_t acc = 0;
+        for (uint32_t t = 0; t < (nseg + 31) / 32; ++t) {
+          S.kpre[t] = acc;
+          acc += __popc(S.keep[t]);
+        }
+        S.out_base = lookback(A, b, acc);
+        atomicAdd(A.total, static_cast<unsigned long long>(acc));
       }
       published = true;
       __syncthreads();
-    }
-    const unsigned long long out_base = write_now ? S.out_base : 0ull;
-    if (lane == 0) S.dvalid[wave] = 0;
-
-    // segmented sums in position order: within a round by a wave scan,
-    // across the rounds of a wave by a carried partial, across waves below
-    T cre = 0, cim = 0;
-    bool copen = false;
-    uint32_t hrun = wbase;
-    bool st_tail[kRounds];
-    uint32_t st_id[kRounds], st_seg[kRounds];
-    uint64_t st_key[kRounds];
-    T st_re[kRounds], st_im[kRounds];
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const uint32_t q = wave * kPerWave + r * 64 + lane;
-      const bool valid = q < N;
-      uint32_t e = 0, id = 0;
-      uint64_t k = 0;
-      bool head = false, tail = false;
-      uint64_t w[2 * WT];
-      T vre = 0, vim = 0;
-      if (valid) {
-        e = S.ord[q];
-        k = S.key[e];
-        id = S.id[e];
-        head = q == 0 || S.key[S.ord[q - 1]] != k;
-        tail = q + 1 >= N || S.key[S.ord[q + 1]] != k;
-        const cplx<T> pv = src.term(id, w);
-        if (e < nR) {
-          vre = S.rv[e].re;
-          vim = S.rv[e].im;
-        } else {
-          vre = pv.re;
-          vim = pv.im;
-        }
-      }
-      // equal keys must be equal strings
-      const bool keq = valid && !head;
-      if (__ballot(keq)) {
-        uint64_t pw[2 * WT];
-#pragma unroll
-        for (int t = 0; t < 2 * WT; ++t) {
-          if (WT > 8 && t >= 2 * src.nw) break;
-          pw[t] = __shfl_up(w[t], 1, 64);
-        }
-        if (lane == 0 && keq) src.string(S.id[S.ord[q - 1]], pw);
-        if (keq && !words_equal<WT>(w, pw, src.nw)) atomicOr(A.err, kErrCollision);
-      }
-      // segmented inclusive scan within the round
-      bool f = head;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const T ore = __shfl_up(vre, d, 64), oim = __shfl_up(vim, d, 64);
-        const bool of = __shfl_up(static_cast<int>(f), d, 64) != 0;
-        if (lane >= d) {
-          if (!f) {
-            vre = ore + vre;
-            vim = oim + vim;
-          }
-          f = f || of;
-        }
-      }
-      if (!f) {
-        vre = cre + vre;
-        vim = cim + vim;
-      }
-      const bool inwave = f || copen;
-      const uint64_t hb = __ballot(head);
-      const uint32_t seg = hrun + static_cast<uint32_t>(__popcll(hb & (lt | (1ull << lane)))) - 1;
-      st_tail[r] = false;
-      if (tail) {
-        if (inwave) {
-          if (write_now)
-            write_term<WT, T>(A, src, static_cast<int64_t>(out_base + seg), w, vre, vim, id);
-          else {
-            st_tail[r] = true;
-            st_id[r] = id;
-            st_seg[r] = seg;
-            st_key[r] = k;
-            st_re[r] = vre;
-            st_im[r] = vim;
-          }
-        } else {  // segment open since an earlier wave: finished below
-          S.dvalid[wave] = 1;
-          S.did[wave] = id;
-          S.dseg[wave] = seg;
-          S.dkey[wave] = k;
-          S.dre[wave] = vre;
-          S.dim[wave] = vim;
-        }
-      }
-      cre = __shfl(vre, 63, 64);
-      cim = __shfl(vim, 63, 64);
-      copen = __shfl(static_cast<int>(inwave), 63, 64) != 0;
-      hrun += static_cast<uint32_t>(__popcll(hb));
-    }
-    if (lane == 0) {
-      S.whead[wave] = copen ? 1u : 0u;
-      S.wre[wave] = cre;
-      S.wim[wave] = cim;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T c_re = 0, c_im = 0;
-      for (int w = 0; w < kWaves; ++w) {
-        S.cin_re[w] = c_re;
-        S.cin_im[w] = c_im;
-        if (S.whead[w]) {
-          c_re = S.wre[w];
-          c_im = S.wim[w];
-        } else {
-          c_re = c_re + S.wre[w];
-          c_im = c_im + S.wim[w];
-        }
-      }
-      for (int w = 0; w < kWaves; ++w)
-        if (S.dvalid[w]) {
-          S.dre[w] = S.cin_re[w] + S.dre[w];
-          S.dim[w] = S.cin_im[w] + S.dim[w];
-        }
-    }
-    __syncthreads();
-
-    if (write_now) {
-      if (lane == 0 && S.dvalid[wave]) {
-        uint64_t w[2 * WT];
-        const uint32_t id = S.did[wave];
-        src.string(id, w);
-        write_term<WT, T>(A, src, static_cast<int64_t>(out_base + S.dseg[wave]), w, S.dre[wave],
-                          S.dim[wave], id);
-      }
+      segment_pass<WT, T, kEmitWriteKept>(A, src, N, nR, wbase, S.out_base, S, run);
       break;
     }
-
-    if (!last) {
-      // the chunk's segments become the running entries of the next chunk
-      if (nseg > static_cast<uint32_t>(kCapR)) {
-        if (threadIdx.x == 0) atomicOr(A.err, kErrCapacity);
-        break;
-      }
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r)
-        if (st_tail[r]) {
-          S.key[st_seg[r]] = st_key[r];
-          S.id[st_seg[r]] = st_id[r];
-          S.rv[st_seg[r]] = cplx<T>{st_re[r], st_im[r]};
-        }
-      if (lane == 0 && S.dvalid[wave]) {
-        const uint32_t sg = S.dseg[wave];
-        S.key[sg] = S.dkey[wave];
-        S.id[sg] = S.did[wave];
-        S.rv[sg] = cplx<T>{S.dre[wave], S.dim[wave]};
-      }
-      __syncthreads();
-      nR = nseg;
-      continue;
-    }
-
-    // last chunk with a drop threshold: keep |c|^2 >= t^2, then write
-    bool dkeep = false;
-    if (S.dvalid[wave]) {
-      const double re = S.dre[wave], im = S.dim[wave];
-      dkeep = !(re * re + im * im < A.drop2);
-    }
-    uint32_t kc = dkeep ? 1u : 0u;
-    bool st_keep[kRounds];
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      st_keep[r] = false;
-      if (st_tail[r]) {
-        const double re = st_re[r], im = st_im[r];
-        st_keep[r] = !(re * re + im * im < A.drop2);
-      }
-      kc += static_cast<uint32_t>(__popcll(__ballot(st_keep[r])));
-    }
-    __syncthreads();  // wcount is reused
-    if (lane == 0) S.wcount[wave] = kc;
+    if (!published && threadIdx.x == 0) lookback(A, b, 0);
     __syncthreads();
-    uint32_t kbase = 0, nkeep = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      const uint32_t c = S.wcount[w];
-      if (w < wave) kbase += c;
-      nkeep += c;
-    }
-    if (threadIdx.x == 0) {
-      S.out_base = lookback(A, b, nkeep);
-      atomicAdd(A.total, static_cast<unsigned long long>(nkeep));
-    }
-    published = true;
-    __syncthreads();
-    const unsigned long long ob = S.out_base;
-    uint32_t run = kbase;
-    if (dkeep) {
-      if (lane == 0) {
-        uint64_t w[2 * WT];
-        src.string(S.did[wave], w);
-        write_term<WT, T>(A, src, static_cast<int64_t>(ob + run), w, S.dre[wave], S.dim[wave],
-                          S.did[wave]);
-      }
-      ++run;
-    }
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const uint64_t km = __ballot(st_keep[r]);
-      if (st_keep[r]) {
-        uint64_t w[2 * WT];
-        src.string(st_id[r], w);
-        write_term<WT, T>(A, src, static_cast<int64_t>(ob + run + __popcll(km & lt)), w, st_re[r],
-                          st_im[r], st_id[r]);
-      }
-      run += static_cast<uint32_t>(__popcll(km));
-    }
-    break;
   }
-  if (!published && threadIdx.x == 0) lookback(A, b, 0);
 }
 
 // ---------------------------------------------------------------- prep
@@ -632,10 +675,23 @@ __global__ void k_class_range(const uint32_t* __restrict__ count, const uint32_t
     range[c] = make_uint2(start[c], count[c]);
 }
 
-__global__ void k_gather_keys(const uint64_t* __restrict__ fp, const uint32_t* __restrict__ idx,
-                              uint32_t m, int kshift, uint64_t* __restrict__ key) {
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
-    key[t] = fp[idx[t]] >> kshift;
+__global__ void k_gather_records(const uint64_t* __restrict__ fp, const uint32_t* __restrict__ idx,
+                                 uint32_t m, int kshift, IRec* __restrict__ rec) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+    const uint32_t i = idx[t];
+    rec[t] = IRec{fp[i] >> kshift, i, 0u};
+  }
+}
+
+__global__ void k_class_bitmap(const uint32_t* __restrict__ count, uint32_t nc,
+                               uint32_t* __restrict__ bits) {
+  const uint32_t nw = (nc + 31) / 32;
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+    uint32_t v = 0;
+    for (uint32_t t = 0; t < 32 && 32 * w + t < nc; ++t)
+      if (count[32 * w + t]) v |= 1u << t;
+    bits[w] = v;
+  }
 }
 
 __global__ void k_bucket_init(uint32_t* ctr, int nctr, unsigned long long* status, uint32_t n) {
@@ -690,7 +746,8 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   DBuf rb(b->m * 2 * W * sizeof(uint64_t), s), eb(b->m, s);
   DBuf keyO(mO * 8ull, s), clsO(mO * 4ull, s);
   DBuf clsI(mI * 8ull, s), clsI2(mI * 8ull, s), idxI(mI * 4ull, s), idxI2(mI * 4ull, s);
-  DBuf keyI(mI * 8ull, s), cnt(nb * 4ull, s), start(nb * 4ull + 4, s), range(nb * 8ull, s);
+  DBuf recI(mI * sizeof(IRec), s), cnt(nb * 4ull, s), start(nb * 4ull + 4, s);
+  DBuf range(nb * 8ull, s), nzI(((nb + 31) / 32) * 4ull, s);
   DBuf ctr(64, s), status(nb * 8ull, s);
   uint32_t* ctr32 = ctr.as<uint32_t>();
   unsigned long long* total = reinterpret_cast<unsigned long long*>(ctr32 + 2);
@@ -723,8 +780,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
     scan_exclusive_u32(cnt.as<uint32_t>(), start.as<uint32_t>(), nb, nullptr, swork.p, s);
     hipLaunchKernelGGL(k_class_range, dim3(grid_for(nb)), dim3(256), 0, s, cnt.as<uint32_t>(),
                        start.as<uint32_t>(), nb, range.as<uint2>());
-    hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(mI)), dim3(256), 0, s, I->fp, idx_sorted, mI,
-                       kshift, keyI.as<uint64_t>());
+    hipLaunchKernelGGL(k_class_bitmap, dim3(grid_for((nb + 31) / 32)), dim3(256), 0, s,
+                       cnt.as<uint32_t>(), nb, nzI.as<uint32_t>());
+    hipLaunchKernelGGL(k_gather_records, dim3(grid_for(mI)), dim3(256), 0, s, I->fp, idx_sorted,
+                       mI, kshift, recI.as<IRec>());
     PAULI_HIP(hipGetLastError());
   }
 
@@ -733,9 +792,9 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   A.keyO = keyO.as<uint64_t>();
   A.clsO = clsO.as<uint32_t>();
   A.mO = mO;
-  A.keyI = keyI.as<uint64_t>();
-  A.idxI = idx_sorted;
+  A.recI = recI.as<IRec>();
   A.rangeI = range.as<uint2>();
+  A.nzI = nzI.as<uint32_t>();
   A.o_is_a = o_is_a ? 1 : 0;
   A.ma = static_cast<uint32_t>(a->m);
   A.sort_lo = sort_lo;
@@ -757,8 +816,18 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   PairSrc<WT, T> src{ra.as<uint64_t>(), ea.as<uint8_t>(), static_cast<const cplx<T>*>(a->coef),
                      a->fp, rb.as<uint64_t>(), eb.as<uint8_t>(),
                      static_cast<const cplx<T>*>(b->coef), b->fp, static_cast<uint32_t>(a->m), W};
+  // persistent grid: as many blocks as fit on the device at once
+  int dev = 0, ncu = 0, per_cu = 0;
+  PAULI_HIP(hipGetDevice(&dev));
+  PAULI_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  PAULI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bucket_merge<WT, T>, kNT, 0));
+  if (per_cu < 1) per_cu = 1;
+  uint32_t grid = static_cast<uint32_t>(ncu) * static_cast<uint32_t>(per_cu);
+  if (grid > nb) grid = nb;
+  DBuf scratch(static_cast<size_t>(grid) * kCapR * sizeof(RunEntry<T>), s);
+  A.scratch = scratch.p;
   StageScope sc(PAULI_STAGE_BUCKET, s, 0.0);
-  hipLaunchKernelGGL((k_bucket_merge<WT, T>), dim3(nb), dim3(kNT), 0, s, A, src);
+  hipLaunchKernelGGL((k_bucket_merge<WT, T>), dim3(grid), dim3(kNT), 0, s, A, src);
   PAULI_HIP(hipGetLastError());
   sc.stop();
   uint32_t host[4] = {0, 0, 0, 0};

@@ -59,6 +59,12 @@ struct PairSrc {
     split(id, i, j);
     return fa[i] ^ fb[j];
   }
+  // Word t of the product string (X words first, then Z words).
+  __device__ __forceinline__ uint64_t word(uint32_t id, int t) const {
+    uint32_t i, j;
+    split(id, i, j);
+    return ra[(size_t)i * 2 * nw + t] ^ rb[(size_t)j * 2 * nw + t];
+  }
 };
 
 // Term t of a stored sum.
