@@ -1,0 +1,1071 @@
+// Fused outer product + sort-and-combine: merge(H1*H2) without storing the
+// |H1|*|H2| unmerged products (Section IV-C's product followed by
+// Section III-H's sort and linear combine).
+//
+// The sort key of a product is its 64-bit fingerprint and
+// fp(a_i * b_j) = fp(a_i) ^ fp(b_j) (the fingerprint is GF(2)-linear and
+// the product XORs the symplectic bits, Section III-E).  The top d bits of
+// the key name the product's bucket.  Stages:
+//
+//  1 prep      per operand: row-major words, coefficient + phase + fp, key,
+//              and a stable sort of its terms by class (top d1 key bits).
+//  2 gen       records (key, pair id) written straight in top-d1-bit order:
+//              the products of class hA of a and class hB of b all have
+//              top bits hA ^ hB, so super-bucket s is the union of the
+//              class tiles (hA, hA ^ s), whose sizes and offsets follow from
+//              the class counts.  Every block writes one contiguous range.
+//  3 partition one stable radix pass per super-bucket on the next d2 bits.
+//  4 sort      per bucket, in LDS: stable radix sort on the 16 key bits below
+//              the bucket bits, runs tied on those bits finished by insertion
+//              sort on the full key; writes the sorted pair ids and each
+//              record's segment index (equal keys = one segment).  Buckets
+//              too large for LDS are sorted on all remaining key bits by
+//              one block in global memory.
+//  5 scan      segment counts -> output offsets.
+//  6 expand    per record: a group of G lanes loads the record's two operand
+//              rows with one 16-byte load per lane (one cache line per row),
+//              forms the product string and phase, and the segment's value
+//              i^k c_a c_b is summed in record order; each segment writes one
+//              merged term.  Equal keys are checked to be equal strings; a
+//              fingerprint collision raises a flag and the caller redoes the
+//              call with the general pipeline.  Segments longer than kLong
+//              records are summed by a whole block in a fixed tree.
+#include <cmath>
+#include <utility>
+
+#include "common.h"
+#include "internal.h"
+
+namespace pauli {
+
+namespace {
+
+constexpr int kB = 256;
+constexpr int kTile = 4096;  // records per partition tile
+constexpr int kItems = kTile / kB;
+constexpr int kSortNT = 1024;
+constexpr int kSortWaves = kSortNT / 64;
+constexpr int kCap = 8192;  // records of a bucket sorted in LDS
+constexpr int kSortRounds = kCap / kSortWaves / 64;
+constexpr int kMaxBits = 16;
+constexpr double kTargetBucket = 4096.0;
+constexpr int kLong = 32;  // segments longer than this are reduced by a block
+constexpr int kRun = 4;    // records per group per step of the expand kernel
+
+enum : uint32_t { kErrCollision = 1u };
+
+template <typename T>
+struct alignas(32) Aux {
+  T re, im;
+  uint64_t fp;
+  uint32_t e;  // (phase + |X & Z|) mod 4
+  uint32_t pad;
+};
+
+inline unsigned grid_for(int64_t n, int per = kB, int64_t cap = 65536) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g);
+}
+
+__device__ __forceinline__ uint32_t wave_incl(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan over a block of NW waves; every thread must call it.
+template <int NW>
+__device__ __forceinline__ uint32_t block_excl(uint32_t v, uint32_t* total, uint32_t* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl(v);
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t x = sh[w];
+    if (w < wave) base += x;
+    all += x;
+  }
+  __syncthreads();
+  if (total) *total = all;
+  return base + inc - v;
+}
+
+// ------------------------------------------------------------------ prep
+
+template <typename T>
+__global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
+                        const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
+                        const uint64_t* __restrict__ fp, int W, int Wp, int64_t ld, uint32_t m,
+                        int kshift, int cshift, int d1, uint64_t* __restrict__ rows,
+                        Aux<T>* __restrict__ aux, uint64_t* __restrict__ key,
+                        uint64_t* __restrict__ cls, uint32_t* __restrict__ idx) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+    int y = 0;
+    for (int w = 0; w < Wp; ++w) {
+      const uint64_t x = w < W ? X[w * ld + t] : 0ull;
+      const uint64_t z = w < W ? Z[w * ld + t] : 0ull;
+      rows[static_cast<size_t>(t) * 2 * Wp + w] = x;
+      rows[static_cast<size_t>(t) * 2 * Wp + Wp + w] = z;
+      y += popc64(x & z);
+    }
+    aux[t] = Aux<T>{c[t].re, c[t].im, fp[t], static_cast<uint32_t>((ph[t] + y) & 3), 0u};
+    const uint64_t k = fp[t] >> kshift;
+    key[t] = k;
+    cls[t] = d1 ? (k >> cshift) : 0ull;
+    idx[t] = t;
+  }
+}
+
+__global__ void k_class_count(const uint64_t* __restrict__ cls, uint32_t m,
+                              uint32_t* __restrict__ g) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
+    atomicAdd(&g[cls[t]], 1u);
+}
+
+__global__ void k_gather_keys(const uint64_t* __restrict__ key, const uint32_t* __restrict__ sidx,
+                              uint32_t m, uint64_t* __restrict__ skey) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
+    skey[t] = key[sidx[t]];
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+// Super-bucket s: T[s][hA] = offset of tile (hA, hA ^ s) inside s; S[s] = size.
+__global__ void __launch_bounds__(kB)
+k_tile_table(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gB, int d1,
+             uint32_t* __restrict__ Tt, uint32_t* __restrict__ S) {
+  __shared__ uint32_t sh[kB / 64];
+  const uint32_t nc = 1u << d1, s = blockIdx.x, h = threadIdx.x;
+  const uint32_t size = h < nc ? gA[h] * gB[h ^ s] : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_excl<kB / 64>(size, &tot, sh);
+  if (h < nc) Tt[s * nc + h] = ex;
+  if (h == 0) S[s] = tot;
+}
+
+// Records of the class tiles, written in super-bucket order.
+__global__ void __launch_bounds__(kB)
+k_gen(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gsA,
+      const uint32_t* __restrict__ sidxA, const uint64_t* __restrict__ skeyA,
+      const uint32_t* __restrict__ gB, const uint32_t* __restrict__ gsB,
+      const uint32_t* __restrict__ sidxB, const uint64_t* __restrict__ skeyB,
+      const uint32_t* __restrict__ Tt, const uint32_t* __restrict__ soff, int d1, uint32_t ma,
+      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const uint32_t nc = 1u << d1, ntile = nc * nc;
+  for (uint32_t tau = blockIdx.x; tau < ntile; tau += gridDim.x) {
+    const uint32_t s = tau >> d1, hA = tau & (nc - 1), hB = hA ^ s;
+    const uint32_t na = gA[hA], nb = gB[hB], n = na * nb;
+    if (n == 0) continue;
+    const uint32_t base = soff[s] + Tt[tau], a0 = gsA[hA], b0 = gsB[hB];
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+      const uint32_t ia = t / nb, jb = t - ia * nb;
+      const uint32_t i = sidxA[a0 + ia], j = sidxB[b0 + jb];
+      keys[base + t] = skeyA[a0 + ia] ^ skeyB[b0 + jb];
+      vals[base + t] = j * ma + i;
+    }
+  }
+}
+
+// ---------------------------------------------- partition of super-buckets
+
+__global__ void k_tiles_per_sb(const uint32_t* __restrict__ S, uint32_t nc,
+                               uint32_t* __restrict__ nt) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < nc; s += gridDim.x * blockDim.x)
+    nt[s] = (S[s] + kTile - 1) / kTile;
+}
+
+// tile tau -> (super-bucket s, tile index inside s); false past the last tile.
+__device__ __forceinline__ bool tile_of(uint32_t tau, const uint32_t* tb, uint32_t nc, uint32_t& s,
+                                        uint32_t& tl) {
+  if (tau >= tb[nc]) return false;
+  uint32_t lo = 0, hi = nc;  // largest s with tb[s] <= tau
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tb[mid] <= tau) lo = mid; else hi = mid;
+  }
+  s = lo;
+  tl = tau - tb[s];
+  return true;
+}
+
+// Count layout: super-bucket s owns C[tb[s]*256, tb[s+1]*256) as [digit][tile],
+// so one exclusive scan of C gives every (s, digit, tile) its output offset.
+__global__ void __launch_bounds__(kB)
+k_pcount(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ soff,
+         const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
+         uint32_t mask, uint32_t* __restrict__ C) {
+  __shared__ uint32_t hist[256];
+  uint32_t s, tl;
+  if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t lo = soff[s] + tl * kTile;
+  const uint32_t end = soff[s] + S[s];
+  const uint32_t hi = end - lo < kTile ? end : lo + kTile;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = lo + r * kB + threadIdx.x;
+    if (i < hi) atomicAdd(&hist[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  const uint32_t ns = tb[s + 1] - tb[s];
+  C[tb[s] * 256u + threadIdx.x * ns + tl] = hist[threadIdx.x];
+}
+
+// Stable scatter of one tile (wave-ballot ranks, LDS staging, coalesced
+// writes of each digit's run).
+__global__ void __launch_bounds__(kB)
+k_pscatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+           const uint32_t* __restrict__ soff, const uint32_t* __restrict__ S,
+           const uint32_t* __restrict__ tb, uint32_t nc, int shift, uint32_t mask,
+           const uint32_t* __restrict__ C) {
+  __shared__ uint64_t s_k[kTile];
+  __shared__ uint32_t s_v[kTile];
+  __shared__ uint32_t s_hist[256], s_start[256], s_run[256], s_goff[256];
+  __shared__ uint32_t s_wc[kB / 64][256];
+  __shared__ uint32_t sh[kB / 64];
+  uint32_t s, tl;
+  if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t lo = soff[s] + tl * kTile;
+  const uint32_t end = soff[s] + S[s];
+  const uint32_t hi = end - lo < kTile ? end : lo + kTile;
+  const uint32_t ns = tb[s + 1] - tb[s];
+  s_hist[tid] = 0;
+  s_run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kB / 64; ++w) s_wc[w][tid] = 0;
+  s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
+  __syncthreads();
+  uint64_t k[kItems];
+  uint32_t v[kItems];
+  int d[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = lo + r * kB + tid;
+    if (i < hi) {
+      k[r] = kin[i];
+      v[r] = vin[i];
+      d[r] = static_cast<int>((k[r] >> shift) & mask);
+      atomicAdd(&s_hist[d[r]], 1u);
+    } else {
+      k[r] = 0;
+      v[r] = 0;
+      d[r] = -1;
+    }
+  }
+  __syncthreads();
+  s_start[tid] = block_excl<kB / 64>(s_hist[tid], nullptr, sh);
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < kItems; ++r) {
+    const bool valid = d[r] >= 0;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool on = valid && ((d[r] >> b) & 1);
+      const uint64_t bm = __ballot(on);
+      peers &= on ? bm : ~bm;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) s_wc[wave][d[r]] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t off = s_start[d[r]] + s_run[d[r]];
+      for (int w = 0; w < wave; ++w) off += s_wc[w][d[r]];
+      off += rank;
+      s_k[off] = k[r];
+      s_v[off] = v[r];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kB / 64; ++w) {
+      add += s_wc[w][tid];
+      s_wc[w][tid] = 0;
+    }
+    s_run[tid] += add;
+    __syncthreads();
+  }
+  const uint32_t cnt = hi - lo;
+  for (uint32_t e = tid; e < cnt; e += kB) {
+    const uint64_t kk = s_k[e];
+    const uint32_t dd = static_cast<uint32_t>((kk >> shift) & mask);
+    const uint32_t g = s_goff[dd] + (e - s_start[dd]);
+    kout[g] = kk;
+    vout[g] = s_v[e];
+  }
+}
+
+// Bucket bk = (s, digit): first record.
+__global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32_t* __restrict__ tb,
+                                 const uint32_t* __restrict__ C, int d2, uint32_t nbk, uint32_t P,
+                                 uint32_t* __restrict__ boff) {
+  const uint32_t mask = (1u << d2) - 1u;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= nbk; b += gridDim.x * blockDim.x) {
+    if (b == nbk) {
+      boff[b] = P;
+      continue;
+    }
+    const uint32_t s = b >> d2, dd = b & mask;
+    const uint32_t ns = tb[s + 1] - tb[s];
+    boff[b] = ns ? C[tb[s] * 256u + dd * ns] : soff[s];
+  }
+}
+
+// ------------------------------------------------------------ bucket sort
+
+struct SortSmem {
+  uint64_t key[kCap];
+  uint32_t id[kCap];
+  uint16_t ord[kCap];
+  uint32_t cnt[kSortWaves][256];
+  uint32_t scan[kSortWaves];
+  uint32_t wcount[kSortWaves];
+};
+
+__device__ __forceinline__ uint32_t sort_span(uint32_t N) {
+  return ((N + 64 * kSortWaves - 1) / (64 * kSortWaves)) * 64;
+}
+
+// ord[0..N) = entries ordered stably by key bits [lo, lo + 8*passes).  Wave w
+// owns positions [w*span, (w+1)*span) in rounds of 64; the rank of an entry
+// among equal digits counts equal digits at earlier positions (eight ballots
+// per round and per-wave digit counters).
+__device__ void lds_sort(uint32_t N, int lo, int passes, SortSmem& S) {
+  for (uint32_t q = threadIdx.x; q < N; q += kSortNT) S.ord[q] = static_cast<uint16_t>(q);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t span = sort_span(N);
+  const int rounds = static_cast<int>(span / 64);
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = lo + 8 * pass;
+    for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortNT) (&S.cnt[0][0])[i] = 0;
+    __syncthreads();
+    uint16_t ent[kSortRounds], rk[kSortRounds];
+    uint8_t dg[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      const bool valid = q < N;
+      ent[r] = valid ? S.ord[q] : 0;
+      const int dgt = valid ? static_cast<int>((S.key[ent[r]] >> shift) & 255) : 0;
+      dg[r] = static_cast<uint8_t>(dgt);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool on = valid && ((dgt >> bit) & 1);
+        const uint64_t bm = __ballot(on);
+        peers &= on ? bm : ~bm;
+      }
+      const uint32_t before = static_cast<uint32_t>(__popcll(peers & lt));
+      uint32_t c0 = 0;
+      if (valid) c0 = S.cnt[wave][dgt];
+      rk[r] = static_cast<uint16_t>(c0 + before);
+      if (valid && before == 0) S.cnt[wave][dgt] = c0 + static_cast<uint32_t>(__popcll(peers));
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    if (threadIdx.x < 256)
+      for (int w = 0; w < kSortWaves; ++w) tot += S.cnt[w][threadIdx.x];
+    const uint32_t dstart = block_excl<kSortWaves>(threadIdx.x < 256 ? tot : 0u, nullptr, S.scan);
+    if (threadIdx.x < 256) {
+      uint32_t run = dstart;
+      for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t c = S.cnt[w][threadIdx.x];
+        S.cnt[w][threadIdx.x] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    uint32_t np[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      np[r] = q < N ? S.cnt[wave][dg[r]] + rk[r] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      if (q < N) S.ord[np[r]] = ent[r];
+    }
+    __syncthreads();
+  }
+}
+
+// Runs of positions tied on the radix field but holding different full keys
+// are put in (key, entry) order by the thread owning the run's first position.
+__device__ void lds_fix_runs(uint32_t N, int lo, uint64_t fmask, SortSmem& S) {
+  bool dirty = false;
+  for (uint32_t q = threadIdx.x + 1; q < N; q += kSortNT) {
+    const uint64_t k1 = S.key[S.ord[q - 1]], k2 = S.key[S.ord[q]];
+    if (k1 != k2 && ((k1 >> lo) & fmask) == ((k2 >> lo) & fmask)) dirty = true;
+  }
+  if (!__syncthreads_or(dirty)) return;
+  for (uint32_t q = threadIdx.x; q < N; q += kSortNT) {
+    const uint64_t f = (S.key[S.ord[q]] >> lo) & fmask;
+    if (q > 0 && ((S.key[S.ord[q - 1]] >> lo) & fmask) == f) continue;
+    uint32_t e = q + 1;
+    while (e < N && ((S.key[S.ord[e]] >> lo) & fmask) == f) ++e;
+    for (uint32_t x = q + 1; x < e; ++x) {
+      const uint16_t v = S.ord[x];
+      const uint64_t kv = S.key[v];
+      int y = static_cast<int>(x) - 1;
+      while (y >= static_cast<int>(q)) {
+        const uint16_t u = S.ord[y];
+        const uint64_t ku = S.key[u];
+        if (ku < kv || (ku == kv && u < v)) break;
+        S.ord[y + 1] = u;
+        --y;
+      }
+      S.ord[y + 1] = v;
+    }
+  }
+  __syncthreads();
+}
+
+struct SegOut {
+  uint32_t* vals;    // sorted pair ids, written over the bucket's records
+  uint32_t* segidx;  // [record] segment index inside the bucket
+  uint32_t* nseg;    // [bucket] segment count
+  uint32_t* long_list;  // (bucket, first record) of segments longer than kLong
+  uint32_t* nlong;
+};
+
+// Buckets that fit in LDS.  A larger bucket is queued for k_heavy_sort.
+__global__ void __launch_bounds__(kSortNT)
+k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
+              uint32_t nbk, int sort_lo, int passes, uint64_t fmask, SegOut out,
+              uint32_t* __restrict__ heavy, uint32_t* __restrict__ nheavy) {
+  __shared__ SortSmem S;
+  const uint32_t b = blockIdx.x;
+  if (b >= nbk) return;
+  const uint32_t lo = boff[b], n = boff[b + 1] - lo;
+  if (n > static_cast<uint32_t>(kCap)) {
+    if (threadIdx.x == 0) heavy[atomicAdd(nheavy, 1u)] = b;
+    return;
+  }
+  for (uint32_t q = threadIdx.x; q < n; q += kSortNT) {
+    S.key[q] = keys[lo + q];
+    S.id[q] = out.vals[lo + q];
+  }
+  __syncthreads();
+  lds_sort(n, sort_lo, passes, S);
+  lds_fix_runs(n, sort_lo, fmask, S);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t span = sort_span(n);
+  uint32_t hc = 0;
+  for (uint32_t r = 0; r * 64 < span; ++r) {
+    const uint32_t q = wave * span + r * 64 + lane;
+    bool head = false;
+    if (q < n) head = q == 0 || S.key[S.ord[q - 1]] != S.key[S.ord[q]];
+    hc += static_cast<uint32_t>(__popcll(__ballot(head)));
+  }
+  if (lane == 0) S.wcount[wave] = hc;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+  for (int w = 0; w < kSortWaves; ++w) {
+    if (w < wave) run += S.wcount[w];
+    total += S.wcount[w];
+  }
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (uint32_t r = 0; r * 64 < span; ++r) {
+    const uint32_t q = wave * span + r * 64 + lane;
+    bool head = false;
+    uint32_t e = 0;
+    if (q < n) {
+      e = S.ord[q];
+      head = q == 0 || S.key[S.ord[q - 1]] != S.key[e];
+    }
+    const uint64_t hb = __ballot(head);
+    if (q < n) {
+      const uint32_t seg = run + static_cast<uint32_t>(__popcll(hb & (lt | (1ull << lane)))) - 1;
+      out.vals[lo + q] = S.id[e];
+      out.segidx[lo + q] = seg;
+    }
+    run += static_cast<uint32_t>(__popcll(hb));
+  }
+  if (threadIdx.x == 0) out.nseg[b] = total;
+  // segments longer than kLong: queued for the block-wide reduction
+  for (uint32_t r = 0; r * 64 < span; ++r) {
+    const uint32_t q = wave * span + r * 64 + lane;
+    if (q < n && (q == 0 || S.key[S.ord[q - 1]] != S.key[S.ord[q]])) {
+      const uint64_t k = S.key[S.ord[q]];
+      const uint32_t lim = q + kLong + 1 < n ? q + kLong + 1 : n;
+      uint32_t e = q + 1;
+      while (e < lim && S.key[S.ord[e]] == k) ++e;
+      if (e - q > static_cast<uint32_t>(kLong)) {
+        const uint32_t slot = atomicAdd(out.nlong, 1u);
+        out.long_list[2 * slot] = b;
+        out.long_list[2 * slot + 1] = q;
+      }
+    }
+  }
+}
+
+// Buckets larger than kCap: one block sorts the bucket's records on all key
+// bits below the bucket bits (LSD, 8-bit digits, global memory, stable) and
+// then marks the segments.
+__global__ void __launch_bounds__(kSortNT)
+k_heavy_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ tkeys,
+             uint32_t* __restrict__ tvals, const uint32_t* __restrict__ boff, int rbits,
+             const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ nheavy, SegOut out) {
+  __shared__ uint32_t s_hist[256], s_start[256], s_run[256];
+  __shared__ uint32_t s_wc[kSortWaves][256];
+  __shared__ uint32_t sh[kSortWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t H = *nheavy;
+  for (uint32_t hix = blockIdx.x; hix < H; hix += gridDim.x) {
+    const uint32_t b = heavy[hix];
+    const uint32_t lo = boff[b], n = boff[b + 1] - lo;
+    uint64_t* ka = keys + lo;
+    uint32_t* va = out.vals + lo;
+    uint64_t* kb = tkeys + lo;
+    uint32_t* vb = tvals + lo;
+    const int passes = (rbits + 7) / 8;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int shift = 8 * pass;
+      if (tid < 256) {
+        s_hist[tid] = 0;
+        s_run[tid] = 0;
+      }
+      for (int i = tid; i < kSortWaves * 256; i += kSortNT) (&s_wc[0][0])[i] = 0;
+      __syncthreads();
+      for (uint32_t q = tid; q < n; q += kSortNT) atomicAdd(&s_hist[(ka[q] >> shift) & 255], 1u);
+      __syncthreads();
+      const uint32_t st = block_excl<kSortWaves>(tid < 256 ? s_hist[tid] : 0u, nullptr, sh);
+      if (tid < 256) s_start[tid] = st;
+      __syncthreads();
+      for (uint32_t base = 0; base < n; base += kSortNT) {
+        const uint32_t q = base + tid;
+        const bool valid = q < n;
+        uint64_t k = 0;
+        uint32_t v = 0;
+        int d = 0;
+        if (valid) {
+          k = ka[q];
+          v = va[q];
+          d = static_cast<int>((k >> shift) & 255);
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+          const bool on = valid && ((d >> bit) & 1);
+          const uint64_t bm = __ballot(on);
+          peers &= on ? bm : ~bm;
+        }
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) s_wc[wave][d] = static_cast<uint32_t>(__popcll(peers));
+        __syncthreads();
+        if (valid) {
+          uint32_t off = s_start[d] + s_run[d];
+          for (int w = 0; w < wave; ++w) off += s_wc[w][d];
+          kb[off + rank] = k;
+          vb[off + rank] = v;
+        }
+        __syncthreads();
+        if (tid < 256) {
+          uint32_t add = 0;
+          for (int w = 0; w < kSortWaves; ++w) {
+            add += s_wc[w][tid];
+            s_wc[w][tid] = 0;
+          }
+          s_run[tid] += add;
+        }
+        __syncthreads();
+      }
+      uint64_t* tk = ka; ka = kb; kb = tk;
+      uint32_t* tv = va; va = vb; vb = tv;
+    }
+    if (passes & 1) {  // the sorted records are in the scratch arrays: copy back
+      for (uint32_t q = tid; q < n; q += kSortNT) {
+        keys[lo + q] = ka[q];
+        out.vals[lo + q] = va[q];
+      }
+      __syncthreads();
+    }
+    const uint64_t* K = keys + lo;
+    uint32_t run = 0;
+    for (uint32_t base = 0; base < n; base += kSortNT) {
+      const uint32_t q = base + tid;
+      const bool head = q < n && (q == 0 || K[q - 1] != K[q]);
+      const uint64_t hb = __ballot(head);
+      if (lane == 0) sh[wave] = static_cast<uint32_t>(__popcll(hb));
+      __syncthreads();
+      uint32_t wb = run, tot = 0;
+      for (int w = 0; w < kSortWaves; ++w) {
+        if (w < wave) wb += sh[w];
+        tot += sh[w];
+      }
+      if (q < n) {
+        out.segidx[lo + q] = wb + static_cast<uint32_t>(__popcll(hb & (lt | (1ull << lane)))) - 1;
+        if (head) {
+          uint32_t e = q + 1;
+          while (e < n && e <= q + kLong && K[e] == K[q]) ++e;
+          if (e - q > static_cast<uint32_t>(kLong)) {
+            const uint32_t slot = atomicAdd(out.nlong, 1u);
+            out.long_list[2 * slot] = b;
+            out.long_list[2 * slot + 1] = q;
+          }
+        }
+      }
+      run += tot;
+      __syncthreads();
+    }
+    if (tid == 0) out.nseg[b] = run;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- expand
+
+template <int WT, typename T>
+struct Operands {
+  const uint64_t* ra;  // [|a|][2*Wp]
+  const uint64_t* rb;
+  const Aux<T>* xa;
+  const Aux<T>* xb;
+  uint32_t ma;
+  int nw;  // W
+};
+
+// G lanes hold one record: lane l < G/2 the X words 2l, 2l+1 of the product
+// string, lane l >= G/2 the Z words; with G == 1 one lane holds X0 and Z0.
+template <int G, typename T>
+struct Rec {
+  uint64_t w0, w1;  // this lane's two product words
+  T re, im;         // value i^k c_a c_b (same in every lane of the group)
+  uint64_t fp;
+};
+
+template <int G, int WT, typename T>
+__device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_t id, int gl) {
+  const uint32_t j = id / op.ma, i = id - j * op.ma;
+  // a row is G 16-byte pieces (Wp = G words per half)
+  const ulonglong2 a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
+  const ulonglong2 b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
+  const Aux<T> xa = op.xa[i], xb = op.xb[j];
+  Rec<G, T> r;
+  r.w0 = a.x ^ b.x;
+  r.w1 = a.y ^ b.y;
+  int part;
+  if (G == 1) {
+    // a.x = X_a, a.y = Z_a; b.x = X_b, b.y = Z_b
+    part = 2 * popc64(a.y & b.x) - popc64(r.w0 & r.w1);
+  } else {
+    constexpr int half = G / 2;
+    const int lane = threadIdx.x & 63;
+    // Z words of the same indices live half lanes up
+    const uint64_t za0 = __shfl(a.x, lane + half, 64), za1 = __shfl(a.y, lane + half, 64);
+    const uint64_t z30 = __shfl(r.w0, lane + half, 64), z31 = __shfl(r.w1, lane + half, 64);
+    part = 0;
+    if (gl < half)
+      part = 2 * (popc64(za0 & b.x) + popc64(za1 & b.y)) - popc64(r.w0 & z30) - popc64(r.w1 & z31);
+#pragma unroll
+    for (int off = half / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    part = __shfl(part, lane - gl, 64);
+  }
+  const int k = static_cast<int>(xa.e + xb.e) + part;
+  const cplx<T> v = rot_ik(k, cmul(cplx<T>{xa.re, xa.im}, cplx<T>{xb.re, xb.im}));
+  r.re = v.re;
+  r.im = v.im;
+  r.fp = xa.fp ^ xb.fp;
+  return r;
+}
+
+struct ExpandArgs {
+  const uint32_t* boff;
+  const uint32_t* vals;
+  const uint32_t* segidx;
+  const uint32_t* segoff;  // [bucket] first output index
+  uint32_t nbk;
+  uint32_t* err;
+  uint64_t* OX;
+  uint64_t* OZ;
+  uint8_t* Oph;
+  void* Oc;
+  uint64_t* Ofp;
+  int64_t ldo;
+};
+
+template <int G, typename T>
+__device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, int64_t o,
+                                          const Rec<G, T>& r, T re, T im) {
+  if (G == 1) {
+    E.OX[o] = r.w0;
+    E.OZ[o] = r.w1;
+  } else {
+    constexpr int half = G / 2;
+    const int base = 2 * (gl < half ? gl : gl - half);
+    uint64_t* D = gl < half ? E.OX : E.OZ;
+    if (base < nw) D[static_cast<int64_t>(base) * E.ldo + o] = r.w0;
+    if (base + 1 < nw) D[static_cast<int64_t>(base + 1) * E.ldo + o] = r.w1;
+  }
+  if (gl == 0) {
+    E.Oph[o] = 0;
+    static_cast<cplx<T>*>(E.Oc)[o] = cplx<T>{re, im};
+    E.Ofp[o] = r.fp;
+  }
+}
+
+// One block per bucket (grid-stride).  Group g takes runs of kRun records;
+// it handles every segment whose first record lies in its run (continuing
+// past the run's end when the segment does), except segments longer than
+// kLong, which k_expand_long sums.
+template <int G, int WT, typename T>
+__global__ void __launch_bounds__(kB)
+k_expand(ExpandArgs E, Operands<WT, T> op) {
+  constexpr int NG = kB / G;
+  const int g = threadIdx.x / G, gl = threadIdx.x % G;
+  for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
+    const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
+    const uint32_t obase = E.segoff[b];
+    for (uint32_t p0 = static_cast<uint32_t>(g) * kRun; p0 < n; p0 += NG * kRun) {
+      // segment index of the record before the run, and of each record
+      uint32_t sprev = p0 ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
+      uint32_t sid[kRun + 1];
+      uint32_t ids[kRun];
+#pragma unroll
+      for (int t = 0; t <= kRun; ++t) sid[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
+#pragma unroll
+      for (int t = 0; t < kRun; ++t) ids[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
+      Rec<G, T> rec[kRun];
+#pragma unroll
+      for (int t = 0; t < kRun; ++t)
+        if (p0 + t < n) rec[t] = load_rec<G, WT, T>(op, ids[t], gl);
+      // walk the run: segments whose first record lies inside it
+      T acc_re = 0, acc_im = 0;
+      uint64_t h0 = 0, h1 = 0;
+      bool open = false;
+      int t_head = 0;
+      Rec<G, T> first;
+      uint64_t diff = 0;
+#pragma unroll
+      for (int t = 0; t < kRun; ++t) {
+        if (p0 + t >= n) break;
+        const bool head = sid[t] != (t ? sid[t - 1] : sprev);
+        if (head) {
+          open = true;
+          t_head = t;
+          acc_re = rec[t].re;
+          acc_im = rec[t].im;
+          first = rec[t];
+          h0 = rec[t].w0;
+          h1 = rec[t].w1;
+        } else if (open) {
+          acc_re = acc_re + rec[t].re;
+          acc_im = acc_im + rec[t].im;
+          diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
+        }
+        const bool ends = p0 + t + 1 >= n || (t + 1 < kRun && sid[t + 1] != sid[t]);
+        if (open && ends) {
+          write_out<G, T>(E, op.nw, gl, static_cast<int64_t>(obase) + sid[t], first, acc_re, acc_im);
+          open = false;
+        }
+      }
+      if (open) {
+        // the run's last segment continues past the run: follow it, unless
+        // it is longer than kLong (then k_expand_long sums it)
+        const uint32_t s_cur = sid[kRun - 1];
+        uint32_t len = static_cast<uint32_t>(kRun - t_head);
+        uint32_t q = p0 + kRun;
+        bool is_long = false;
+        while (q < n && E.segidx[lo + q] == s_cur) {
+          if (++len > static_cast<uint32_t>(kLong)) {
+            is_long = true;
+            break;
+          }
+          const Rec<G, T> r = load_rec<G, WT, T>(op, E.vals[lo + q], gl);
+          acc_re = acc_re + r.re;
+          acc_im = acc_im + r.im;
+          diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
+          ++q;
+        }
+        if (!is_long)
+          write_out<G, T>(E, op.nw, gl, static_cast<int64_t>(obase) + s_cur, first, acc_re,
+                          acc_im);
+      }
+      // an equal key must be an equal string
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
+      if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
+    }
+  }
+}
+
+// Segments longer than kLong: one block per segment; group g adds records
+// g, g + NG, ... in order, then the NG partial sums are added in group order.
+template <int G, int WT, typename T>
+__global__ void __launch_bounds__(kB)
+k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ long_list,
+              const uint32_t* __restrict__ nlong) {
+  constexpr int NG = kB / G;
+  __shared__ T s_re[NG], s_im[NG];
+  __shared__ uint32_t s_end;
+  const int g = threadIdx.x / G, gl = threadIdx.x % G;
+  const uint32_t L = *nlong;
+  for (uint32_t x = blockIdx.x; x < L; x += gridDim.x) {
+    const uint32_t b = long_list[2 * x], q0 = long_list[2 * x + 1];
+    const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
+    const uint32_t s0 = E.segidx[lo + q0];
+    if (threadIdx.x == 0) {  // segment indices grow along the bucket: binary search
+      uint32_t l = q0, h = n;    // first position past the segment is in (l, h]
+      while (h - l > 1) {
+        const uint32_t mid = l + (h - l) / 2;
+        if (E.segidx[lo + mid] == s0) l = mid; else h = mid;
+      }
+      s_end = h;
+    }
+    __syncthreads();
+    const uint32_t q1 = s_end;
+    const Rec<G, T> first = load_rec<G, WT, T>(op, E.vals[lo + q0], gl);
+    T re = 0, im = 0;
+    uint64_t diff = 0;
+    for (uint32_t q = q0 + g; q < q1; q += NG) {
+      const Rec<G, T> r = load_rec<G, WT, T>(op, E.vals[lo + q], gl);
+      re = re + r.re;
+      im = im + r.im;
+      diff |= (r.w0 ^ first.w0) | (r.w1 ^ first.w1);
+    }
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
+    if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
+    if (gl == 0) {
+      s_re[g] = re;
+      s_im[g] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x < G) {
+      T tr = 0, ti = 0;
+      for (int h = 0; h < NG; ++h) {
+        tr = tr + s_re[h];
+        ti = ti + s_im[h];
+      }
+      write_out<G, T>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, tr, ti);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------- host
+
+template <typename T>
+struct SidePrep {
+  DBuf rows, aux, key, cls, cls2, idx, idx2, skey, g, gs;
+  uint32_t* sidx = nullptr;
+};
+
+template <typename T>
+void prep_side(const paulisum* t, int Wp, int kb, int d1, SidePrep<T>& P, hipStream_t s) {
+  const uint32_t m = static_cast<uint32_t>(t->m);
+  const uint32_t nc = 1u << d1;
+  P.rows = DBuf(static_cast<size_t>(m) * 2 * Wp * 8, s);
+  P.aux = DBuf(static_cast<size_t>(m) * sizeof(Aux<T>), s);
+  P.key = DBuf(m * 8ull, s);
+  P.cls = DBuf(m * 8ull, s);
+  P.cls2 = DBuf(m * 8ull, s);
+  P.idx = DBuf(m * 4ull, s);
+  P.idx2 = DBuf(m * 4ull, s);
+  P.skey = DBuf(m * 8ull, s);
+  P.g = DBuf(nc * 4ull, s);
+  P.gs = DBuf(nc * 4ull + 4, s);
+  hipLaunchKernelGGL(k_fprep<T>, dim3(grid_for(m)), dim3(kB), 0, s, t->X, t->Z, t->ph,
+                     static_cast<const cplx<T>*>(t->coef), t->fp, t->W, Wp, t->ld, m, 64 - kb,
+                     kb - d1, d1, P.rows.template as<uint64_t>(), P.aux.template as<Aux<T>>(),
+                     P.key.template as<uint64_t>(), P.cls.template as<uint64_t>(),
+                     P.idx.template as<uint32_t>());
+  PAULI_HIP(hipGetLastError());
+  P.sidx = P.idx.template as<uint32_t>();
+  uint64_t* scls = P.cls.template as<uint64_t>();
+  if (d1 > 0) {
+    DBuf w(radix_workspace_bytes(m), s);
+    if (radix_sort_pairs(P.cls.template as<uint64_t>(), P.idx.template as<uint32_t>(),
+                         P.cls2.template as<uint64_t>(), P.idx2.template as<uint32_t>(), m, d1,
+                         w.p, s)) {
+      P.sidx = P.idx2.template as<uint32_t>();
+      scls = P.cls2.template as<uint64_t>();
+    }
+  }
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nc)), dim3(kB), 0, s, P.g.template as<uint32_t>(),
+                     nc, 0u);
+  hipLaunchKernelGGL(k_class_count, dim3(grid_for(m)), dim3(kB), 0, s, scls, m,
+                     P.g.template as<uint32_t>());
+  DBuf w2(scan_workspace_bytes(nc), s);
+  scan_exclusive_u32(P.g.template as<uint32_t>(), P.gs.template as<uint32_t>(), nc,
+                     P.gs.template as<uint32_t>() + nc, w2.p, s);
+  hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(m)), dim3(kB), 0, s,
+                     P.key.template as<uint64_t>(), P.sidx, m, P.skey.template as<uint64_t>());
+  PAULI_HIP(hipGetLastError());
+}
+
+template <int G, int WT, typename T>
+paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  const int W = a->W;
+  const int Wp = G;  // G == 1 iff W == 1; otherwise the next power of two >= W
+  const uint32_t P = static_cast<uint32_t>(a->m * b->m);
+  const int kb = o.key_bits;
+  int d = 0;
+  if (P > kTargetBucket) d = static_cast<int>(std::ceil(std::log2(P / kTargetBucket)));
+  if (d > kMaxBits) d = kMaxBits;
+  if (d > kb) d = kb;
+  const int d1 = d < 8 ? d : 8;
+  const int d2 = d - d1;
+  const uint32_t nc = 1u << d1;
+  const uint32_t nbk = 1u << d;
+  const int rem = kb - d;  // key bits below the bucket bits
+  int sort_lo, passes;
+  uint64_t fmask;
+  if (rem >= 16) {
+    sort_lo = rem - 16;
+    passes = 2;
+    fmask = 0xFFFFull;
+  } else {
+    sort_lo = 0;
+    passes = (rem + 7) / 8;
+    fmask = rem ? ((1ull << rem) - 1) : 0ull;
+  }
+
+  SidePrep<T> A, B;
+  const bool same = a == b;
+  {
+    StageScope sc(PAULI_STAGE_PREP, s, (a->m + (same ? 0 : b->m)) * (16.0 * W + 32.0 * 2));
+    prep_side<T>(a, Wp, kb, d1, A, s);
+    if (!same) prep_side<T>(b, Wp, kb, d1, B, s);
+  }
+  const SidePrep<T>& Bs = same ? A : B;
+
+  DBuf keys(P * 8ull, s), vals(P * 4ull, s), keys2(P * 8ull, s), vals2(P * 4ull, s);
+  DBuf Tt(static_cast<size_t>(nc) * nc * 4, s), S(nc * 4ull, s), soff(nc * 4ull + 4, s);
+  DBuf boff((nbk + 1) * 4ull, s), ctr(64, s);
+  uint32_t* ctr32 = ctr.as<uint32_t>();  // [0] heavy count [1] long count [2] err [3] total
+  uint64_t* K = keys.as<uint64_t>();
+  uint32_t* V = vals.as<uint32_t>();
+  uint64_t* K2 = keys2.as<uint64_t>();
+  uint32_t* V2 = vals2.as<uint32_t>();
+  {
+    StageScope sc(PAULI_STAGE_SORT, s, P * (12.0 + (d2 ? 32.0 : 0.0)));
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr32, 16u, 0u);
+    hipLaunchKernelGGL(k_tile_table, dim3(nc), dim3(kB), 0, s, A.g.template as<uint32_t>(),
+                       Bs.g.template as<uint32_t>(), d1, Tt.as<uint32_t>(), S.as<uint32_t>());
+    DBuf w(scan_workspace_bytes(nc), s);
+    scan_exclusive_u32(S.as<uint32_t>(), soff.as<uint32_t>(), nc, soff.as<uint32_t>() + nc, w.p,
+                       s);
+    hipLaunchKernelGGL(k_gen, dim3(grid_for(static_cast<int64_t>(nc) * nc, 1, 16384)), dim3(kB), 0,
+                       s, A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
+                       A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
+                       Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
+                       Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, static_cast<uint32_t>(a->m), K,
+                       V);
+    PAULI_HIP(hipGetLastError());
+    if (d2 > 0) {
+      DBuf nt(nc * 4ull, s), tb(nc * 4ull + 4, s);
+      hipLaunchKernelGGL(k_tiles_per_sb, dim3(grid_for(nc)), dim3(kB), 0, s, S.as<uint32_t>(), nc,
+                         nt.as<uint32_t>());
+      scan_exclusive_u32(nt.as<uint32_t>(), tb.as<uint32_t>(), nc, tb.as<uint32_t>() + nc, w.p,
+                         s);
+      const uint32_t gb = P / kTile + nc + 1;  // bound on the number of tiles
+      DBuf C(static_cast<size_t>(gb) * 256 * 4, s);
+      const int shift = kb - d;
+      const uint32_t mask = (1u << d2) - 1u;
+      hipLaunchKernelGGL(k_pcount, dim3(gb), dim3(kB), 0, s, K, soff.as<uint32_t>(),
+                         S.as<uint32_t>(), tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
+      DBuf w3(scan_workspace_bytes(static_cast<int64_t>(gb) * 256), s);
+      scan_exclusive_u32(C.as<uint32_t>(), C.as<uint32_t>(), static_cast<int64_t>(gb) * 256,
+                         nullptr, w3.p, s);
+      hipLaunchKernelGGL(k_pscatter, dim3(gb), dim3(kB), 0, s, K, V, K2, V2, soff.as<uint32_t>(),
+                         S.as<uint32_t>(), tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
+      hipLaunchKernelGGL(k_bucket_offsets, dim3(grid_for(nbk + 1)), dim3(kB), 0, s,
+                         soff.as<uint32_t>(), tb.as<uint32_t>(), C.as<uint32_t>(), d2, nbk, P,
+                         boff.as<uint32_t>());
+      PAULI_HIP(hipGetLastError());
+      std::swap(K, K2);
+      std::swap(V, V2);
+    } else {
+      PAULI_HIP(hipMemcpyAsync(boff.p, soff.p, (nbk + 1) * 4ull, hipMemcpyDeviceToDevice, s));
+    }
+  }
+
+  DBuf segidx(P * 4ull, s), nseg(nbk * 4ull + 4, s), segoff(nbk * 4ull + 4, s);
+  DBuf heavy(nbk * 4ull, s), long_list(static_cast<size_t>(P / kLong + 2) * 8, s);
+  SegOut so{V, segidx.as<uint32_t>(), nseg.as<uint32_t>(), long_list.as<uint32_t>(), ctr32 + 1};
+  {
+    StageScope sc(PAULI_STAGE_SEGMENT, s, P * 20.0);
+    hipLaunchKernelGGL(k_bucket_sort, dim3(nbk), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(), nbk,
+                       sort_lo, passes, fmask, so, heavy.as<uint32_t>(), ctr32);
+    hipLaunchKernelGGL(k_heavy_sort, dim3(64), dim3(kSortNT), 0, s, K, K2, V2, boff.as<uint32_t>(),
+                       rem, heavy.as<uint32_t>(), ctr32, so);
+    PAULI_HIP(hipGetLastError());
+    DBuf w(scan_workspace_bytes(nbk), s);
+    scan_exclusive_u32(nseg.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
+                       segoff.as<uint32_t>() + nbk, w.p, s);
+    PAULI_HIP(hipMemcpyAsync(ctr32 + 3, segoff.as<uint32_t>() + nbk, 4, hipMemcpyDeviceToDevice, s));
+  }
+  uint32_t host[4];
+  PAULI_HIP(hipMemcpyAsync(host, ctr32, sizeof(host), hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipStreamSynchronize(s));
+  const uint32_t U = host[3];
+
+  paulisum* out = new_sum(a->n, U, U, a->dtype, s);
+  ExpandArgs E{boff.as<uint32_t>(), V, segidx.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
+               ctr32 + 2, out->X, out->Z, out->ph, out->coef, out->fp, out->ld};
+  Operands<WT, T> op{A.rows.template as<uint64_t>(), Bs.rows.template as<uint64_t>(),
+                     A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
+                     static_cast<uint32_t>(a->m), W};
+  {
+    StageScope sc(PAULI_STAGE_WRITE, s,
+                  U * (16.0 * W + sizeof(cplx<T>) + 1 + 8) + P * 8.0);
+    hipLaunchKernelGGL((k_expand<G, WT, T>), dim3(grid_for(nbk, 1, 4096)), dim3(kB), 0, s, E, op);
+    hipLaunchKernelGGL((k_expand_long<G, WT, T>), dim3(256), dim3(kB), 0, s, E, op,
+                       long_list.as<uint32_t>(), ctr32 + 1);
+    PAULI_HIP(hipGetLastError());
+  }
+  PAULI_HIP(hipMemcpyAsync(host, ctr32, sizeof(host), hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipStreamSynchronize(s));
+  if (host[2] != 0) {
+    free_sum(out);
+    return nullptr;  // a fingerprint collision: the caller uses the general path
+  }
+  return out;
+}
+
+template <typename T>
+paulisum* fused_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  switch (a->W) {
+    case 1: return fused_t<1, 1, T>(a, b, o, s);
+    case 2: return fused_t<2, 2, T>(a, b, o, s);
+    case 3: return fused_t<4, 3, T>(a, b, o, s);
+    case 4: return fused_t<4, 4, T>(a, b, o, s);
+    case 5: return fused_t<8, 5, T>(a, b, o, s);
+    case 6: return fused_t<8, 6, T>(a, b, o, s);
+    case 7: return fused_t<8, 7, T>(a, b, o, s);
+    case 8: return fused_t<8, 8, T>(a, b, o, s);
+    default: return fused_t<16, kMaxWords, T>(a, b, o, s);
+  }
+}
+
+}  // namespace
+
+paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  if (o.drop_abs >= 0.0) return nullptr;  // drop thresholds use the general path
+  if (a->dtype == PAULI_C128) return fused_w<double>(a, b, o, s);
+  return fused_w<float>(a, b, o, s);
+}
+
+}  // namespace pauli
