@@ -161,7 +161,7 @@ k_gen(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gsA,
       const uint32_t* __restrict__ gB, const uint32_t* __restrict__ gsB,
       const uint32_t* __restrict__ sidxB, const uint64_t* __restrict__ skeyB,
       const uint32_t* __restrict__ Tt, const uint32_t* __restrict__ soff, int d1, uint32_t ma,
-      uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+      int ibits, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const uint32_t nc = 1u << d1, ntile = nc * nc;
   for (uint32_t tau = blockIdx.x; tau < ntile; tau += gridDim.x) {
     const uint32_t s = tau >> d1, hA = tau & (nc - 1), hB = hA ^ s;
@@ -172,7 +172,7 @@ k_gen(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gsA,
       const uint32_t ia = t / nb, jb = t - ia * nb;
       const uint32_t i = sidxA[a0 + ia], j = sidxB[b0 + jb];
       keys[base + t] = skeyA[a0 + ia] ^ skeyB[b0 + jb];
-      vals[base + t] = j * ma + i;
+      vals[base + t] = ibits >= 0 ? ((j << ibits) | i) : j * ma + i;
     }
   }
 }
@@ -638,13 +638,25 @@ k_heavy_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ tkeys,
 
 template <int WT, typename T>
 struct Operands {
-  const uint64_t* ra;  // [|a|][2*Wp]
+  const uint64_t* ra;  // [|a|][2*G] (X words, then Z words, each half padded)
   const uint64_t* rb;
   const Aux<T>* xa;
   const Aux<T>* xb;
   uint32_t ma;
-  int nw;  // W
+  int ibits;  // pair id = (j << ibits) | i when ibits >= 0, else j*ma + i
+  int nw;     // W
 };
+
+__device__ __forceinline__ void split_id(uint32_t id, uint32_t ma, int ibits, uint32_t& i,
+                                         uint32_t& j) {
+  if (ibits >= 0) {
+    j = id >> ibits;
+    i = id & ((1u << ibits) - 1u);
+  } else {
+    j = id / ma;
+    i = id - j * ma;
+  }
+}
 
 // G lanes hold one record: lane l < G/2 the X words 2l, 2l+1 of the product
 // string, lane l >= G/2 the Z words; with G == 1 one lane holds X0 and Z0.
@@ -657,8 +669,9 @@ struct Rec {
 
 template <int G, int WT, typename T>
 __device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_t id, int gl) {
-  const uint32_t j = id / op.ma, i = id - j * op.ma;
-  // a row is G 16-byte pieces (Wp = G words per half)
+  uint32_t i, j;
+  split_id(id, op.ma, op.ibits, i, j);
+  // a row is G 16-byte pieces
   const ulonglong2 a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
   const ulonglong2 b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
   const Aux<T> xa = op.xa[i], xb = op.xb[j];
@@ -672,7 +685,7 @@ __device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_
   } else {
     constexpr int half = G / 2;
     const int lane = threadIdx.x & 63;
-    // Z words of the same indices live half lanes up
+    // the Z words of the same indices live half lanes up
     const uint64_t za0 = __shfl(a.x, lane + half, 64), za1 = __shfl(a.y, lane + half, 64);
     const uint64_t z30 = __shfl(r.w0, lane + half, 64), z31 = __shfl(r.w1, lane + half, 64);
     part = 0;
@@ -705,6 +718,153 @@ struct ExpandArgs {
   int64_t ldo;
 };
 
+// Merged terms of one block step, staged for coalesced stores.
+template <int WT, typename T, int RB>
+struct Stage {
+  uint64_t x[WT][RB];
+  uint64_t z[WT][RB];
+  cplx<T> c[RB];
+  uint64_t fp[RB];
+  uint8_t valid[RB];
+  uint32_t first, count;
+};
+
+template <int G, int WT, typename T, int RB>
+__device__ __forceinline__ void stage_out(Stage<WT, T, RB>& st, int nw, int gl, uint32_t slot,
+                                          const Rec<G, T>& r, T re, T im) {
+  if (G == 1) {
+    st.x[0][slot] = r.w0;
+    st.z[0][slot] = r.w1;
+  } else {
+    constexpr int half = G / 2;
+    const int base = 2 * (gl < half ? gl : gl - half);
+    uint64_t(*D)[RB] = gl < half ? st.x : st.z;
+    if (base < nw) D[base][slot] = r.w0;
+    if (base + 1 < nw) D[base + 1][slot] = r.w1;
+  }
+  if (gl == 0) {
+    st.c[slot] = cplx<T>{re, im};
+    st.fp[slot] = r.fp;
+    st.valid[slot] = 1;
+  }
+}
+
+// One block per bucket (grid-stride).  The block walks the bucket in steps
+// of RB records; group g takes the kRun records of step position g*kRun and
+// handles every segment whose first record lies there (continuing past the
+// run when the segment does), except segments longer than kLong, which
+// k_expand_long sums.  The terms of a step's segments form one contiguous
+// output range: they are staged in LDS and stored coalesced, array by array.
+template <int G, int WT, typename T>
+__global__ void __launch_bounds__(kB)
+k_expand(ExpandArgs E, Operands<WT, T> op) {
+  constexpr int NG = kB / G;
+  constexpr int RB = NG * kRun;
+  __shared__ Stage<WT, T, RB> st;
+  const int g = threadIdx.x / G, gl = threadIdx.x % G;
+  const int nw = op.nw;
+  for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
+    const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
+    const uint32_t obase = E.segoff[b];
+    for (uint32_t r0 = 0; r0 < n; r0 += RB) {
+      if (threadIdx.x == 0) {
+        const uint32_t s0 = E.segidx[lo + r0];
+        const uint32_t first = (r0 > 0 && E.segidx[lo + r0 - 1] == s0) ? s0 + 1 : s0;
+        const uint32_t rl = (r0 + RB < n ? r0 + RB : n) - 1;
+        const uint32_t slast = E.segidx[lo + rl];
+        st.first = first;
+        st.count = slast + 1 > first ? slast + 1 - first : 0u;
+      }
+      for (int t = threadIdx.x; t < RB; t += kB) st.valid[t] = 0;
+      __syncthreads();
+      const uint32_t sfirst = st.first;
+      const uint32_t p0 = r0 + static_cast<uint32_t>(g) * kRun;
+      if (p0 < n) {
+        const uint32_t sprev = p0 ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
+        uint32_t sid[kRun];
+        uint32_t ids[kRun];
+#pragma unroll
+        for (int t = 0; t < kRun; ++t) {
+          sid[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
+          ids[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
+        }
+        Rec<G, T> rec[kRun];
+#pragma unroll
+        for (int t = 0; t < kRun; ++t)
+          if (p0 + t < n) rec[t] = load_rec<G, WT, T>(op, ids[t], gl);
+        T acc_re = 0, acc_im = 0;
+        uint64_t h0 = 0, h1 = 0, diff = 0;
+        bool open = false;
+        int t_head = 0;
+        Rec<G, T> first;
+#pragma unroll
+        for (int t = 0; t < kRun; ++t) {
+          if (p0 + t >= n) break;
+          const bool head = sid[t] != (t ? sid[t - 1] : sprev);
+          if (head) {
+            open = true;
+            t_head = t;
+            acc_re = rec[t].re;
+            acc_im = rec[t].im;
+            first = rec[t];
+            h0 = rec[t].w0;
+            h1 = rec[t].w1;
+          } else if (open) {
+            acc_re = acc_re + rec[t].re;
+            acc_im = acc_im + rec[t].im;
+            diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
+          }
+          const bool ends = p0 + t + 1 >= n || (t + 1 < kRun && sid[t + 1] != sid[t]);
+          if (open && ends) {
+            stage_out<G, WT, T, RB>(st, nw, gl, sid[t] - sfirst, first, acc_re, acc_im);
+            open = false;
+          }
+        }
+        if (open) {
+          // the run's last segment continues past the run: follow it, unless
+          // it is longer than kLong (then k_expand_long sums it)
+          const uint32_t s_cur = sid[kRun - 1];
+          uint32_t len = static_cast<uint32_t>(kRun - t_head);
+          uint32_t q = p0 + kRun;
+          bool is_long = false;
+          while (q < n && E.segidx[lo + q] == s_cur) {
+            if (++len > static_cast<uint32_t>(kLong)) {
+              is_long = true;
+              break;
+            }
+            const Rec<G, T> r = load_rec<G, WT, T>(op, E.vals[lo + q], gl);
+            acc_re = acc_re + r.re;
+            acc_im = acc_im + r.im;
+            diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
+            ++q;
+          }
+          if (!is_long) stage_out<G, WT, T, RB>(st, nw, gl, s_cur - sfirst, first, acc_re, acc_im);
+        }
+        // an equal key must be an equal string
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
+        if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
+      }
+      __syncthreads();
+      const uint32_t cnt = st.count;
+      const int64_t ob = static_cast<int64_t>(obase) + sfirst;
+      for (int w = 0; w < nw; ++w)
+        for (uint32_t k = threadIdx.x; k < cnt; k += kB)
+          if (st.valid[k]) {
+            E.OX[w * E.ldo + ob + k] = st.x[w][k];
+            E.OZ[w * E.ldo + ob + k] = st.z[w][k];
+          }
+      for (uint32_t k = threadIdx.x; k < cnt; k += kB)
+        if (st.valid[k]) {
+          E.Oph[ob + k] = 0;
+          static_cast<cplx<T>*>(E.Oc)[ob + k] = st.c[k];
+          E.Ofp[ob + k] = st.fp[k];
+        }
+      __syncthreads();
+    }
+  }
+}
+
 template <int G, typename T>
 __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, int64_t o,
                                           const Rec<G, T>& r, T re, T im) {
@@ -722,91 +882,6 @@ __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, i
     E.Oph[o] = 0;
     static_cast<cplx<T>*>(E.Oc)[o] = cplx<T>{re, im};
     E.Ofp[o] = r.fp;
-  }
-}
-
-// One block per bucket (grid-stride).  Group g takes runs of kRun records;
-// it handles every segment whose first record lies in its run (continuing
-// past the run's end when the segment does), except segments longer than
-// kLong, which k_expand_long sums.
-template <int G, int WT, typename T>
-__global__ void __launch_bounds__(kB)
-k_expand(ExpandArgs E, Operands<WT, T> op) {
-  constexpr int NG = kB / G;
-  const int g = threadIdx.x / G, gl = threadIdx.x % G;
-  for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
-    const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
-    const uint32_t obase = E.segoff[b];
-    for (uint32_t p0 = static_cast<uint32_t>(g) * kRun; p0 < n; p0 += NG * kRun) {
-      // segment index of the record before the run, and of each record
-      uint32_t sprev = p0 ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
-      uint32_t sid[kRun + 1];
-      uint32_t ids[kRun];
-#pragma unroll
-      for (int t = 0; t <= kRun; ++t) sid[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
-#pragma unroll
-      for (int t = 0; t < kRun; ++t) ids[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
-      Rec<G, T> rec[kRun];
-#pragma unroll
-      for (int t = 0; t < kRun; ++t)
-        if (p0 + t < n) rec[t] = load_rec<G, WT, T>(op, ids[t], gl);
-      // walk the run: segments whose first record lies inside it
-      T acc_re = 0, acc_im = 0;
-      uint64_t h0 = 0, h1 = 0;
-      bool open = false;
-      int t_head = 0;
-      Rec<G, T> first;
-      uint64_t diff = 0;
-#pragma unroll
-      for (int t = 0; t < kRun; ++t) {
-        if (p0 + t >= n) break;
-        const bool head = sid[t] != (t ? sid[t - 1] : sprev);
-        if (head) {
-          open = true;
-          t_head = t;
-          acc_re = rec[t].re;
-          acc_im = rec[t].im;
-          first = rec[t];
-          h0 = rec[t].w0;
-          h1 = rec[t].w1;
-        } else if (open) {
-          acc_re = acc_re + rec[t].re;
-          acc_im = acc_im + rec[t].im;
-          diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
-        }
-        const bool ends = p0 + t + 1 >= n || (t + 1 < kRun && sid[t + 1] != sid[t]);
-        if (open && ends) {
-          write_out<G, T>(E, op.nw, gl, static_cast<int64_t>(obase) + sid[t], first, acc_re, acc_im);
-          open = false;
-        }
-      }
-      if (open) {
-        // the run's last segment continues past the run: follow it, unless
-        // it is longer than kLong (then k_expand_long sums it)
-        const uint32_t s_cur = sid[kRun - 1];
-        uint32_t len = static_cast<uint32_t>(kRun - t_head);
-        uint32_t q = p0 + kRun;
-        bool is_long = false;
-        while (q < n && E.segidx[lo + q] == s_cur) {
-          if (++len > static_cast<uint32_t>(kLong)) {
-            is_long = true;
-            break;
-          }
-          const Rec<G, T> r = load_rec<G, WT, T>(op, E.vals[lo + q], gl);
-          acc_re = acc_re + r.re;
-          acc_im = acc_im + r.im;
-          diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
-          ++q;
-        }
-        if (!is_long)
-          write_out<G, T>(E, op.nw, gl, static_cast<int64_t>(obase) + s_cur, first, acc_re,
-                          acc_im);
-      }
-      // an equal key must be an equal string
-#pragma unroll
-      for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
-      if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
-    }
   }
 }
 
@@ -942,6 +1017,11 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
     fmask = rem ? ((1ull << rem) - 1) : 0ull;
   }
 
+  // pair id: (j << ibits) | i when that fits in 32 bits, else j*|a| + i
+  int ibits = 0;
+  while ((int64_t(1) << ibits) < a->m) ++ibits;
+  if ((static_cast<uint64_t>(b->m) << ibits) > 0xFFFFFFFFull) ibits = -1;
+
   SidePrep<T> A, B;
   const bool same = a == b;
   {
@@ -971,8 +1051,8 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                        s, A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
                        A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
                        Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
-                       Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, static_cast<uint32_t>(a->m), K,
-                       V);
+                       Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, static_cast<uint32_t>(a->m),
+                       ibits, K, V);
     PAULI_HIP(hipGetLastError());
     if (d2 > 0) {
       DBuf nt(nc * 4ull, s), tb(nc * 4ull + 4, s);
@@ -1027,7 +1107,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                ctr32 + 2, out->X, out->Z, out->ph, out->coef, out->fp, out->ld};
   Operands<WT, T> op{A.rows.template as<uint64_t>(), Bs.rows.template as<uint64_t>(),
                      A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
-                     static_cast<uint32_t>(a->m), W};
+                     static_cast<uint32_t>(a->m), ibits, W};
   {
     StageScope sc(PAULI_STAGE_WRITE, s,
                   U * (16.0 * W + sizeof(cplx<T>) + 1 + 8) + P * 8.0);
