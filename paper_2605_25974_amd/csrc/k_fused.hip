@@ -50,7 +50,7 @@ constexpr int kSortRounds = kCap / kSortWaves / 64;
 constexpr int kMaxBits = 16;
 constexpr double kTargetBucket = 4096.0;
 constexpr int kLong = 32;  // segments longer than this are reduced by a block
-constexpr int kRun = 4;    // records per group per step of the expand kernel
+constexpr int kRun = 4;    // records per lane group per chunk of the expand kernel
 
 enum : uint32_t { kErrCollision = 1u };
 
@@ -718,7 +718,7 @@ struct ExpandArgs {
   int64_t ldo;
 };
 
-// Merged terms of one block step, staged for coalesced stores.
+// Merged terms of one wave chunk, staged for coalesced stores.
 template <int WT, typename T, int RB>
 struct Stage {
   uint64_t x[WT][RB];
@@ -726,7 +726,6 @@ struct Stage {
   cplx<T> c[RB];
   uint64_t fp[RB];
   uint8_t valid[RB];
-  uint32_t first, count;
 };
 
 template <int G, int WT, typename T, int RB>
@@ -749,49 +748,57 @@ __device__ __forceinline__ void stage_out(Stage<WT, T, RB>& st, int nw, int gl, 
   }
 }
 
-// One block per bucket (grid-stride).  The block walks the bucket in steps
-// of RB records; group g takes the kRun records of step position g*kRun and
-// handles every segment whose first record lies there (continuing past the
-// run when the segment does), except segments longer than kLong, which
-// k_expand_long sums.  The terms of a step's segments form one contiguous
-// output range: they are staged in LDS and stored coalesced, array by array.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Buckets are spread over blocks; inside a bucket every wave independently
+// takes chunks of RB consecutive records (no block barriers).  Group g of a
+// wave takes kRun records of the chunk and handles every segment whose first
+// record lies there (continuing past the run when the segment does), except
+// segments longer than kLong, which k_expand_long sums.  The terms of a
+// chunk's segments form one contiguous output range: they are staged in the
+// wave's LDS region and stored coalesced, array by array.
 template <int G, int WT, typename T>
-__global__ void __launch_bounds__(kB)
+__global__ void __launch_bounds__(kB, 4)
 k_expand(ExpandArgs E, Operands<WT, T> op) {
-  constexpr int NG = kB / G;
+  constexpr int NG = 64 / G;  // groups per wave
   constexpr int RB = NG * kRun;
-  __shared__ Stage<WT, T, RB> st;
-  const int g = threadIdx.x / G, gl = threadIdx.x % G;
+  constexpr int NW = kB / 64;
+  __shared__ Stage<WT, T, RB> stage[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  Stage<WT, T, RB>& st = stage[wave];
+  const int g = lane / G, gl = lane % G;
   const int nw = op.nw;
   for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
     const uint32_t obase = E.segoff[b];
-    for (uint32_t r0 = 0; r0 < n; r0 += RB) {
-      if (threadIdx.x == 0) {
-        const uint32_t s0 = E.segidx[lo + r0];
-        const uint32_t first = (r0 > 0 && E.segidx[lo + r0 - 1] == s0) ? s0 + 1 : s0;
-        const uint32_t rl = (r0 + RB < n ? r0 + RB : n) - 1;
-        const uint32_t slast = E.segidx[lo + rl];
-        st.first = first;
-        st.count = slast + 1 > first ? slast + 1 - first : 0u;
-      }
-      for (int t = threadIdx.x; t < RB; t += kB) st.valid[t] = 0;
-      __syncthreads();
-      const uint32_t sfirst = st.first;
+    for (uint32_t r0 = static_cast<uint32_t>(wave) * RB; r0 < n; r0 += NW * RB) {
+      for (int kk = lane; kk < RB; kk += 64) st.valid[kk] = 0;
       const uint32_t p0 = r0 + static_cast<uint32_t>(g) * kRun;
+      const uint32_t sprev = (p0 && p0 < n) ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
+      uint32_t sid[kRun], ids[kRun];
+#pragma unroll
+      for (int t = 0; t < kRun; ++t) {
+        sid[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
+        ids[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
+      }
+      // first segment with its first record in the chunk, and the chunk's
+      // last segment (from groups 0 and NG-1)
+      const uint32_t s_at0 = __shfl(sid[0], 0, 64);
+      const uint32_t s_before = __shfl(sprev, 0, 64);
+      const uint32_t sfirst = s_at0 == s_before ? s_at0 + 1 : s_at0;
+      const uint32_t rl = (r0 + RB < n ? r0 + RB : n) - 1 - r0;  // last record, chunk-relative
+      const uint32_t s_last = __shfl(sid[rl % kRun], static_cast<int>((rl / kRun) * G), 64);
+      const uint32_t cnt = s_last + 1 > sfirst ? s_last + 1 - sfirst : 0u;
+      Rec<G, T> rec[kRun];
+#pragma unroll
+      for (int t = 0; t < kRun; ++t)
+        if (p0 + t < n) rec[t] = load_rec<G, WT, T>(op, ids[t], gl);
+      wave_sync();  // valid[] cleared before any stage_out
       if (p0 < n) {
-        const uint32_t sprev = p0 ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
-        uint32_t sid[kRun];
-        uint32_t ids[kRun];
-#pragma unroll
-        for (int t = 0; t < kRun; ++t) {
-          sid[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
-          ids[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
-        }
-        Rec<G, T> rec[kRun];
-#pragma unroll
-        for (int t = 0; t < kRun; ++t)
-          if (p0 + t < n) rec[t] = load_rec<G, WT, T>(op, ids[t], gl);
         T acc_re = 0, acc_im = 0;
         uint64_t h0 = 0, h1 = 0, diff = 0;
         bool open = false;
@@ -845,22 +852,27 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
         for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
         if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
       }
-      __syncthreads();
-      const uint32_t cnt = st.count;
+      wave_sync();
       const int64_t ob = static_cast<int64_t>(obase) + sfirst;
-      for (int w = 0; w < nw; ++w)
-        for (uint32_t k = threadIdx.x; k < cnt; k += kB)
-          if (st.valid[k]) {
-            E.OX[w * E.ldo + ob + k] = st.x[w][k];
-            E.OZ[w * E.ldo + ob + k] = st.z[w][k];
+      // two arrays per store instruction when the chunk has at most 32 terms
+      constexpr int kPer = RB <= 32 ? 2 : 1;
+      const uint32_t k = RB <= 32 ? static_cast<uint32_t>(lane & 31) : static_cast<uint32_t>(lane);
+      const int sub = RB <= 32 ? (lane >> 5) : 0;
+      for (int w0 = 0; w0 < nw; w0 += kPer) {
+        const int w = w0 + sub;
+        for (uint32_t kk = k; kk < cnt; kk += 64 / kPer)
+          if (w < nw && st.valid[kk]) {
+            E.OX[w * E.ldo + ob + kk] = st.x[w][kk];
+            E.OZ[w * E.ldo + ob + kk] = st.z[w][kk];
           }
-      for (uint32_t k = threadIdx.x; k < cnt; k += kB)
-        if (st.valid[k]) {
-          E.Oph[ob + k] = 0;
-          static_cast<cplx<T>*>(E.Oc)[ob + k] = st.c[k];
-          E.Ofp[ob + k] = st.fp[k];
+      }
+      for (uint32_t kk = static_cast<uint32_t>(lane); kk < cnt; kk += 64)
+        if (st.valid[kk]) {
+          E.Oph[ob + kk] = 0;
+          static_cast<cplx<T>*>(E.Oc)[ob + kk] = st.c[kk];
+          E.Ofp[ob + kk] = st.fp[kk];
         }
-      __syncthreads();
+      wave_sync();  // the stage is reused by the next chunk
     }
   }
 }
