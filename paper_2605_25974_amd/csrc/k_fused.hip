@@ -54,13 +54,25 @@ constexpr int kRun = 4;    // records per lane group per chunk of the expand ker
 
 enum : uint32_t { kErrCollision = 1u };
 
+// Per-term data of an operand as four 64-bit words: the coefficient's real
+// and imaginary parts (one per word, in the sum's precision), the
+// fingerprint, and e = (phase + |X & Z|) mod 4.
 template <typename T>
 struct alignas(32) Aux {
-  T re, im;
-  uint64_t fp;
-  uint32_t e;  // (phase + |X & Z|) mod 4
-  uint32_t pad;
+  uint64_t w[4];
 };
+template <typename T>
+__host__ __device__ __forceinline__ uint64_t to_word(T v) {
+  uint64_t u = 0;
+  __builtin_memcpy(&u, &v, sizeof(T));
+  return u;
+}
+template <typename T>
+__device__ __forceinline__ T from_word(uint64_t u) {
+  T v;
+  __builtin_memcpy(&v, &u, sizeof(T));
+  return v;
+}
 
 inline unsigned grid_for(int64_t n, int per = kB, int64_t cap = 65536) {
   int64_t g = (n + per - 1) / per;
@@ -116,7 +128,12 @@ __global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restri
       rows[static_cast<size_t>(t) * 2 * Wp + Wp + w] = z;
       y += popc64(x & z);
     }
-    aux[t] = Aux<T>{c[t].re, c[t].im, fp[t], static_cast<uint32_t>((ph[t] + y) & 3), 0u};
+    Aux<T> x;
+    x.w[0] = to_word<T>(c[t].re);
+    x.w[1] = to_word<T>(c[t].im);
+    x.w[2] = fp[t];
+    x.w[3] = static_cast<uint64_t>((ph[t] + y) & 3);
+    aux[t] = x;
     const uint64_t k = fp[t] >> kshift;
     key[t] = k;
     cls[t] = d1 ? (k >> cshift) : 0ull;
@@ -667,14 +684,41 @@ struct Rec {
   uint64_t fp;
 };
 
+// Raw loads of one record: this lane's 16-byte pieces of the two operand
+// rows, and its share of the 8 metadata words (aux of a_i, then of b_j).
+template <int G>
+struct Raw {
+  static constexpr int PW = G >= 8 ? 1 : 8 / G;
+  ulonglong2 a, b;
+  uint64_t piece[PW];
+};
+
 template <int G, int WT, typename T>
-__device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_t id, int gl) {
+__device__ __forceinline__ Raw<G> issue_rec(const Operands<WT, T>& op, uint32_t id, int gl) {
   uint32_t i, j;
   split_id(id, op.ma, op.ibits, i, j);
-  // a row is G 16-byte pieces
-  const ulonglong2 a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
-  const ulonglong2 b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
-  const Aux<T> xa = op.xa[i], xb = op.xb[j];
+  Raw<G> r;
+  // a row is G 16-byte pieces, one per lane
+  r.a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
+  r.b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
+#pragma unroll
+  for (int p = 0; p < Raw<G>::PW; ++p) {
+    const int k = gl * Raw<G>::PW + p;
+    r.piece[p] = k < 4 ? op.xa[i].w[k & 3] : (k < 8 ? op.xb[j].w[k & 3] : 0ull);
+  }
+  return r;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ Rec<G, T> finish_rec(const Raw<G>& raw, int gl) {
+  constexpr int PW = Raw<G>::PW;
+  const int lane = threadIdx.x & 63, base = lane - gl;
+  // metadata word k lives in lane k / PW of the group
+  auto word = [&](int k) -> uint64_t {
+    if (G == 1) return raw.piece[k];
+    return __shfl(raw.piece[k % PW], base + k / PW, 64);
+  };
+  const ulonglong2 a = raw.a, b = raw.b;
   Rec<G, T> r;
   r.w0 = a.x ^ b.x;
   r.w1 = a.y ^ b.y;
@@ -684,7 +728,6 @@ __device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_
     part = 2 * popc64(a.y & b.x) - popc64(r.w0 & r.w1);
   } else {
     constexpr int half = G / 2;
-    const int lane = threadIdx.x & 63;
     // the Z words of the same indices live half lanes up
     const uint64_t za0 = __shfl(a.x, lane + half, 64), za1 = __shfl(a.y, lane + half, 64);
     const uint64_t z30 = __shfl(r.w0, lane + half, 64), z31 = __shfl(r.w1, lane + half, 64);
@@ -693,14 +736,22 @@ __device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_
       part = 2 * (popc64(za0 & b.x) + popc64(za1 & b.y)) - popc64(r.w0 & z30) - popc64(r.w1 & z31);
 #pragma unroll
     for (int off = half / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    part = __shfl(part, lane - gl, 64);
+    part = __shfl(part, base, 64);
   }
-  const int k = static_cast<int>(xa.e + xb.e) + part;
-  const cplx<T> v = rot_ik(k, cmul(cplx<T>{xa.re, xa.im}, cplx<T>{xb.re, xb.im}));
+  const uint64_t ar = word(0), ai = word(1), af = word(2), ae = word(3);
+  const uint64_t br = word(4), bi = word(5), bf = word(6), be = word(7);
+  const int k = static_cast<int>(ae + be) + part;
+  const cplx<T> v = rot_ik(k, cmul(cplx<T>{from_word<T>(ar), from_word<T>(ai)},
+                                   cplx<T>{from_word<T>(br), from_word<T>(bi)}));
   r.re = v.re;
   r.im = v.im;
-  r.fp = xa.fp ^ xb.fp;
+  r.fp = af ^ bf;
   return r;
+}
+
+template <int G, int WT, typename T>
+__device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_t id, int gl) {
+  return finish_rec<G, T>(issue_rec<G, WT, T>(op, id, gl), gl);
 }
 
 struct ExpandArgs {
@@ -754,6 +805,59 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Segment indices and ids of the kRun records of a lane group's run, as
+// loaded by the lane (distributed over the group's lanes when G allows).
+template <int G>
+struct Meta {
+  static constexpr bool kSplit = G >= kRun + 2;
+  uint32_t ms[kSplit ? 1 : kRun + 2];
+  uint32_t mi[kSplit ? 1 : kRun];
+};
+
+template <int G>
+__device__ __forceinline__ Meta<G> fetch_meta(const ExpandArgs& E, uint32_t lo, uint32_t n,
+                                              uint32_t p0, int gl) {
+  Meta<G> m;
+  if (Meta<G>::kSplit) {
+    // lane gl: segment index of record p0 + gl (gl <= kRun), its id
+    // (gl < kRun), the segment index before the run (gl == kRun + 1)
+    m.ms[0] = 0xFFFFFFFEu;
+    m.mi[0] = 0u;
+    if (gl <= kRun) {
+      if (p0 + gl < n) m.ms[0] = E.segidx[lo + p0 + gl];
+      if (gl < kRun && p0 + gl < n) m.mi[0] = E.vals[lo + p0 + gl];
+    } else if (gl == kRun + 1) {
+      m.ms[0] = (p0 && p0 < n) ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t <= kRun; ++t) m.ms[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
+    m.ms[kRun + 1] = (p0 && p0 < n) ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int t = 0; t < kRun; ++t) m.mi[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
+  }
+  return m;
+}
+
+template <int G>
+__device__ __forceinline__ void unpack_meta(const Meta<G>& m, int gl, uint32_t* sid,
+                                            uint32_t* ids, uint32_t& sprev) {
+  if (Meta<G>::kSplit) {
+    const int base = (threadIdx.x & 63) - gl;
+#pragma unroll
+    for (int t = 0; t <= kRun; ++t) sid[t] = __shfl(m.ms[0], base + t, 64);
+#pragma unroll
+    for (int t = 0; t < kRun; ++t) ids[t] = __shfl(m.mi[0], base + t, 64);
+    sprev = __shfl(m.ms[0], base + kRun + 1, 64);
+  } else {
+#pragma unroll
+    for (int t = 0; t <= kRun; ++t) sid[t] = m.ms[t];
+#pragma unroll
+    for (int t = 0; t < kRun; ++t) ids[t] = m.mi[t];
+    sprev = m.ms[kRun + 1];
+  }
+}
+
 // Buckets are spread over blocks; inside a bucket every wave independently
 // takes chunks of RB consecutive records (no block barriers).  Group g of a
 // wave takes kRun records of the chunk and handles every segment whose first
@@ -761,12 +865,19 @@ __device__ __forceinline__ void wave_sync() {
 // segments longer than kLong, which k_expand_long sums.  The terms of a
 // chunk's segments form one contiguous output range: they are staged in the
 // wave's LDS region and stored coalesced, array by array.
+//
+// Loads and stores share one in-order completion counter per wave, so a wait
+// for a load also waits for every store issued before it.  The loop is
+// therefore pipelined: the ids of chunk c+2 and the row/metadata gathers of
+// chunk c+1 are issued before the stores of chunk c, and no wait ever has an
+// older store ahead of it.
 template <int G, int WT, typename T>
-__global__ void __launch_bounds__(kB, 4)
+__global__ void __launch_bounds__(kB, 3)
 k_expand(ExpandArgs E, Operands<WT, T> op) {
   constexpr int NG = 64 / G;  // groups per wave
   constexpr int RB = NG * kRun;
   constexpr int NW = kB / 64;
+  constexpr uint32_t STEP = NW * RB;
   __shared__ Stage<WT, T, RB> stage[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   Stage<WT, T, RB>& st = stage[wave];
@@ -775,28 +886,38 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
   for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
     const uint32_t obase = E.segoff[b];
-    for (uint32_t r0 = static_cast<uint32_t>(wave) * RB; r0 < n; r0 += NW * RB) {
-      for (int kk = lane; kk < RB; kk += 64) st.valid[kk] = 0;
-      const uint32_t p0 = r0 + static_cast<uint32_t>(g) * kRun;
-      const uint32_t sprev = (p0 && p0 < n) ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
-      uint32_t sid[kRun], ids[kRun];
+    uint32_t r0 = static_cast<uint32_t>(wave) * RB;
+    if (r0 >= n) continue;
+    const uint32_t goff = static_cast<uint32_t>(g) * kRun;
+    // pipeline prologue: metadata of chunks 0 and 1, gathers of chunk 0
+    Meta<G> m_cur = fetch_meta<G>(E, lo, n, r0 + goff, gl);
+    Meta<G> m_next = fetch_meta<G>(E, lo, n, r0 + STEP + goff, gl);
+    uint32_t sid[kRun + 1], ids[kRun], sprev;
+    unpack_meta<G>(m_cur, gl, sid, ids, sprev);
+    // ids past the bucket's end read as 0, a valid pair: the gathers are
+    // issued unconditionally so that no stale registers stay live
+    Raw<G> raw[kRun];
 #pragma unroll
-      for (int t = 0; t < kRun; ++t) {
-        sid[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
-        ids[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
-      }
+    for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
+    for (; r0 < n; r0 += STEP) {
+      const uint32_t p0 = r0 + goff;
+      const Meta<G> m_after = fetch_meta<G>(E, lo, n, r0 + 2 * STEP + goff, gl);
+      for (int kk = lane; kk < RB; kk += 64) st.valid[kk] = 0;
       // first segment with its first record in the chunk, and the chunk's
       // last segment (from groups 0 and NG-1)
       const uint32_t s_at0 = __shfl(sid[0], 0, 64);
       const uint32_t s_before = __shfl(sprev, 0, 64);
       const uint32_t sfirst = s_at0 == s_before ? s_at0 + 1 : s_at0;
       const uint32_t rl = (r0 + RB < n ? r0 + RB : n) - 1 - r0;  // last record, chunk-relative
-      const uint32_t s_last = __shfl(sid[rl % kRun], static_cast<int>((rl / kRun) * G), 64);
+      uint32_t s_mine = sid[0];
+#pragma unroll
+      for (int t = 1; t < kRun; ++t)
+        if (static_cast<int>(rl % kRun) == t) s_mine = sid[t];
+      const uint32_t s_last = __shfl(s_mine, static_cast<int>((rl / kRun) * G), 64);
       const uint32_t cnt = s_last + 1 > sfirst ? s_last + 1 - sfirst : 0u;
       Rec<G, T> rec[kRun];
 #pragma unroll
-      for (int t = 0; t < kRun; ++t)
-        if (p0 + t < n) rec[t] = load_rec<G, WT, T>(op, ids[t], gl);
+      for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T>(raw[t], gl);
       wave_sync();  // valid[] cleared before any stage_out
       if (p0 < n) {
         T acc_re = 0, acc_im = 0;
@@ -821,7 +942,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
             acc_im = acc_im + rec[t].im;
             diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
           }
-          const bool ends = p0 + t + 1 >= n || (t + 1 < kRun && sid[t + 1] != sid[t]);
+          const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
           if (open && ends) {
             stage_out<G, WT, T, RB>(st, nw, gl, sid[t] - sfirst, first, acc_re, acc_im);
             open = false;
@@ -852,6 +973,11 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
         for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
         if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
       }
+      // gathers of the next chunk go out before this chunk's stores
+      unpack_meta<G>(m_next, gl, sid, ids, sprev);
+#pragma unroll
+      for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
+      m_next = m_after;
       wave_sync();
       const int64_t ob = static_cast<int64_t>(obase) + sfirst;
       // two arrays per store instruction when the chunk has at most 32 terms
