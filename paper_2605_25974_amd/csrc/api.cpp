@@ -420,7 +420,7 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
     hipStream_t s = as_stream(stream);
     a->last_stream = b->last_stream = s;
     paulisum* r = nullptr;
-    if (m.mode == PAULI_MERGE_PLAIN && a->m > 0 && b->m > 0) r = fused_bucket(a, b, m, s);
+    if (a->m > 0 && b->m > 0) r = fused_bucket(a, b, m, s);
     if (!r) r = merge_generic(a, b, m, s);
     *out = r;
   });

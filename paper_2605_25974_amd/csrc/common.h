@@ -65,6 +65,89 @@ __device__ __forceinline__ cplx<T> rot_ik(int k, cplx<T> v) {
   }
 }
 
+// ------------------------------------------------- accumulation policies
+//
+// A segment's value is the sum of its records' values i^k * c_a * c_b, in
+// record order.
+//
+// kPlain: products and sums in the operands' precision.
+//
+// kComp (the precision form): products in FP32 from the operands rounded to
+// FP32, summed with Sum2 of Ogita, Rump and Oishi (2005): Knuth's TwoSum
+// splits each addition into the rounded sum and its exact rounding error,
+// and the errors are added up beside the sum.  The accumulator also keeps
+// the mass A = sum of |record value|.  A segment whose result is below
+// tau * A has cancelled; its records are then summed again in FP64 from the
+// operands' own coefficients.
+constexpr int kPlain = 0;
+constexpr int kComp = 1;
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+template <int MODE, typename TV>
+struct Acc;
+
+template <typename TV>
+struct Acc<kPlain, TV> {
+  TV re, im;
+  __device__ __forceinline__ void zero() { re = im = TV(0); }
+  __device__ __forceinline__ void begin(TV r, TV i) {
+    re = r;
+    im = i;
+  }
+  __device__ __forceinline__ void add(TV r, TV i) {
+    re = re + r;
+    im = im + i;
+  }
+  __device__ __forceinline__ void add(const Acc& o) { add(o.re, o.im); }
+  __device__ __forceinline__ TV value_re() const { return re; }
+  __device__ __forceinline__ TV value_im() const { return im; }
+  __device__ __forceinline__ bool cancels(double) const { return false; }
+};
+
+template <>
+struct Acc<kComp, float> {
+  float sr, er, si, ei, mass;
+  __device__ __forceinline__ void zero() { sr = er = si = ei = mass = 0.0f; }
+  __device__ __forceinline__ void begin(float r, float i) {
+    sr = r;
+    si = i;
+    er = ei = 0.0f;
+    mass = hypotf(r, i);
+  }
+  __device__ __forceinline__ void add(float r, float i) {
+    float s, e;
+    two_sum(sr, r, s, e);
+    sr = s;
+    er = er + e;
+    two_sum(si, i, s, e);
+    si = s;
+    ei = ei + e;
+    mass = mass + hypotf(r, i);
+  }
+  // adds another partial sum (its rounding errors included)
+  __device__ __forceinline__ void add(const Acc& o) {
+    float s, e;
+    two_sum(sr, o.sr, s, e);
+    sr = s;
+    er = er + (o.er + e);
+    two_sum(si, o.si, s, e);
+    si = s;
+    ei = ei + (o.ei + e);
+    mass = mass + o.mass;
+  }
+  __device__ __forceinline__ float value_re() const { return sr + er; }
+  __device__ __forceinline__ float value_im() const { return si + ei; }
+  __device__ __forceinline__ bool cancels(double tau) const {
+    return static_cast<double>(hypotf(value_re(), value_im())) <
+           tau * static_cast<double>(mass);
+  }
+};
+
 // ------------------------------------------------------------ phase rule
 //
 // Write each letter as L(x,z) = i^{xz} X^x Z^z (so L(1,1) = iXZ = Y, Table I

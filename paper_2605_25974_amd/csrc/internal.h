@@ -132,8 +132,12 @@ struct MergeArgs {
 // merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
 
-// k_bucket.hip: merge(a*b) by the fused bucket kernel; nullptr when a
-// fingerprint collision or a bucket overflow asks for merge_generic instead.
+// The terms of s whose modulus is not below drop_abs (strict drop), in
+// their order, as a new container.
+paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st);
+
+// k_fused.hip: merge(a*b) by the staged fused pipeline; nullptr when a
+// fingerprint collision asks for merge_generic instead.
 paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
 
 }  // namespace pauli

@@ -31,6 +31,7 @@
 //              call with the general pipeline.  Segments longer than kLong
 //              records are summed by a whole block in a fixed tree.
 #include <cmath>
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -677,10 +678,11 @@ __device__ __forceinline__ void split_id(uint32_t id, uint32_t ma, int ibits, ui
 
 // G lanes hold one record: lane l < G/2 the X words 2l, 2l+1 of the product
 // string, lane l >= G/2 the Z words; with G == 1 one lane holds X0 and Z0.
-template <int G, typename T>
+// TV is the arithmetic type of the value.
+template <int G, typename TV>
 struct Rec {
   uint64_t w0, w1;  // this lane's two product words
-  T re, im;         // value i^k c_a c_b (same in every lane of the group)
+  TV re, im;        // value i^k c_a c_b (same in every lane of the group)
   uint64_t fp;
 };
 
@@ -709,8 +711,10 @@ __device__ __forceinline__ Raw<G> issue_rec(const Operands<WT, T>& op, uint32_t 
   return r;
 }
 
-template <int G, typename T>
-__device__ __forceinline__ Rec<G, T> finish_rec(const Raw<G>& raw, int gl) {
+// TS: type the operands' coefficients are stored in; TV: type the product
+// is computed in (the stored coefficients are rounded to TV first).
+template <int G, typename TS, typename TV>
+__device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl) {
   constexpr int PW = Raw<G>::PW;
   const int lane = threadIdx.x & 63, base = lane - gl;
   // metadata word k lives in lane k / PW of the group
@@ -719,7 +723,7 @@ __device__ __forceinline__ Rec<G, T> finish_rec(const Raw<G>& raw, int gl) {
     return __shfl(raw.piece[k % PW], base + k / PW, 64);
   };
   const ulonglong2 a = raw.a, b = raw.b;
-  Rec<G, T> r;
+  Rec<G, TV> r;
   r.w0 = a.x ^ b.x;
   r.w1 = a.y ^ b.y;
   int part;
@@ -741,17 +745,18 @@ __device__ __forceinline__ Rec<G, T> finish_rec(const Raw<G>& raw, int gl) {
   const uint64_t ar = word(0), ai = word(1), af = word(2), ae = word(3);
   const uint64_t br = word(4), bi = word(5), bf = word(6), be = word(7);
   const int k = static_cast<int>(ae + be) + part;
-  const cplx<T> v = rot_ik(k, cmul(cplx<T>{from_word<T>(ar), from_word<T>(ai)},
-                                   cplx<T>{from_word<T>(br), from_word<T>(bi)}));
+  const cplx<TV> v =
+      rot_ik(k, cmul(cplx<TV>{static_cast<TV>(from_word<TS>(ar)), static_cast<TV>(from_word<TS>(ai))},
+                     cplx<TV>{static_cast<TV>(from_word<TS>(br)), static_cast<TV>(from_word<TS>(bi))}));
   r.re = v.re;
   r.im = v.im;
   r.fp = af ^ bf;
   return r;
 }
 
-template <int G, int WT, typename T>
-__device__ __forceinline__ Rec<G, T> load_rec(const Operands<WT, T>& op, uint32_t id, int gl) {
-  return finish_rec<G, T>(issue_rec<G, WT, T>(op, id, gl), gl);
+template <int G, int WT, typename TS, typename TV>
+__device__ __forceinline__ Rec<G, TV> load_rec(const Operands<WT, TS>& op, uint32_t id, int gl) {
+  return finish_rec<G, TS, TV>(issue_rec<G, WT, TS>(op, id, gl), gl);
 }
 
 struct ExpandArgs {
@@ -767,6 +772,7 @@ struct ExpandArgs {
   void* Oc;
   uint64_t* Ofp;
   int64_t ldo;
+  double tau;  // cancellation threshold of the compensated form
 };
 
 // Merged terms of one wave chunk, staged for coalesced stores.
@@ -779,9 +785,9 @@ struct Stage {
   uint8_t valid[RB];
 };
 
-template <int G, int WT, typename T, int RB>
+template <int G, int WT, typename T, int RB, typename TV>
 __device__ __forceinline__ void stage_out(Stage<WT, T, RB>& st, int nw, int gl, uint32_t slot,
-                                          const Rec<G, T>& r, T re, T im) {
+                                          const Rec<G, TV>& r, T re, T im) {
   if (G == 1) {
     st.x[0][slot] = r.w0;
     st.z[0][slot] = r.w1;
@@ -803,6 +809,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FP64 sum of the records at bucket positions q0 .. q1-1, in order, from the
+// operands' own coefficients (the re-merge of a cancelled segment).
+template <int G, int WT, typename T>
+__device__ __noinline__ cplx<double> remerge64(const ExpandArgs& E, const Operands<WT, T>& op,
+                                               uint32_t lo, uint32_t q0, uint32_t q1, int gl) {
+  double re = 0.0, im = 0.0;
+  for (uint32_t q = q0; q < q1; ++q) {
+    const Rec<G, double> r = load_rec<G, WT, T, double>(op, E.vals[lo + q], gl);
+    re = re + r.re;
+    im = im + r.im;
+  }
+  return {re, im};
 }
 
 // Segment indices and ids of the kRun records of a lane group's run, as
@@ -871,16 +891,19 @@ __device__ __forceinline__ void unpack_meta(const Meta<G>& m, int gl, uint32_t* 
 // therefore pipelined: the ids of chunk c+2 and the row/metadata gathers of
 // chunk c+1 are issued before the stores of chunk c, and no wait ever has an
 // older store ahead of it.
-template <int G, int WT, typename T>
+// With MODE == kComp a segment whose compensated FP32 sum cancels is summed
+// again in FP64 (remerge64) before it is staged.
+template <int G, int WT, typename T, int MODE>
 __global__ void __launch_bounds__(kB, 3)
 k_expand(ExpandArgs E, Operands<WT, T> op) {
+  using TV = typename std::conditional<MODE == kComp, float, T>::type;
   constexpr int NG = 64 / G;  // groups per wave
   constexpr int RB = NG * kRun;
   constexpr int NW = kB / 64;
   constexpr uint32_t STEP = NW * RB;
-  __shared__ Stage<WT, T, RB> stage[NW];
+  __shared__ Stage<WT, TV, RB> stage[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  Stage<WT, T, RB>& st = stage[wave];
+  Stage<WT, TV, RB>& st = stage[wave];
   const int g = lane / G, gl = lane % G;
   const int nw = op.nw;
   for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
@@ -915,16 +938,27 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
         if (static_cast<int>(rl % kRun) == t) s_mine = sid[t];
       const uint32_t s_last = __shfl(s_mine, static_cast<int>((rl / kRun) * G), 64);
       const uint32_t cnt = s_last + 1 > sfirst ? s_last + 1 - sfirst : 0u;
-      Rec<G, T> rec[kRun];
+      Rec<G, TV> rec[kRun];
 #pragma unroll
-      for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T>(raw[t], gl);
+      for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl);
       wave_sync();  // valid[] cleared before any stage_out
       if (p0 < n) {
-        T acc_re = 0, acc_im = 0;
+        Acc<MODE, TV> acc;
+        acc.zero();
         uint64_t h0 = 0, h1 = 0, diff = 0;
         bool open = false;
         int t_head = 0;
-        Rec<G, T> first;
+        Rec<G, TV> first;
+        // stages segment [q0, q1) (bucket positions) once its sum is known
+        auto emit = [&](uint32_t slot, uint32_t q0, uint32_t q1) {
+          TV vr = acc.value_re(), vi = acc.value_im();
+          if (MODE == kComp && acc.cancels(E.tau)) {
+            const cplx<double> c = remerge64<G, WT, T>(E, op, lo, q0, q1, gl);
+            vr = static_cast<TV>(c.re);
+            vi = static_cast<TV>(c.im);
+          }
+          stage_out<G, WT, TV, RB, TV>(st, nw, gl, slot, first, vr, vi);
+        };
 #pragma unroll
         for (int t = 0; t < kRun; ++t) {
           if (p0 + t >= n) break;
@@ -932,19 +966,17 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
           if (head) {
             open = true;
             t_head = t;
-            acc_re = rec[t].re;
-            acc_im = rec[t].im;
+            acc.begin(rec[t].re, rec[t].im);
             first = rec[t];
             h0 = rec[t].w0;
             h1 = rec[t].w1;
           } else if (open) {
-            acc_re = acc_re + rec[t].re;
-            acc_im = acc_im + rec[t].im;
+            acc.add(rec[t].re, rec[t].im);
             diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
           }
           const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
           if (open && ends) {
-            stage_out<G, WT, T, RB>(st, nw, gl, sid[t] - sfirst, first, acc_re, acc_im);
+            emit(sid[t] - sfirst, p0 + t_head, p0 + t + 1);
             open = false;
           }
         }
@@ -960,13 +992,12 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
               is_long = true;
               break;
             }
-            const Rec<G, T> r = load_rec<G, WT, T>(op, E.vals[lo + q], gl);
-            acc_re = acc_re + r.re;
-            acc_im = acc_im + r.im;
+            const Rec<G, TV> r = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
+            acc.add(r.re, r.im);
             diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
             ++q;
           }
-          if (!is_long) stage_out<G, WT, T, RB>(st, nw, gl, s_cur - sfirst, first, acc_re, acc_im);
+          if (!is_long) emit(s_cur - sfirst, p0 + t_head, q);
         }
         // an equal key must be an equal string
 #pragma unroll
@@ -995,7 +1026,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
       for (uint32_t kk = static_cast<uint32_t>(lane); kk < cnt; kk += 64)
         if (st.valid[kk]) {
           E.Oph[ob + kk] = 0;
-          static_cast<cplx<T>*>(E.Oc)[ob + kk] = st.c[kk];
+          static_cast<cplx<TV>*>(E.Oc)[ob + kk] = st.c[kk];
           E.Ofp[ob + kk] = st.fp[kk];
         }
       wave_sync();  // the stage is reused by the next chunk
@@ -1003,9 +1034,9 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
   }
 }
 
-template <int G, typename T>
+template <int G, typename TO, typename TV>
 __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, int64_t o,
-                                          const Rec<G, T>& r, T re, T im) {
+                                          const Rec<G, TV>& r, TO re, TO im) {
   if (G == 1) {
     E.OX[o] = r.w0;
     E.OZ[o] = r.w1;
@@ -1018,19 +1049,23 @@ __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, i
   }
   if (gl == 0) {
     E.Oph[o] = 0;
-    static_cast<cplx<T>*>(E.Oc)[o] = cplx<T>{re, im};
+    static_cast<cplx<TO>*>(E.Oc)[o] = cplx<TO>{re, im};
     E.Ofp[o] = r.fp;
   }
 }
 
 // Segments longer than kLong: one block per segment; group g adds records
 // g, g + NG, ... in order, then the NG partial sums are added in group order.
-template <int G, int WT, typename T>
+// In the compensated form a cancelled segment is summed again the same way
+// in FP64.
+template <int G, int WT, typename T, int MODE>
 __global__ void __launch_bounds__(kB)
 k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ long_list,
               const uint32_t* __restrict__ nlong) {
+  using TV = typename std::conditional<MODE == kComp, float, T>::type;
   constexpr int NG = kB / G;
-  __shared__ T s_re[NG], s_im[NG];
+  __shared__ Acc<MODE, TV> s_acc[NG];
+  __shared__ double s_re[NG], s_im[NG];
   __shared__ uint32_t s_end;
   const int g = threadIdx.x / G, gl = threadIdx.x % G;
   const uint32_t L = *nlong;
@@ -1048,31 +1083,47 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
     }
     __syncthreads();
     const uint32_t q1 = s_end;
-    const Rec<G, T> first = load_rec<G, WT, T>(op, E.vals[lo + q0], gl);
-    T re = 0, im = 0;
+    const Rec<G, TV> first = load_rec<G, WT, T, TV>(op, E.vals[lo + q0], gl);
+    Acc<MODE, TV> acc;
+    acc.zero();
     uint64_t diff = 0;
     for (uint32_t q = q0 + g; q < q1; q += NG) {
-      const Rec<G, T> r = load_rec<G, WT, T>(op, E.vals[lo + q], gl);
-      re = re + r.re;
-      im = im + r.im;
+      const Rec<G, TV> r = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
+      acc.add(r.re, r.im);
       diff |= (r.w0 ^ first.w0) | (r.w1 ^ first.w1);
     }
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
     if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
-    if (gl == 0) {
-      s_re[g] = re;
-      s_im[g] = im;
-    }
+    if (gl == 0) s_acc[g] = acc;
     __syncthreads();
-    if (threadIdx.x < G) {
-      T tr = 0, ti = 0;
+    // every thread forms the same total, so the branch below is uniform
+    Acc<MODE, TV> tot;
+    tot.zero();
+    for (int h = 0; h < NG; ++h) tot.add(s_acc[h]);
+    TV vr = tot.value_re(), vi = tot.value_im();
+    if (MODE == kComp && tot.cancels(E.tau)) {
+      double re = 0.0, im = 0.0;
+      for (uint32_t q = q0 + g; q < q1; q += NG) {
+        const Rec<G, double> r = load_rec<G, WT, T, double>(op, E.vals[lo + q], gl);
+        re = re + r.re;
+        im = im + r.im;
+      }
+      if (gl == 0) {
+        s_re[g] = re;
+        s_im[g] = im;
+      }
+      __syncthreads();
+      double tr = 0.0, ti = 0.0;
       for (int h = 0; h < NG; ++h) {
         tr = tr + s_re[h];
         ti = ti + s_im[h];
       }
-      write_out<G, T>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, tr, ti);
+      vr = static_cast<TV>(tr);
+      vi = static_cast<TV>(ti);
     }
+    if (threadIdx.x < G)
+      write_out<G, TV, TV>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, vr, vi);
     __syncthreads();
   }
 }
@@ -1128,8 +1179,9 @@ void prep_side(const paulisum* t, int Wp, int kb, int d1, SidePrep<T>& P, hipStr
   PAULI_HIP(hipGetLastError());
 }
 
-template <int G, int WT, typename T>
+template <int G, int WT, typename T, int MODE>
 paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  using TV = typename std::conditional<MODE == kComp, float, T>::type;
   const int W = a->W;
   const int Wp = G;  // G == 1 iff W == 1; otherwise the next power of two >= W
   const uint32_t P = static_cast<uint32_t>(a->m * b->m);
@@ -1240,17 +1292,18 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   PAULI_HIP(hipStreamSynchronize(s));
   const uint32_t U = host[3];
 
-  paulisum* out = new_sum(a->n, U, U, a->dtype, s);
+  paulisum* out = new_sum(a->n, U, U, MODE == kComp ? PAULI_C64 : a->dtype, s);
   ExpandArgs E{boff.as<uint32_t>(), V, segidx.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
-               ctr32 + 2, out->X, out->Z, out->ph, out->coef, out->fp, out->ld};
+               ctr32 + 2, out->X, out->Z, out->ph, out->coef, out->fp, out->ld, o.tau};
   Operands<WT, T> op{A.rows.template as<uint64_t>(), Bs.rows.template as<uint64_t>(),
                      A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
                      static_cast<uint32_t>(a->m), ibits, W};
   {
     StageScope sc(PAULI_STAGE_WRITE, s,
-                  U * (16.0 * W + sizeof(cplx<T>) + 1 + 8) + P * 8.0);
-    hipLaunchKernelGGL((k_expand<G, WT, T>), dim3(grid_for(nbk, 1, 4096)), dim3(kB), 0, s, E, op);
-    hipLaunchKernelGGL((k_expand_long<G, WT, T>), dim3(256), dim3(kB), 0, s, E, op,
+                  U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + P * 8.0);
+    hipLaunchKernelGGL((k_expand<G, WT, T, MODE>), dim3(grid_for(nbk, 1, 4096)), dim3(kB), 0, s, E,
+                       op);
+    hipLaunchKernelGGL((k_expand_long<G, WT, T, MODE>), dim3(256), dim3(kB), 0, s, E, op,
                        long_list.as<uint32_t>(), ctr32 + 1);
     PAULI_HIP(hipGetLastError());
   }
@@ -1263,27 +1316,42 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   return out;
 }
 
-template <typename T>
+template <typename T, int MODE>
 paulisum* fused_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
   switch (a->W) {
-    case 1: return fused_t<1, 1, T>(a, b, o, s);
-    case 2: return fused_t<2, 2, T>(a, b, o, s);
-    case 3: return fused_t<4, 3, T>(a, b, o, s);
-    case 4: return fused_t<4, 4, T>(a, b, o, s);
-    case 5: return fused_t<8, 5, T>(a, b, o, s);
-    case 6: return fused_t<8, 6, T>(a, b, o, s);
-    case 7: return fused_t<8, 7, T>(a, b, o, s);
-    case 8: return fused_t<8, 8, T>(a, b, o, s);
-    default: return fused_t<16, kMaxWords, T>(a, b, o, s);
+    case 1: return fused_t<1, 1, T, MODE>(a, b, o, s);
+    case 2: return fused_t<2, 2, T, MODE>(a, b, o, s);
+    case 3: return fused_t<4, 3, T, MODE>(a, b, o, s);
+    case 4: return fused_t<4, 4, T, MODE>(a, b, o, s);
+    case 5: return fused_t<8, 5, T, MODE>(a, b, o, s);
+    case 6: return fused_t<8, 6, T, MODE>(a, b, o, s);
+    case 7: return fused_t<8, 7, T, MODE>(a, b, o, s);
+    case 8: return fused_t<8, 8, T, MODE>(a, b, o, s);
+    default: return fused_t<16, kMaxWords, T, MODE>(a, b, o, s);
   }
 }
 
 }  // namespace
 
 paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
-  if (o.drop_abs >= 0.0) return nullptr;  // drop thresholds use the general path
-  if (a->dtype == PAULI_C128) return fused_w<double>(a, b, o, s);
-  return fused_w<float>(a, b, o, s);
+  paulisum* r;
+  if (o.mode == PAULI_MERGE_COMPENSATED)
+    r = a->dtype == PAULI_C128 ? fused_w<double, kComp>(a, b, o, s) : fused_w<float, kComp>(a, b, o, s);
+  else
+    r = a->dtype == PAULI_C128 ? fused_w<double, kPlain>(a, b, o, s)
+                               : fused_w<float, kPlain>(a, b, o, s);
+  if (r && o.drop_abs >= 0.0) {
+    paulisum* kept = nullptr;
+    try {
+      kept = drop_terms(r, o.drop_abs, s);
+    } catch (...) {
+      free_sum(r);
+      throw;
+    }
+    free_sum(r);
+    r = kept;
+  }
+  return r;
 }
 
 }  // namespace pauli

@@ -18,6 +18,7 @@
 // The same pipeline serves a materialised sum (term source) and the fused
 // outer product (pair source, no product is ever stored).
 #include <memory>
+#include <type_traits>
 
 #include "common.h"
 #include "internal.h"
@@ -63,17 +64,17 @@ __global__ void k_term_records(const uint64_t* __restrict__ f, int64_t m, int ks
 // head[r] in {0, 1}; v[r] = value of record r; *dirty |= 1 when a key run
 // holds more than one string.  second_pass: only run if *dirty, and do not
 // raise it again.
-template <int WT, typename T, typename Src>
+template <int WT, typename TV, typename Src>
 __global__ void __launch_bounds__(kBlock)
 k_heads(Src src, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t N,
-        uint32_t* __restrict__ head, cplx<T>* __restrict__ v, uint32_t* __restrict__ dirty,
+        uint32_t* __restrict__ head, cplx<TV>* __restrict__ v, uint32_t* __restrict__ dirty,
         int second_pass) {
   if (second_pass && *dirty == 0) return;
   uint64_t w[2 * WT], pw[2 * WT];
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
        r += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t id = vals[r];
-    v[r] = src.term(id, w);
+    v[r] = src.template term<TV>(id, w);
     uint32_t h = 1;
     if (r > 0 && keys[r] == keys[r - 1]) {
       src.string(vals[r - 1], pw);
@@ -148,12 +149,21 @@ __device__ __forceinline__ bool keep_value(cplx<T> c, double drop2) {
   return !(re * re + im * im < drop2);
 }
 
-// Short segments: one thread adds its records in order.
-template <typename T>
-__global__ void k_seg_reduce(const cplx<T>* __restrict__ v, const uint32_t* __restrict__ seg_start,
-                             const uint32_t* __restrict__ nseg, cplx<T>* __restrict__ coef,
+// FP64 value of record r (the re-merge of a cancelled segment).
+template <int WT, typename Src>
+__device__ __forceinline__ cplx<double> value64(const Src& src, uint32_t id) {
+  uint64_t w[2 * WT];
+  return src.template term<double>(id, w);
+}
+
+// Short segments: one thread adds its records in order.  In the compensated
+// form a cancelled segment is added again in FP64 from the source.
+template <int WT, typename TV, int MODE, typename Src>
+__global__ void k_seg_reduce(Src src, const uint32_t* __restrict__ vals,
+                             const cplx<TV>* __restrict__ v, const uint32_t* __restrict__ seg_start,
+                             const uint32_t* __restrict__ nseg, cplx<TV>* __restrict__ coef,
                              uint32_t* __restrict__ keep, uint32_t* __restrict__ long_list,
-                             uint32_t* __restrict__ nlong, double drop2) {
+                             uint32_t* __restrict__ nlong, double drop2, double tau) {
   const uint32_t U = *nseg;
   for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < U;
        u += (int64_t)gridDim.x * blockDim.x) {
@@ -162,45 +172,66 @@ __global__ void k_seg_reduce(const cplx<T>* __restrict__ v, const uint32_t* __re
       long_list[atomicAdd(nlong, 1u)] = static_cast<uint32_t>(u);
       continue;
     }
-    cplx<T> acc = v[s0];
-    for (uint32_t r = s0 + 1; r < s1; ++r) {
-      acc.re += v[r].re;
-      acc.im += v[r].im;
+    Acc<MODE, TV> acc;
+    acc.begin(v[s0].re, v[s0].im);
+    for (uint32_t r = s0 + 1; r < s1; ++r) acc.add(v[r].re, v[r].im);
+    cplx<TV> c{acc.value_re(), acc.value_im()};
+    if (MODE == kComp && acc.cancels(tau)) {
+      double re = 0.0, im = 0.0;
+      for (uint32_t r = s0; r < s1; ++r) {
+        const cplx<double> x = value64<WT>(src, vals[r]);
+        re = re + x.re;
+        im = im + x.im;
+      }
+      c = cplx<TV>{static_cast<TV>(re), static_cast<TV>(im)};
     }
-    coef[u] = acc;
-    keep[u] = keep_value(acc, drop2) ? 1u : 0u;
+    coef[u] = c;
+    keep[u] = keep_value(c, drop2) ? 1u : 0u;
   }
 }
 
 // Long segments: one block each; thread t adds records t, t+256, ... in
-// order, then a fixed pairwise tree combines the 256 partial sums.
-template <typename T>
+// order, then the 256 partial sums are added in thread order (the same in
+// every thread, so the re-merge decision is uniform over the block).
+template <int WT, typename TV, int MODE, typename Src>
 __global__ void __launch_bounds__(kBlock)
-k_seg_reduce_long(const cplx<T>* __restrict__ v, const uint32_t* __restrict__ seg_start,
-                  const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ nlong,
-                  cplx<T>* __restrict__ coef, uint32_t* __restrict__ keep, double drop2) {
-  __shared__ T s_re[kBlock], s_im[kBlock];
+k_seg_reduce_long(Src src, const uint32_t* __restrict__ vals, const cplx<TV>* __restrict__ v,
+                  const uint32_t* __restrict__ seg_start, const uint32_t* __restrict__ long_list,
+                  const uint32_t* __restrict__ nlong, cplx<TV>* __restrict__ coef,
+                  uint32_t* __restrict__ keep, double drop2, double tau) {
+  __shared__ Acc<MODE, TV> s_acc[kBlock];
+  __shared__ double s_re[kBlock], s_im[kBlock];
   const uint32_t L = *nlong;
   for (uint32_t b = blockIdx.x; b < L; b += gridDim.x) {
     const uint32_t u = long_list[b];
     const uint32_t s0 = seg_start[u], s1 = seg_start[u + 1];
-    T re = 0, im = 0;
-    for (uint32_t r = s0 + threadIdx.x; r < s1; r += kBlock) {
-      re += v[r].re;
-      im += v[r].im;
-    }
-    s_re[threadIdx.x] = re;
-    s_im[threadIdx.x] = im;
+    Acc<MODE, TV> acc;
+    acc.zero();
+    for (uint32_t r = s0 + threadIdx.x; r < s1; r += kBlock) acc.add(v[r].re, v[r].im);
+    s_acc[threadIdx.x] = acc;
     __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-      if (threadIdx.x < h) {
-        s_re[threadIdx.x] += s_re[threadIdx.x + h];
-        s_im[threadIdx.x] += s_im[threadIdx.x + h];
+    Acc<MODE, TV> tot;
+    tot.zero();
+    for (int h = 0; h < kBlock; ++h) tot.add(s_acc[h]);
+    cplx<TV> c{tot.value_re(), tot.value_im()};
+    if (MODE == kComp && tot.cancels(tau)) {
+      double re = 0.0, im = 0.0;
+      for (uint32_t r = s0 + threadIdx.x; r < s1; r += kBlock) {
+        const cplx<double> x = value64<WT>(src, vals[r]);
+        re = re + x.re;
+        im = im + x.im;
       }
+      s_re[threadIdx.x] = re;
+      s_im[threadIdx.x] = im;
       __syncthreads();
+      double tr = 0.0, ti = 0.0;
+      for (int h = 0; h < kBlock; ++h) {
+        tr = tr + s_re[h];
+        ti = ti + s_im[h];
+      }
+      c = cplx<TV>{static_cast<TV>(tr), static_cast<TV>(ti)};
     }
     if (threadIdx.x == 0) {
-      cplx<T> c{s_re[0], s_im[0]};
       coef[u] = c;
       keep[u] = keep_value(c, drop2) ? 1u : 0u;
     }
@@ -237,9 +268,11 @@ k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __res
 
 // -------------------------------------------------------------- pipeline
 
-template <int WT, typename T, typename Src>
+template <int WT, typename T, int MODE, typename Src>
 paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf& keys_buf,
                        DBuf& vals_buf, const MergeArgs& o, hipStream_t s) {
+  using TV = typename std::conditional<MODE == kComp, float, T>::type;
+  if (MODE == kComp) dt = PAULI_C64;
   uint64_t* keys = keys_buf.as<uint64_t>();
   uint32_t* vals = vals_buf.as<uint32_t>();
   DBuf keys_alt(N * sizeof(uint64_t), s), vals_alt(N * sizeof(uint32_t), s);
@@ -256,19 +289,19 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf&
   uint32_t* ctr = ctr_buf.as<uint32_t>();
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ctr, 16);
   DBuf head_buf(N * sizeof(uint32_t), s), segid_buf(N * sizeof(uint32_t), s);
-  DBuf v_buf(N * sizeof(cplx<T>), s);
+  DBuf v_buf(N * sizeof(cplx<TV>), s);
   uint32_t* head = head_buf.as<uint32_t>();
   uint32_t* segid = segid_buf.as<uint32_t>();
-  cplx<T>* v = v_buf.as<cplx<T>>();
+  cplx<TV>* v = v_buf.as<cplx<TV>>();
 
   const unsigned g = grid_for(N);
   auto sc_seg = std::make_unique<StageScope>(PAULI_STAGE_SEGMENT, s,
-                                             N * (12.0 + 4.0 + sizeof(cplx<T>)));
-  hipLaunchKernelGGL((k_heads<WT, T, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
+                                             N * (12.0 + 4.0 + sizeof(cplx<TV>)));
+  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
                      v, ctr + 0, 0);
   hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, head, N,
                      ctr + 0);
-  hipLaunchKernelGGL((k_heads<WT, T, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
+  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
                      v, ctr + 0, 1);
   PAULI_HIP(hipGetLastError());
 
@@ -279,16 +312,16 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf&
   hipLaunchKernelGGL(k_seg_starts, dim3(g), dim3(kBlock), 0, s, head, segid, N, ctr + 1, seg_start);
   head_buf.reset();
 
-  DBuf coef_buf(N * sizeof(cplx<T>), s);
-  cplx<T>* coef = coef_buf.as<cplx<T>>();
+  DBuf coef_buf(N * sizeof(cplx<TV>), s);
+  cplx<TV>* coef = coef_buf.as<cplx<TV>>();
   uint32_t* keep = segid;  // segid is dead after k_seg_starts
   DBuf long_buf(N * sizeof(uint32_t), s);
   uint32_t* long_list = long_buf.as<uint32_t>();
   const double drop2 = o.drop_abs < 0.0 ? -1.0 : o.drop_abs * o.drop_abs;
-  hipLaunchKernelGGL((k_seg_reduce<T>), dim3(g), dim3(kBlock), 0, s, v, seg_start, ctr + 1, coef,
-                     keep, long_list, ctr + 3, drop2);
-  hipLaunchKernelGGL((k_seg_reduce_long<T>), dim3(1024), dim3(kBlock), 0, s, v, seg_start,
-                     long_list, ctr + 3, coef, keep, drop2);
+  hipLaunchKernelGGL((k_seg_reduce<WT, TV, MODE, Src>), dim3(g), dim3(kBlock), 0, s, src, vals, v,
+                     seg_start, ctr + 1, coef, keep, long_list, ctr + 3, drop2, o.tau);
+  hipLaunchKernelGGL((k_seg_reduce_long<WT, TV, MODE, Src>), dim3(1024), dim3(kBlock), 0, s, src,
+                     vals, v, seg_start, long_list, ctr + 3, coef, keep, drop2, o.tau);
   PAULI_HIP(hipGetLastError());
   sc_seg.reset();
   v_buf.reset();
@@ -309,10 +342,10 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf&
 
   paulisum* out = new_sum(n, U, U, dt, s);
   if (U > 0) {
-    StageScope sc_w(PAULI_STAGE_WRITE, s, U * (16.0 * src.nw + sizeof(cplx<T>) + 1 + 8));
-    hipLaunchKernelGGL((k_write_output<WT, T, Src>), dim3(grid_for(nseg)), dim3(kBlock), 0, s, src,
+    StageScope sc_w(PAULI_STAGE_WRITE, s, U * (16.0 * src.nw + sizeof(cplx<TV>) + 1 + 8));
+    hipLaunchKernelGGL((k_write_output<WT, TV, Src>), dim3(grid_for(nseg)), dim3(kBlock), 0, s, src,
                        vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z, out->ph,
-                       static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
+                       static_cast<cplx<TV>*>(out->coef), out->fp, out->ld);
     PAULI_HIP(hipGetLastError());
   }
   return out;
@@ -329,7 +362,9 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                        keys.as<uint64_t>(), vals.as<uint32_t>());
     PAULI_HIP(hipGetLastError());
     TermSrc<WT, T> src{a->X, a->Z, a->ph, static_cast<const cplx<T>*>(a->coef), a->fp, a->ld, a->W};
-    return run_pipeline<WT, T>(src, a->n, N, a->dtype, keys, vals, o, s);
+    return o.mode == PAULI_MERGE_COMPENSATED
+               ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s)
+               : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s);
   }
   const int64_t N = a->m * b->m;
   const int W = a->W;
@@ -346,7 +381,9 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   PairSrc<WT, T> src{ra.as<uint64_t>(), ea.as<uint8_t>(), static_cast<const cplx<T>*>(a->coef),
                      a->fp, rb.as<uint64_t>(), eb.as<uint8_t>(),
                      static_cast<const cplx<T>*>(b->coef), b->fp, static_cast<uint32_t>(a->m), W};
-  return run_pipeline<WT, T>(src, a->n, N, a->dtype, keys, vals, o, s);
+  return o.mode == PAULI_MERGE_COMPENSATED
+             ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s)
+             : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s);
 }
 
 template <typename T>
@@ -364,7 +401,66 @@ paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   }
 }
 
+template <typename T>
+__global__ void k_keep_flags(const cplx<T>* __restrict__ c, int64_t m, double drop2,
+                             uint32_t* __restrict__ keep) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x)
+    keep[t] = keep_value(c[t], drop2) ? 1u : 0u;
+}
+
+template <typename T>
+__global__ void k_gather_kept(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
+                              const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
+                              const uint64_t* __restrict__ fp, int W, int64_t m, int64_t ld,
+                              const uint32_t* __restrict__ keep, const uint32_t* __restrict__ idx,
+                              uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
+                              uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc,
+                              uint64_t* __restrict__ Ofp, int64_t ldo) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (!keep[t]) continue;
+    const int64_t o = idx[t];
+    for (int w = 0; w < W; ++w) {
+      OX[w * ldo + o] = X[w * ld + t];
+      OZ[w * ldo + o] = Z[w * ld + t];
+    }
+    Oph[o] = ph[t];
+    Oc[o] = c[t];
+    Ofp[o] = fp[t];
+  }
+}
+
+template <typename T>
+paulisum* drop_t(const paulisum* a, double drop_abs, hipStream_t s) {
+  const int64_t m = a->m;
+  DBuf keep((m + 1) * 4, s), idx((m + 1) * 4, s), tot(4, s);
+  DBuf work(scan_workspace_bytes(m), s);
+  const unsigned g = grid_for(m);
+  hipLaunchKernelGGL(k_keep_flags<T>, dim3(g), dim3(kBlock), 0, s,
+                     static_cast<const cplx<T>*>(a->coef), m, drop_abs * drop_abs,
+                     keep.as<uint32_t>());
+  scan_exclusive_u32(keep.as<uint32_t>(), idx.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, s);
+  uint32_t kept = 0;
+  PAULI_HIP(hipMemcpyAsync(&kept, tot.p, 4, hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipStreamSynchronize(s));
+  paulisum* out = new_sum(a->n, kept, kept, a->dtype, s);
+  if (kept > 0)
+    hipLaunchKernelGGL(k_gather_kept<T>, dim3(g), dim3(kBlock), 0, s, a->X, a->Z, a->ph,
+                       static_cast<const cplx<T>*>(a->coef), a->fp, a->W, m, a->ld,
+                       keep.as<uint32_t>(), idx.as<uint32_t>(), out->X, out->Z, out->ph,
+                       static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
+  PAULI_HIP(hipGetLastError());
+  return out;
+}
+
 }  // namespace
+
+paulisum* drop_terms(const paulisum* a, double drop_abs, hipStream_t s) {
+  if (a->m == 0) return new_sum(a->n, 0, 0, a->dtype, s);
+  if (a->dtype == PAULI_C128) return drop_t<double>(a, drop_abs, s);
+  return drop_t<float>(a, drop_abs, s);
+}
 
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
   if (a->dtype == PAULI_C128) return merge_w<double>(a, b, o, s);

@@ -36,8 +36,10 @@ struct PairSrc {
       w[q] = A[q] ^ B[q];
     }
   }
-  // Product string (into w) and value i^k * c_a * c_b.
-  __device__ __forceinline__ cplx<T> term(uint32_t id, uint64_t* w) const {
+  // Product string (into w) and value i^k * c_a * c_b, computed in TV from
+  // the coefficients rounded to TV.
+  template <typename TV = T>
+  __device__ __forceinline__ cplx<TV> term(uint32_t id, uint64_t* w) const {
     uint32_t i, j;
     split(id, i, j);
     const uint64_t* A = ra + (size_t)i * 2 * nw;
@@ -52,7 +54,9 @@ struct PairSrc {
       w[q] = x;
       w[nw + q] = z;
     }
-    return rot_ik(acc, cmul(ca[i], cb[j]));
+    const cplx<T> a = ca[i], b = cb[j];
+    return rot_ik(acc, cmul(cplx<TV>{static_cast<TV>(a.re), static_cast<TV>(a.im)},
+                            cplx<TV>{static_cast<TV>(b.re), static_cast<TV>(b.im)}));
   }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const {
     uint32_t i, j;
@@ -86,9 +90,11 @@ struct TermSrc {
       w[nw + q] = Z[q * ld + id];
     }
   }
-  __device__ __forceinline__ cplx<T> term(uint32_t id, uint64_t* w) const {
+  template <typename TV = T>
+  __device__ __forceinline__ cplx<TV> term(uint32_t id, uint64_t* w) const {
     string(id, w);
-    return rot_ik(ph[id], c[id]);
+    const cplx<T> v = c[id];
+    return rot_ik(ph[id], cplx<TV>{static_cast<TV>(v.re), static_cast<TV>(v.im)});
   }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const { return f[id]; }
 };

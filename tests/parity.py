@@ -110,3 +110,42 @@ def assert_sorted_by_key(gpu, key_bits=64):
            [gpu["z"][:, w] for w in range(W - 1, -1, -1)]
     order = np.lexsort(cols[::-1])
     assert np.array_equal(order, np.arange(len(key))), "merged output is not in key order"
+
+
+U32 = 2.0 ** -24
+
+
+def assert_compensated(gpu, ref, input_rounding=True):
+    """Bound check of the compensated FP32 form, string by string.
+
+    Each contribution carries the FP32 product error: the two inputs
+    rounded to FP32 (when they were FP64; relative u each) and the complex
+    product (sqrt(5) u, Brent, Percival and Zimmermann 2007), about 4.3 u of
+    its modulus.  Sum2 adds u |sum| plus a second-order term, and a
+    re-merged segment is FP64-accurate before its final rounding to FP32.
+    So |gpu - ref| <= 4.5 u A + 1.01 u |ref| + 1e-12 A for every string."""
+    gi, ri = align(gpu["x"], gpu["z"], ref.x, ref.z)
+    assert np.all(gpu["phase"] == 0)
+    assert gpu["coef"].dtype == np.complex64
+    g = gpu["coef"][gi].astype(np.complex128)
+    r = ref.coef[ri]
+    A = ref.mass[ri]
+    per_term = (4.5 if input_rounding else 2.5) * U32
+    tol = per_term * A + 1.01 * U32 * np.abs(r) + 1e-12 * A
+    err = np.abs(g - r)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, "compensated bound broken at %d strings, e.g. gpu %r oracle %r A %r" % (
+        bad.size, g[bad[:3]], r[bad[:3]], A[bad[:3]])
+
+
+def max_rel_err_after_drop(gpu, ref, drop_rel=1e-6):
+    """max |gpu - ref| / |ref| over strings with |ref| >= drop_rel * max |ref|
+    (the comparison of the cancellation case: both sides dropped below
+    drop_rel times the largest coefficient)."""
+    gi, ri = align(gpu["x"], gpu["z"], ref.x, ref.z)
+    g = gpu["coef"][gi].astype(np.complex128)
+    r = ref.coef[ri]
+    if r.size == 0:
+        return 0.0
+    sel = np.abs(r) >= drop_rel * np.max(np.abs(r))
+    return float(np.max(np.abs(g[sel] - r[sel]) / np.abs(r[sel])))
