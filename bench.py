@@ -1,15 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput of the fused Pauli-sum outer product + sort-and-combine.
+"""Throughput of the fused Pauli-sum outer product with sort-and-combine.
 
-One step = pauli_outer_product_merged on the n=500, 10,000 x 10,000
-Jordan-Wigner-shaped workload (1e8 products, complex128, plain FP64): every
-pair is multiplied (XOR of the X/Z words, phase from popcounts, coefficient
-product times i^k), the products are sorted on their fingerprint key and
-equal strings are combined.  Inputs are resident in HBM before timing starts;
-each step ends with the merged sum on the device.
+One step = pauli_outer_product_merged on the chosen workload.  The default is
+the n=500, 10,000 x 10,000 Jordan-Wigner-shaped sum product (1e8 products,
+complex128, plain FP64).  Every pair is multiplied: XOR of the X/Z words,
+phase from popcounts, coefficient product times i^k.  The products are then
+ordered by their fingerprint key and equal strings are combined.  Inputs are
+resident in HBM before timing starts, and each step ends with the merged sum
+on the device.
+
+The same steps are then run in the precision form: FP32 products,
+compensated merge, FP64 re-merge of cancelled segments.  Its largest
+relative coefficient error against the plain FP64 result of the same GPU is
+reported beside its throughput.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits with a
-message.
+message.  --copy-calibration runs a plain copy kernel of known size instead;
+its FETCH_SIZE / WRITE_SIZE counters scale the expand kernel's counters to
+bytes.
 """
 from __future__ import annotations
 
@@ -25,11 +33,21 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+COMP_TAU = 0.3         # cancellation threshold of the precision form
 WORKLOADS = {
-    1: "n=16, 2,000 x 2,000 weight-1..4 sums, complex128, plain FP64 (4e6 products)",
-    2: "n=500, 10,000 x 10,000 Jordan-Wigner-shaped sums, complex128, plain FP64 (1e8 products)",
-    3: "n=500, H*H with 20,000 Jordan-Wigner-shaped real terms, FP64 plain (4e8 products)",
+    1: "n=16, 2,000 x 2,000 weight-1..4 sums, complex128 (4e6 products)",
+    2: "n=500, 10,000 x 10,000 Jordan-Wigner-shaped sums, complex128 (1e8 products)",
+    3: "n=500, H*H with 20,000 Jordan-Wigner-shaped real terms, complex128 (4e8 products)",
 }
+# sources of the kernel each stage's traffic figure was measured on
+STAGE_SOURCES = {
+    "write": ["paper_2605_25974_amd/csrc/k_fused.hip", "paper_2605_25974_amd/csrc/common.h"],
+}
+COPY_BYTES = 2 << 30
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def _inputs(workload):
@@ -38,47 +56,41 @@ def _inputs(workload):
         return synth.workload1()
     if workload == 2:
         return synth.workload2()
-    if workload == 3:
-        H = synth.workload3()
-        return H, H
-    raise SystemExit("unknown workload %d" % workload)
+    H = synth.workload3()
+    return H, H
 
 
-def _traffic(stage, source_files):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current sources of the kernel."""
+def _sources_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def _traffic(stage, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current sources of the kernel and on this workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or stage not in STAGE_SOURCES:
         return None
     try:
         rec = json.load(open(path)).get(stage)
-    except Exception:
+    except (OSError, ValueError):
         return None
-    if not rec:
+    if not rec or rec.get("workload") != workload:
         return None
-    h = hashlib.sha256()
-    for f in source_files:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest():
+    if rec.get("source_sha256") != _sources_sha(STAGE_SOURCES[stage]):
         return None
     return rec.get("bytes_per_launch")
-
-
-STAGE_SOURCES = {
-    "bucket": ["paper_2605_25974_amd/csrc/k_bucket.hip", "paper_2605_25974_amd/csrc/common.h"],
-    "sort": ["paper_2605_25974_amd/csrc/k_sort.hip"],
-    "segment": ["paper_2605_25974_amd/csrc/k_merge.hip", "paper_2605_25974_amd/csrc/common.h"],
-    "outer_product": ["paper_2605_25974_amd/csrc/k_basic.hip", "paper_2605_25974_amd/csrc/common.h"],
-}
 
 
 def cpu_baseline(A, B, target_s=15.0):
     """The CPU oracle timed on a bounded block of the same pair space."""
     from oracle import oracle as O
     SA = O.Sum(A["n"], A["x"], A["z"], A["phase"], A["coef"])
-    SB = O.Sum(B["n"], B["x"], B["z"], B["phase"], B["coef"])
+    SB = SA if B is A else O.Sum(B["n"], B["x"], B["z"], B["phase"], B["coef"])
     mj = B["x"].shape[0]
-    rows = 4
+    rows = 2
     t = time.perf_counter()
     O.product_merge(SA, SB, i_range=(0, rows), j_range=(0, mj))
     dt = time.perf_counter() - t
@@ -87,8 +99,57 @@ def cpu_baseline(A, B, target_s=15.0):
     O.product_merge(SA, SB, i_range=(0, rows), j_range=(0, mj))
     dt = time.perf_counter() - t
     return {"value": rows * mj / dt, "unit": "products/s", "cores": 1, "kind": "oracle",
-            "sample": "%d x %d pair block (%d products) of the same workload, %.1f s, "
-                      "single thread" % (rows, mj, rows * mj, dt)}
+            "sample": "rows 0..%d of the left sum times all %d right terms (%d products) of "
+                      "the same workload, multiply and exact merge, %.1f s, one thread"
+                      % (rows - 1, mj, rows * mj, dt)}
+
+
+def _timed(pl, torch, GA, GB, steps, warmup, **kw):
+    for _ in range(warmup):
+        pl.outer_product_merged(GA, GB, **kw).destroy()
+    torch.cuda.synchronize()
+    pl.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U = 0
+    for _ in range(steps):
+        out = pl.outer_product_merged(GA, GB, **kw)
+        U = out.m
+        out.destroy()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = pl.profile_read()
+    pl.profile_enable(False)
+    return elapsed, U, stages
+
+
+def _rel_err(pl, torch, GA, GB, tau):
+    """Max relative error of the precision form against plain FP64 on this
+    GPU, over strings with |c| >= 1e-6 max |c| (both outputs hold the same
+    strings in the same order)."""
+    ref = pl.outer_product_merged(GA, GB).export_torch()
+    got = pl.outer_product_merged(GA, GB, mode=pl.COMPENSATED, tau=tau).export_torch()
+    for k in ("x", "z", "fp"):
+        if not torch.equal(ref[k], got[k]):
+            raise SystemExit("precision form produced different strings than plain FP64")
+    r = ref["coef"]
+    g = got["coef"].to(torch.complex128)
+    mag = r.abs()
+    sel = mag >= 1e-6 * mag.max()
+    return float(((g - r).abs()[sel] / mag[sel]).max())
+
+
+def copy_calibration(steps):
+    import torch
+    n = COPY_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel": "torch.mul(src, 1.0, out=dst), float32",
+                      "bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES,
+                      "launches": steps}), flush=True)
 
 
 def main():
@@ -98,13 +159,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compensated", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.steps)
+        return
 
     import torch
     import paper_2605_25974_amd as pl
@@ -114,27 +180,12 @@ def main():
     GA = pl.PauliSum.from_dict(A)
     GB = GA if B is A else pl.PauliSum.from_dict(B)
     P = A["x"].shape[0] * B["x"].shape[0]
+    _log("inputs resident: %d x %d terms, n=%d" % (A["x"].shape[0], B["x"].shape[0], A["n"]))
 
-    for _ in range(args.warmup):
-        out = pl.outer_product_merged(GA, GB)
-        out.destroy()
-    torch.cuda.synchronize()
-
-    pl.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    U = 0
-    for _ in range(args.steps):
-        out = pl.outer_product_merged(GA, GB)
-        U = out.m
-        out.destroy()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = pl.profile_read()
-    pl.profile_enable(False)
-
-    elapsed = t1 - t0
+    elapsed, U, stages = _timed(pl, torch, GA, GB, args.steps, args.warmup)
     ms_per_step = 1e3 * elapsed / args.steps
+    _log("plain FP64: %.3f ms/step" % ms_per_step)
+
     dom = max(stages, key=lambda k: stages[k][0]) if stages else None
     roof = None
     if dom:
@@ -142,8 +193,9 @@ def main():
         achieved = (by / launches) / (ms / launches * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": _traffic(dom, STAGE_SOURCES.get(dom, [])),
-                "kernel_stage": dom, "launch_ms": round(ms / launches, 4),
+                "traffic": _traffic(dom, args.workload),
+                "kernel": "k_expand" if dom == "write" else dom,
+                "stage": dom, "launch_ms": round(ms / launches, 4),
                 "algorithmic_bytes_per_launch": by / launches}
 
     rec = {
@@ -158,13 +210,27 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded generators standing in for the paper's random sums)",
+        "data": "synthetic (seeded generators of the workload's shape)",
         "config": {"workload": WORKLOADS[args.workload], "products": P, "merged_terms": U},
         "merged_terms_per_s": U * args.steps / elapsed,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "roofline": roof,
     }
+    if not args.no_compensated:
+        ce, cu, cst = _timed(pl, torch, GA, GB, args.steps, args.warmup,
+                             mode=pl.COMPENSATED, tau=COMP_TAU)
+        _log("precision form: %.3f ms/step" % (1e3 * ce / args.steps))
+        rec["compensated"] = {
+            "value": P * args.steps / ce, "unit": "products/s", "dtype": "f32 (compensated)",
+            "ms_per_step": round(1e3 * ce / args.steps, 4), "tau": COMP_TAU,
+            "merged_terms": cu,
+            "max_rel_err_vs_fp64": _rel_err(pl, torch, GA, GB, COMP_TAU),
+            "max_rel_err_vs_fp64_tau_1e-3": _rel_err(pl, torch, GA, GB, 1e-3),
+            "err_definition": "max |c32 - c64| / |c64| over strings with |c64| >= 1e-6 max|c64|",
+            "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in cst.items()},
+        }
     if not args.no_cpu_baseline:
+        _log("timing the CPU oracle")
         rec["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 

@@ -183,11 +183,11 @@ pauli_status_t pauli_set_memory_budget(uint64_t bytes);
  *   skipped).  Recording adds two event records per kernel launch. */
 typedef enum {
   PAULI_STAGE_OUTER_PRODUCT = 0, /* materialised product kernel */
-  PAULI_STAGE_PREP = 1,          /* operand preparation and record generation */
-  PAULI_STAGE_SORT = 2,          /* global radix passes */
-  PAULI_STAGE_SEGMENT = 3,       /* segment heads and segmented reduction */
-  PAULI_STAGE_WRITE = 4,         /* output of the merged terms */
-  PAULI_STAGE_BUCKET = 5,        /* fused partition-sort-merge kernel */
+  PAULI_STAGE_PREP = 1,          /* operand preparation */
+  PAULI_STAGE_SORT = 2,          /* record generation and radix / partition passes */
+  PAULI_STAGE_SEGMENT = 3,       /* bucket sorts, segment heads, segmented reduction */
+  PAULI_STAGE_WRITE = 4,         /* output of the merged terms (fused: the expand kernel) */
+  PAULI_STAGE_LONG = 5,          /* fused: long segments, drop compaction */
   PAULI_STAGE_COUNT = 6
 } pauli_stage_t;
 pauli_status_t pauli_profile_enable(int32_t on);

@@ -30,7 +30,7 @@ EXPORTS = (
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read",
 )
-STAGES = ("outer_product", "prep", "sort", "segment", "write", "bucket")
+STAGES = ("outer_product", "prep", "sort", "segment", "write", "long")
 
 
 class PauliLibraryMissing(RuntimeError):

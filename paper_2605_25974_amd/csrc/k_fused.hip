@@ -1015,19 +1015,23 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
       constexpr int kPer = RB <= 32 ? 2 : 1;
       const uint32_t k = RB <= 32 ? static_cast<uint32_t>(lane & 31) : static_cast<uint32_t>(lane);
       const int sub = RB <= 32 ? (lane >> 5) : 0;
+      // the output is not read again here: streaming stores keep it from
+      // evicting the operand rows out of L2
       for (int w0 = 0; w0 < nw; w0 += kPer) {
         const int w = w0 + sub;
         for (uint32_t kk = k; kk < cnt; kk += 64 / kPer)
           if (w < nw && st.valid[kk]) {
-            E.OX[w * E.ldo + ob + kk] = st.x[w][kk];
-            E.OZ[w * E.ldo + ob + kk] = st.z[w][kk];
+            __builtin_nontemporal_store(st.x[w][kk], &E.OX[w * E.ldo + ob + kk]);
+            __builtin_nontemporal_store(st.z[w][kk], &E.OZ[w * E.ldo + ob + kk]);
           }
       }
       for (uint32_t kk = static_cast<uint32_t>(lane); kk < cnt; kk += 64)
         if (st.valid[kk]) {
-          E.Oph[ob + kk] = 0;
-          static_cast<cplx<TV>*>(E.Oc)[ob + kk] = st.c[kk];
-          E.Ofp[ob + kk] = st.fp[kk];
+          __builtin_nontemporal_store(uint8_t(0), &E.Oph[ob + kk]);
+          TV* oc = reinterpret_cast<TV*>(static_cast<cplx<TV>*>(E.Oc) + ob + kk);
+          __builtin_nontemporal_store(st.c[kk].re, oc);
+          __builtin_nontemporal_store(st.c[kk].im, oc + 1);
+          __builtin_nontemporal_store(st.fp[kk], &E.Ofp[ob + kk]);
         }
       wave_sync();  // the stage is reused by the next chunk
     }
@@ -1303,6 +1307,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                   U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + P * 8.0);
     hipLaunchKernelGGL((k_expand<G, WT, T, MODE>), dim3(grid_for(nbk, 1, 4096)), dim3(kB), 0, s, E,
                        op);
+    PAULI_HIP(hipGetLastError());
+  }
+  {
+    StageScope sc(PAULI_STAGE_LONG, s, 0.0);
     hipLaunchKernelGGL((k_expand_long<G, WT, T, MODE>), dim3(256), dim3(kB), 0, s, E, op,
                        long_list.as<uint32_t>(), ctr32 + 1);
     PAULI_HIP(hipGetLastError());
@@ -1341,6 +1349,7 @@ paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o,
     r = a->dtype == PAULI_C128 ? fused_w<double, kPlain>(a, b, o, s)
                                : fused_w<float, kPlain>(a, b, o, s);
   if (r && o.drop_abs >= 0.0) {
+    StageScope sc(PAULI_STAGE_LONG, s, r->m * (16.0 * r->W + coef_bytes(r->dtype) + 9) * 2);
     paulisum* kept = nullptr;
     try {
       kept = drop_terms(r, o.drop_abs, s);
