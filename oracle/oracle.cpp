@@ -28,6 +28,13 @@
 //    exact cancellation gives exactly zero.
 //  * Truncation, Section III-B (non-Clifford paragraph): a merged term whose
 //    modulus is strictly below a threshold is removed.
+//  * Commutation, Section II-C: two strings anticommute when the number of
+//    qubits holding two different non-identity letters is odd.
+//  * Rotation step, Section II-D eq. (5): with R = cos(theta) I
+//    - i sin(theta) P, "product" mode left-multiplies every term by R;
+//    "conjugation" mode leaves a term Q that commutes with P unchanged and
+//    maps an anticommuting Q to cos(theta) Q - i sin(theta) PQ.  Each step is
+//    merged exactly, rounded, and truncated.
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared oracle.cpp
 // (contraction off so that the plain complex product matches a product
@@ -242,6 +249,15 @@ struct Sum {
   int phase(int64_t t) const { return ph ? (ph[t] & 3) : 0; }
 };
 
+// Section II-C: anticommute iff an odd number of qubits hold two different
+// non-identity letters.
+int anticommutes(const std::string& a, const std::string& b) {
+  int c = 0;
+  for (size_t q = 0; q < a.size(); ++q)
+    if (a[q] != I_ && b[q] != I_ && a[q] != b[q]) ++c;
+  return c & 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -339,6 +355,43 @@ void* oracle_product_merge(int n, int64_t m1, const uint64_t* x1, const uint64_t
     }
   }
   return finish(n, acc, drop_abs);
+}
+
+// A sequence of rotation steps (Section II-D eq. (5)) applied to the merged
+// input sum.  Step s uses the string (px, pz)[s] and angle theta[s]; mode 0
+// multiplies every term on the left by cos(theta) I - i sin(theta) P, mode 1
+// conjugates (commuting terms unchanged).  After each step equal strings are
+// combined exactly, rounded to double and truncated at drop_abs.  The mass
+// returned is that of the last step's contributions.
+void* oracle_propagate(int n, int64_t m, const uint64_t* x, const uint64_t* z, const uint8_t* ph,
+                       const double* c, int steps, const uint64_t* px, const uint64_t* pz,
+                       const double* theta, int mode, double drop_abs) {
+  const Sum S{n, m, x, z, ph, c};
+  const int W = words_for(n);
+  std::map<std::string, Acc> acc;
+  for (int64_t t = 0; t < m; ++t)
+    add_value(acc[S.letters(t)], S.phase(t), c[2 * t], c[2 * t + 1]);
+  Result* cur = finish(n, acc, -1.0);
+  std::string prod;
+  for (int st = 0; st < steps; ++st) {
+    const std::string P = decode(n, px + static_cast<size_t>(st) * W, pz + static_cast<size_t>(st) * W);
+    const double co = std::cos(theta[st]), si = std::sin(theta[st]);
+    std::map<std::string, Acc> next;
+    for (size_t u = 0; u < cur->keys.size(); ++u) {
+      const std::string& Q = cur->keys[u];
+      const double re = cur->coef[2 * u], im = cur->coef[2 * u + 1];
+      if (mode == 1 && !anticommutes(P, Q)) {
+        add_value(next[Q], 0, re, im);
+        continue;
+      }
+      add_product(next[Q], 0, re, im, co, 0.0);          // cos(theta) Q
+      const int k = multiply(P, Q, prod);                 // P Q = i^k (letters)
+      add_product(next[prod], k + 3, re, im, si, 0.0);    // -i sin(theta) P Q
+    }
+    delete cur;
+    cur = finish(n, next, drop_abs);
+  }
+  return cur;
 }
 
 int64_t oracle_result_size(void* h) {

@@ -72,6 +72,10 @@ def lib():
         L.oracle_product_coeff.restype = _int
         L.oracle_product_coeff.argtypes = (
             [_int] + [_i64, _u64p, _u64p, _u8p, _f64p] * 2 + [_i64, _u64p, _u64p, _f64p, _f64p, _i64p])
+        L.oracle_propagate.restype = ctypes.c_void_p
+        L.oracle_propagate.argtypes = (
+            [_int, _i64, _u64p, _u64p, _u8p, _f64p, _int, _u64p, _u64p, _f64p, _int,
+             ctypes.c_double])
         L.oracle_table_set.restype = None
         L.oracle_table_set.argtypes = [_int, _int, _int, _int]
         L.oracle_table_reset.restype = None
@@ -190,6 +194,25 @@ def product_merge(a: Sum, b: Sum, drop_abs: float = -1.0, i_range=None, j_range=
     j0, j1 = j_range if j_range is not None else (0, b.m)
     h = lib().oracle_product_merge(a.n, *a._args(), *b._args(), float(drop_abs), i0, i1, j0, j1)
     return _take(a.n, h)
+
+
+PRODUCT, CONJUGATE = 0, 1
+
+
+def propagate(s: Sum, px, pz, theta, mode=CONJUGATE, drop_abs: float = -1.0) -> Merged:
+    """Rotation steps of Section II-D eq. (5) on the merged sum s: step t uses
+    the string (px[t], pz[t]) (packed words, shape (steps, W)) and angle
+    theta[t].  mode PRODUCT multiplies every term on the left by
+    cos(theta) I - i sin(theta) P; CONJUGATE leaves terms commuting with P
+    unchanged.  Each step is merged exactly and truncated at drop_abs."""
+    W = _W(s.n)
+    px = np.ascontiguousarray(px, dtype=np.uint64).reshape(-1, W)
+    pz = np.ascontiguousarray(pz, dtype=np.uint64).reshape(-1, W)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+    assert px.shape[0] == pz.shape[0] == th.size
+    h = lib().oracle_propagate(s.n, *s._args(), int(th.size), _ptr(px, _u64p), _ptr(pz, _u64p),
+                               _ptr(th, _f64p), int(mode), float(drop_abs))
+    return _take(s.n, h)
 
 
 def product_coeff(a: Sum, b: Sum, xq, zq):
