@@ -161,6 +161,28 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
                                            const pauli_tune_t* tune, paulisum_t* out,
                                            void* stream);
 
+/* pauli_propagate: a sequence of Pauli rotations applied to a sum (Section
+ * II-D, eq. (5); Section III-B, truncation).  Step t uses the string
+ * P_t = (p_x[t], p_z[t]) (packed as in paulisum_create, W words each, host
+ * memory) and the angle theta[t] (host memory); R_t = cos(theta_t) I
+ * - i sin(theta_t) P_t.
+ *   PAULI_ROTATE_PRODUCT:   S <- merge(R_t * S), every term multiplied on
+ *                           the left (the fused outer product with the 2-term
+ *                           sum R_t).
+ *   PAULI_ROTATE_CONJUGATE: terms commuting with P_t are kept; each
+ *                           anticommuting term Q becomes
+ *                           cos(theta_t) Q - i sin(theta_t) P_t Q; then merge.
+ * Every step ends with the merge of opts (mode, drop_abs, ...), so a
+ * drop_abs >= 0 truncates after each step.  steps == 0 returns merge(s).
+ * s is not modified; *out is a new sum (C64 once a compensated step ran).
+ * Each step synchronises the stream once per size it has to learn.
+ * Errors: INVALID for a NULL argument, steps < 0, an unknown mode or a
+ * rotation string with bits at or above n. */
+typedef enum { PAULI_ROTATE_PRODUCT = 0, PAULI_ROTATE_CONJUGATE = 1 } pauli_rotate_mode_t;
+pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
+                               const uint64_t* p_z, const double* theta, int32_t rotate_mode,
+                               const pauli_merge_opts_t* opts, paulisum_t* out, void* stream);
+
 /* Replaces the device allocator used for every buffer the library makes
  * (NULL, NULL restores the default, hipMallocAsync / hipFreeAsync on the
  * call's stream).  alloc returns NULL on failure.  Not thread-safe with

@@ -28,7 +28,7 @@ EXPORTS = (
     "pauli_status_string", "pauli_last_error", "paulisum_create", "paulisum_destroy",
     "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
-    "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read",
+    "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
 )
 STAGES = ("outer_product", "prep", "sort", "segment", "write", "long")
 
@@ -99,6 +99,9 @@ def lib():
     L.pauli_outer_product_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
                                               ctypes.POINTER(_vp), ctypes.POINTER(MergeOpts),
                                               ctypes.POINTER(Tune), ctypes.POINTER(_vp), _vp]
+    L.pauli_propagate.restype = st
+    L.pauli_propagate.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32,
+                                  ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
     L.pauli_set_allocator.restype = st
     L.pauli_set_allocator.argtypes = [_vp, _vp, _vp]
     L.pauli_set_memory_budget.restype = st
@@ -273,6 +276,28 @@ def outer_product_merged(a: PauliSum, b: PauliSum, mode=PLAIN, drop_abs=-1.0, ta
     o = _opts(mode, drop_abs, tau, key_bits)
     _check(lib().pauli_outer_product_merged(a.handle, b.handle, ctypes.byref(o),
                                             ctypes.byref(out), _stream(stream)))
+    return PauliSum(out)
+
+
+ROTATE_PRODUCT, ROTATE_CONJUGATE = 0, 1
+
+
+def propagate(s: PauliSum, px, pz, theta, rotate_mode=ROTATE_CONJUGATE, mode=PLAIN,
+              drop_abs=-1.0, tau=0.0, key_bits=0, stream=None) -> PauliSum:
+    """Rotation steps R_t = cos(theta_t) I - i sin(theta_t) P_t applied to s
+    (pauli_propagate).  px, pz: (steps, W) packed words of the P_t; theta:
+    (steps,) angles.  Each step ends with merge and the drop_abs truncation."""
+    W = _words(s.info()[0])
+    px = np.ascontiguousarray(px, dtype=np.uint64).reshape(-1, W)
+    pz = np.ascontiguousarray(pz, dtype=np.uint64).reshape(-1, W)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+    if not (px.shape[0] == pz.shape[0] == th.size):
+        raise ValueError("px, pz and theta must have one entry per step")
+    o = _opts(mode, drop_abs, tau, key_bits)
+    out = _vp()
+    _check(lib().pauli_propagate(s.handle, int(th.size), px.ctypes.data, pz.ctypes.data,
+                                 th.ctypes.data, int(rotate_mode), ctypes.byref(o),
+                                 ctypes.byref(out), _stream(stream)))
     return PauliSum(out)
 
 

@@ -451,6 +451,47 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
   });
 }
 
+pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
+                               const uint64_t* p_z, const double* theta, int32_t rotate_mode,
+                               const pauli_merge_opts_t* opts, paulisum_t* out, void* stream) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_sum(s, "s");
+    if (steps < 0) fail(PAULI_ERR_INVALID, "steps is negative");
+    if (steps > 0 && (!p_x || !p_z || !theta))
+      fail(PAULI_ERR_INVALID, "p_x, p_z and theta must not be NULL");
+    if (rotate_mode != PAULI_ROTATE_PRODUCT && rotate_mode != PAULI_ROTATE_CONJUGATE)
+      fail(PAULI_ERR_INVALID, "unknown rotate_mode " + std::to_string(rotate_mode));
+    const int W = s->W;
+    const int tail = s->n - 64 * (W - 1);
+    const uint64_t pad = tail == 64 ? 0 : ~((uint64_t(1) << tail) - 1);
+    for (int32_t t = 0; t < steps; ++t)
+      if ((p_x[static_cast<size_t>(t) * W + W - 1] | p_z[static_cast<size_t>(t) * W + W - 1]) & pad)
+        fail(PAULI_ERR_INVALID, "rotation string " + std::to_string(t) + " has a bit at or above n");
+    const MergeArgs m = merge_args(opts);
+    use_device(s);
+    hipStream_t st = as_stream(stream);
+    s->last_stream = st;
+    if (steps == 0) {
+      *out = merge_generic(s, nullptr, m, st);
+      return;
+    }
+    paulisum* cur = s;
+    try {
+      for (int32_t t = 0; t < steps; ++t) {
+        paulisum* next = rotate_step(cur, p_x + static_cast<size_t>(t) * W,
+                                     p_z + static_cast<size_t>(t) * W, theta[t], rotate_mode, m, st);
+        if (cur != s) free_sum(cur);
+        cur = next;
+      }
+    } catch (...) {
+      if (cur != s) free_sum(cur);
+      throw;
+    }
+    *out = cur;
+  });
+}
+
 pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, void* ctx) {
   return guarded([&] {
     if ((alloc == nullptr) != (free_fn == nullptr))

@@ -136,6 +136,11 @@ paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o
 // their order, as a new container.
 paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st);
 
+// k_rotate.hip: one rotation step (product or conjugation semantics),
+// followed by the merge o.  px, pz: host words of the rotation string.
+paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
+                      int mode, const MergeArgs& o, hipStream_t st);
+
 // k_fused.hip: merge(a*b) by the staged fused pipeline; nullptr when a
 // fingerprint collision asks for merge_generic instead.
 paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);

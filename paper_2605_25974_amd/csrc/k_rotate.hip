@@ -1,0 +1,194 @@
+// Rotation steps of a Pauli-propagation loop (Section II-D, eq. (5)).
+//
+// R = cos(theta) I - i sin(theta) P.
+//   product mode:     S <- merge(R * S), the fused outer product of the
+//                     2-term sum R with S.
+//   conjugation mode: a term Q that commutes with P is kept; an
+//                     anticommuting Q becomes cos(theta) Q and
+//                     -i sin(theta) P Q.  The 1 or 2 terms per input term are
+//                     written by one streaming kernel, then merged.
+// Both end with the merge options' truncation.
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace pauli {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<unsigned>(g);
+}
+
+// The rotation string, passed by value.
+struct RotString {
+  uint64_t x[kMaxWords];
+  uint64_t z[kMaxWords];
+  uint64_t fp;
+  int W;
+  int y;  // |X & Z| of P
+};
+
+// cnt[t] = 1 + (term t anticommutes with P): the parity of the symplectic
+// product (Section III-F), sum over words of |X_t & Z_P| + |Z_t & X_P|.
+__global__ void k_rot_count(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
+                            int64_t ld, int64_t m, RotString P, uint32_t* __restrict__ cnt) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int s = 0;
+    for (int w = 0; w < P.W; ++w) s += popc64((X[w * ld + t] & P.z[w]) ^ (Z[w * ld + t] & P.x[w]));
+    cnt[t] = 1u + static_cast<uint32_t>(s & 1);
+  }
+}
+
+template <typename T>
+__global__ void k_rot_write(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
+                            const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
+                            const uint64_t* __restrict__ fp, int64_t ld, int64_t m, RotString P,
+                            T co, T si, const uint32_t* __restrict__ cnt,
+                            const uint32_t* __restrict__ off, uint64_t* __restrict__ OX,
+                            uint64_t* __restrict__ OZ, uint8_t* __restrict__ Oph,
+                            cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp, int64_t ldo) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = off[t];
+    const bool anti = cnt[t] == 2;
+    const cplx<T> v = c[t];
+    int k = P.y;  // phase of P * Q (P on the left), Section III-A
+    for (int w = 0; w < P.W; ++w) {
+      const uint64_t xq = X[w * ld + t], zq = Z[w * ld + t];
+      OX[w * ldo + o] = xq;
+      OZ[w * ldo + o] = zq;
+      if (anti) {
+        const uint64_t x3 = P.x[w] ^ xq, z3 = P.z[w] ^ zq;
+        k += popc64(xq & zq) + 2 * popc64(P.z[w] & xq) - popc64(x3 & z3);
+        OX[w * ldo + o + 1] = x3;
+        OZ[w * ldo + o + 1] = z3;
+      }
+    }
+    Oph[o] = ph[t];
+    Ofp[o] = fp[t];
+    Oc[o] = anti ? cplx<T>{v.re * co, v.im * co} : v;
+    if (anti) {
+      // -i sin(theta) i^k P Q: the factor -i = i^3 joins the phase exponent
+      Oph[o + 1] = static_cast<uint8_t>((ph[t] + k + 3) & 3);
+      Oc[o + 1] = cplx<T>{v.re * si, v.im * si};
+      Ofp[o + 1] = fp[t] ^ P.fp;
+    }
+  }
+}
+
+RotString rot_string(int n, const uint64_t* px, const uint64_t* pz) {
+  RotString P{};
+  P.W = words_for(n);
+  P.fp = 0;
+  P.y = 0;
+  for (int w = 0; w < P.W; ++w) {
+    P.x[w] = px[w];
+    P.z[w] = pz[w];
+    P.y += __builtin_popcountll(px[w] & pz[w]);
+    for (int b = 0; b < 64; ++b) {
+      if ((px[w] >> b) & 1) P.fp ^= fp_column(2 * (64 * w + b));
+      if ((pz[w] >> b) & 1) P.fp ^= fp_column(2 * (64 * w + b) + 1);
+    }
+  }
+  return P;
+}
+
+template <typename T>
+paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const MergeArgs& o,
+                      hipStream_t st) {
+  const int64_t m = s->m;
+  DBuf cnt((m + 1) * 4, st), off((m + 1) * 4, st), tot(4, st), work(scan_workspace_bytes(m), st);
+  const unsigned g = grid_for(m);
+  paulisum* mat = nullptr;
+  {
+    StageScope sc(PAULI_STAGE_PREP, st, m * (16.0 * s->W + 8));
+    hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, m, P,
+                       cnt.as<uint32_t>());
+    scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, st);
+    uint32_t M2 = 0;
+    PAULI_HIP(hipMemcpyAsync(&M2, tot.p, 4, hipMemcpyDeviceToHost, st));
+    PAULI_HIP(hipStreamSynchronize(st));
+    mat = new_sum(s->n, M2, M2, s->dtype, st);
+    hipLaunchKernelGGL(k_rot_write<T>, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ph,
+                       static_cast<const cplx<T>*>(s->coef), s->fp, s->ld, m, P,
+                       static_cast<T>(std::cos(theta)), static_cast<T>(std::sin(theta)),
+                       cnt.as<uint32_t>(), off.as<uint32_t>(), mat->X, mat->Z, mat->ph,
+                       static_cast<cplx<T>*>(mat->coef), mat->fp, mat->ld);
+    PAULI_HIP(hipGetLastError());
+  }
+  paulisum* r = nullptr;
+  try {
+    r = merge_generic(mat, nullptr, o, st);
+  } catch (...) {
+    free_sum(mat);
+    throw;
+  }
+  free_sum(mat);
+  return r;
+}
+
+// The 2-term sum cos(theta) I - i sin(theta) P in the dtype of s.
+paulisum* rotation_sum(const paulisum* s, const RotString& P, double theta, hipStream_t st) {
+  const int W = s->W;
+  paulisum* R = new_sum(s->n, 2, 2, s->dtype, st);
+  std::vector<uint64_t> words(4 * W, 0);  // X[w][2], then Z[w][2]
+  for (int w = 0; w < W; ++w) {
+    words[2 * w + 1] = P.x[w];
+    words[2 * W + 2 * w + 1] = P.z[w];
+  }
+  const uint8_t ph[2] = {0, 0};
+  const uint64_t fps[2] = {0, P.fp};
+  const double co = std::cos(theta), si = std::sin(theta);
+  double c128[4] = {co, 0.0, 0.0, -si};
+  float c64[4] = {static_cast<float>(co), 0.0f, 0.0f, static_cast<float>(-si)};
+  try {
+    // R->ld == 2: word w of term t is X[w * 2 + t]
+    PAULI_HIP(hipMemcpyAsync(R->X, words.data(), 2 * W * 8, hipMemcpyHostToDevice, st));
+    PAULI_HIP(hipMemcpyAsync(R->Z, words.data() + 2 * W, 2 * W * 8, hipMemcpyHostToDevice, st));
+    PAULI_HIP(hipMemcpyAsync(R->ph, ph, 2, hipMemcpyHostToDevice, st));
+    PAULI_HIP(hipMemcpyAsync(R->fp, fps, 16, hipMemcpyHostToDevice, st));
+    if (s->dtype == PAULI_C128)
+      PAULI_HIP(hipMemcpyAsync(R->coef, c128, sizeof(c128), hipMemcpyHostToDevice, st));
+    else
+      PAULI_HIP(hipMemcpyAsync(R->coef, c64, sizeof(c64), hipMemcpyHostToDevice, st));
+    PAULI_HIP(hipStreamSynchronize(st));  // the host staging arrays go out of scope
+  } catch (...) {
+    free_sum(R);
+    throw;
+  }
+  return R;
+}
+
+}  // namespace
+
+paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
+                      int mode, const MergeArgs& o, hipStream_t st) {
+  const RotString P = rot_string(s->n, px, pz);
+  if (mode == PAULI_ROTATE_CONJUGATE) {
+    if (s->m == 0) return merge_generic(s, nullptr, o, st);
+    return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, st)
+                                  : conjugate_t<float>(s, P, theta, o, st);
+  }
+  paulisum* R = rotation_sum(s, P, theta, st);
+  paulisum* r = nullptr;
+  try {
+    if (s->m > 0) r = fused_bucket(R, s, o, st);
+    if (!r) r = merge_generic(R, s, o, st);
+  } catch (...) {
+    free_sum(R);
+    throw;
+  }
+  free_sum(R);
+  return r;
+}
+
+}  // namespace pauli

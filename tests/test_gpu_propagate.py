@@ -1,0 +1,97 @@
+"""Rotation steps of the propagation loop (pauli_propagate) against the CPU
+oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import paper_2605_25974_amd as pl
+import synth
+from oracle import oracle as O
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _osum(d):
+    return O.Sum(d["n"], d["x"], d["z"], d.get("phase"), d["coef"])
+
+
+def _state(m, n=500):
+    return synth.workload5_state(m=m, n=n)
+
+
+def _rots(steps, n=500):
+    th, x, z = synth.workload5_rotations(steps=steps, n=n)
+    return th, x, z
+
+
+def _no_band(ref_full, thr):
+    return not np.any(np.abs(np.abs(ref_full.coef) - thr) <= 1e-9 * thr)
+
+
+@pytest.mark.parametrize("rot_mode,steps", [(pl.ROTATE_CONJUGATE, 8), (pl.ROTATE_PRODUCT, 4)])
+def test_propagate_fp64_matches_oracle(rot_mode, steps):
+    S = _state(3000)
+    th, x, z = _rots(steps)
+    thr = 1e-10
+    g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, rotate_mode=rot_mode,
+                     drop_abs=thr).export()
+    ref = O.propagate(_osum(S), x, z, th, mode=rot_mode, drop_abs=thr)
+    assert _no_band(ref, thr)
+    parity.assert_merged_fp64(g, ref)
+    parity.assert_sorted_by_key(g)
+    if rot_mode == pl.ROTATE_PRODUCT:
+        assert g["x"].shape[0] > 2 ** (steps - 1) * 3000 // 2  # the literal step doubles the sum
+
+
+def test_propagate_compensated():
+    S = _state(3000)
+    th, x, z = _rots(8)
+    g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, mode=pl.COMPENSATED,
+                     drop_abs=1e-10).export()
+    ref = O.propagate(_osum(S), x, z, th, mode=O.CONJUGATE, drop_abs=1e-10)
+    assert g["coef"].dtype == np.complex64
+    err = parity.max_rel_err_after_drop(g, ref)
+    print("8 conjugation steps, compensated: max rel err %.3e" % err)
+    assert err <= 1e-5
+
+
+def test_propagate_edge_cases():
+    n = 70
+    S = synth.random_sum(synth.rng_for(730), n, 400, wmax=5)
+    G = pl.PauliSum.from_dict(S)
+    W = 2
+    # no steps: the merged input
+    g0 = pl.propagate(G, np.zeros((0, W)), np.zeros((0, W)), []).export()
+    parity.assert_merged_fp64(g0, O.merge(_osum(S)))
+    # identity generator: everything commutes; the product mode scales by
+    # cos(theta) - i sin(theta)
+    zx = np.zeros((1, W), np.uint64)
+    for rm in (pl.ROTATE_CONJUGATE, pl.ROTATE_PRODUCT):
+        g = pl.propagate(G, zx, zx, [0.9], rotate_mode=rm).export()
+        parity.assert_merged_fp64(g, O.propagate(_osum(S), zx, zx, [0.9], mode=rm))
+    # an empty sum stays empty
+    E = {"n": n, "x": np.zeros((0, W), np.uint64), "z": np.zeros((0, W), np.uint64),
+         "phase": np.zeros(0, np.uint8), "coef": np.zeros(0, np.complex128)}
+    px = np.zeros((1, W), np.uint64)
+    px[0, 0] = 5
+    for rm in (pl.ROTATE_CONJUGATE, pl.ROTATE_PRODUCT):
+        assert pl.propagate(pl.PauliSum.from_dict(E), px, px, [0.3], rotate_mode=rm).m == 0
+    # a generator with a bit at or above n is rejected
+    bad = np.zeros((1, W), np.uint64)
+    bad[0, 1] = np.uint64(1) << np.uint64(10)   # qubit 74 >= 70
+    with pytest.raises(pl.PauliError) as e:
+        pl.propagate(G, bad, zx, [0.3])
+    assert e.value.status == "INVALID"
+
+
+def test_propagate_small_n_many_merges():
+    """n = 4: only 256 strings exist, so every step merges heavily."""
+    n = 4
+    S = synth.random_sum(synth.rng_for(731), n, 60, wmax=4)
+    rng = synth.rng_for(732)
+    steps = 10
+    x, z = synth.random_weight(rng, n, steps, 1, 3)
+    th = rng.uniform(0, np.pi, steps)
+    for rm in (pl.ROTATE_CONJUGATE, pl.ROTATE_PRODUCT):
+        g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, rotate_mode=rm).export()
+        parity.assert_merged_fp64(g, O.propagate(_osum(S), x, z, th, mode=rm))
