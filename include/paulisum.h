@@ -75,12 +75,15 @@ typedef struct {
   int32_t key_bits;
 } pauli_merge_opts_t;
 
-/* Launch-shape parameters (0 = library default / tuned value). */
+/* Launch-shape parameters of the fused pipeline (0 = tuned or default).
+ *  bucket_bits  the records of a product are split into 2^bucket_bits
+ *               buckets by the top bits of their key, and each bucket is
+ *               sorted in LDS (about |a||b| / 2^bucket_bits records each);
+ *               1..16.
+ *  reserved     must be 0. */
 typedef struct {
-  int32_t tile_i;          /* left terms per work tile */
-  int32_t tile_j;          /* right terms per work tile */
-  int32_t words_per_thread;
-  int32_t radix_bits;      /* digit width of the radix passes */
+  int32_t bucket_bits;
+  int32_t reserved[3];
 } pauli_tune_t;
 
 /* Text of a status code (static storage). */
@@ -154,8 +157,13 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
                                           void* stream);
 
 /* pauli_outer_product_batched: nb independent fused products
- * out[t] = merge(a[t] * b[t]); the pairs may differ in qubit count and term
- * counts but a[t], b[t] must agree with each other.  tune may be NULL. */
+ * out[t] = merge(a[t] * b[t]) with one set of merge options; the pairs may
+ * differ in qubit count and term counts but a[t], b[t] must agree with each
+ * other.  tune == NULL: the bucket width of each product is the one measured
+ * fastest for its (word count, size, precision) class, timed on the first
+ * product of the class this process meets (each candidate computes the same
+ * result; the class's choice is kept for later calls).  On error no output
+ * is returned and every product made so far is freed. */
 pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
                                            const pauli_merge_opts_t* opts,
                                            const pauli_tune_t* tune, paulisum_t* out,

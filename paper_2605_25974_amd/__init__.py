@@ -49,8 +49,7 @@ class MergeOpts(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("tile_i", ctypes.c_int32), ("tile_j", ctypes.c_int32),
-                ("words_per_thread", ctypes.c_int32), ("radix_bits", ctypes.c_int32)]
+    _fields_ = [("bucket_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _vp = ctypes.c_void_p
@@ -308,7 +307,7 @@ def outer_product_batched(a_list, b_list, mode=PLAIN, drop_abs=-1.0, tau=0.0, ke
     B = (_vp * max(nb, 1))(*[x.handle for x in b_list])
     O = (_vp * max(nb, 1))()
     o = _opts(mode, drop_abs, tau, key_bits)
-    t = Tune(*tune) if tune is not None else None
+    t = Tune(int(tune)) if tune is not None else None  # tune: bucket bits
     _check(lib().pauli_outer_product_batched(nb, A, B, ctypes.byref(o),
                                              ctypes.byref(t) if t is not None else None, O,
                                              _stream(stream)))

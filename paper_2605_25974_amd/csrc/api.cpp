@@ -242,6 +242,91 @@ MergeArgs merge_args(const pauli_merge_opts_t* o) {
   return m;
 }
 
+// Bucket-width autotuner of the batched form.  For each class of products
+// (word count, log2 of the product count, coefficient type, merge mode) the
+// first product met is run with the size heuristic's width and its two
+// neighbours, timed with events on the call's stream; the fastest width is
+// kept for the class.  Every candidate computes the same merged sum (the
+// bucket split does not change the order of records within a segment), so
+// the fastest run's output is the product's result.
+struct TuneKey {
+  int W, logp, dtype, mode;
+  bool operator<(const TuneKey& o) const {
+    if (W != o.W) return W < o.W;
+    if (logp != o.logp) return logp < o.logp;
+    if (dtype != o.dtype) return dtype < o.dtype;
+    return mode < o.mode;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+constexpr int64_t kTuneMinProducts = int64_t(1) << 22;  // smaller products are not worth timing
+
+paulisum* fused_or_generic(const paulisum* a, const paulisum* b, const MergeArgs& m,
+                           hipStream_t s) {
+  paulisum* r = nullptr;
+  if (a->m > 0 && b->m > 0) r = fused_bucket(a, b, m, s);
+  if (!r) r = merge_generic(a, b, m, s);
+  return r;
+}
+
+paulisum* batched_one(const paulisum* a, const paulisum* b, const MergeArgs& m, bool autotune,
+                      hipStream_t s) {
+  const int64_t P = a->m * b->m;
+  if (!autotune || m.bucket_bits > 0 || P < kTuneMinProducts)
+    return fused_or_generic(a, b, m, s);
+  int logp = 0;
+  while ((int64_t(1) << logp) < P) ++logp;
+  const TuneKey key{a->W, logp, a->dtype, m.mode};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      MergeArgs mt = m;
+      mt.bucket_bits = it->second;
+      return fused_or_generic(a, b, mt, s);
+    }
+  }
+  const int d0 = fused_default_bucket_bits(P, m.key_bits);
+  paulisum* best = nullptr;
+  float best_ms = 0.0f;
+  int best_d = d0;
+  hipEvent_t e0, e1;
+  PAULI_HIP(hipEventCreate(&e0));
+  PAULI_HIP(hipEventCreate(&e1));
+  try {
+    for (int d = d0 - 1; d <= d0 + 1; ++d) {
+      if (d < 1 || d > 16 || d > m.key_bits) continue;
+      MergeArgs mt = m;
+      mt.bucket_bits = d;
+      PAULI_HIP(hipEventRecord(e0, s));
+      paulisum* r = fused_or_generic(a, b, mt, s);
+      PAULI_HIP(hipEventRecord(e1, s));
+      PAULI_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      PAULI_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (!best || ms < best_ms) {
+        free_sum(best);
+        best = r;
+        best_ms = ms;
+        best_d = d;
+      } else {
+        free_sum(r);
+      }
+    }
+  } catch (...) {
+    free_sum(best);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best_d;
+  return best;
+}
+
 }  // namespace
 
 extern "C" {
@@ -431,9 +516,11 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
                                            const pauli_tune_t* tune, paulisum_t* out,
                                            void* stream) {
   return guarded([&] {
-    (void)tune;
     if (nb < 0) fail(PAULI_ERR_INVALID, "nb is negative");
     if (nb > 0 && (!a || !b || !out)) fail(PAULI_ERR_INVALID, "a, b and out must not be NULL");
+    if (tune && (tune->bucket_bits < 0 || tune->bucket_bits > 16 || tune->reserved[0] ||
+                 tune->reserved[1] || tune->reserved[2]))
+      fail(PAULI_ERR_INVALID, "tune: bucket_bits must be in 0..16 and reserved fields 0");
     for (int32_t t = 0; t < nb; ++t) check_pair(a[t], b[t]);
     const MergeArgs m = merge_args(opts);
     hipStream_t s = as_stream(stream);
@@ -441,7 +528,10 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
     try {
       for (int32_t t = 0; t < nb; ++t) {
         use_device(a[t]);
-        res[t] = merge_generic(a[t], b[t], m, s);
+        a[t]->last_stream = b[t]->last_stream = s;
+        MergeArgs mt = m;
+        if (tune && tune->bucket_bits > 0) mt.bucket_bits = tune->bucket_bits;
+        res[t] = batched_one(a[t], b[t], mt, tune == nullptr, s);
       }
     } catch (...) {
       for (auto* r : res) free_sum(r);

@@ -128,6 +128,7 @@ struct MergeArgs {
   double drop_abs = -1.0;
   double tau = 1e-3;
   int key_bits = 64;
+  int bucket_bits = 0;  // fused pipeline: 0 = the size heuristic
 };
 // merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
@@ -144,5 +145,7 @@ paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz,
 // k_fused.hip: merge(a*b) by the staged fused pipeline; nullptr when a
 // fingerprint collision asks for merge_generic instead.
 paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
+// The bucket width the size heuristic picks for p products.
+int fused_default_bucket_bits(int64_t p, int key_bits);
 
 }  // namespace pauli

@@ -1190,8 +1190,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   const int Wp = G;  // G == 1 iff W == 1; otherwise the next power of two >= W
   const uint32_t P = static_cast<uint32_t>(a->m * b->m);
   const int kb = o.key_bits;
-  int d = 0;
-  if (P > kTargetBucket) d = static_cast<int>(std::ceil(std::log2(P / kTargetBucket)));
+  int d = o.bucket_bits > 0 ? o.bucket_bits : fused_default_bucket_bits(P, kb);
   if (d > kMaxBits) d = kMaxBits;
   if (d > kb) d = kb;
   const int d1 = d < 8 ? d : 8;
@@ -1340,6 +1339,14 @@ paulisum* fused_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
 }
 
 }  // namespace
+
+int fused_default_bucket_bits(int64_t p, int key_bits) {
+  int d = 0;
+  if (p > kTargetBucket) d = static_cast<int>(std::ceil(std::log2(p / kTargetBucket)));
+  if (d > kMaxBits) d = kMaxBits;
+  if (d > key_bits) d = key_bits;
+  return d;
+}
 
 paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
   paulisum* r;
