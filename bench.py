@@ -38,6 +38,10 @@ WORKLOADS = {
     1: "n=16, 2,000 x 2,000 weight-1..4 sums, complex128 (4e6 products)",
     2: "n=500, 10,000 x 10,000 Jordan-Wigner-shaped sums, complex128 (1e8 products)",
     3: "n=500, H*H with 20,000 Jordan-Wigner-shaped real terms, complex128 (4e8 products)",
+    4: "256 products, n in {64,128,256,500}, lognormal term counts (median 2,000, clipped "
+       "to [100, 20,000]), complex64, compensated, autotuned, in calls of 32",
+    5: "1e6 terms at n=500 (weight 1..20, |c| log-uniform in [1e-8, 1]) through 64 "
+       "rotations, drop |c| < 1e-10",
 }
 # sources of the kernel each stage's traffic figure was measured on
 STAGE_SOURCES = {
@@ -123,17 +127,152 @@ def _timed(pl, torch, GA, GB, steps, warmup, **kw):
     return elapsed, U, stages
 
 
-def _rel_err(pl, torch, GA, GB, tau):
+def _rel_err(pl, torch, GA, GB, tau, CA=None, CB=None):
     """Max relative error of the precision form against plain FP64 on this
     GPU, over strings with |c| >= 1e-6 max |c| (both outputs hold the same
-    strings in the same order)."""
+    strings in the same order).  CA, CB: the operands of the precision form
+    when they differ from the FP64 ones (complex64 copies)."""
     ref = pl.outer_product_merged(GA, GB).export_torch()
-    got = pl.outer_product_merged(GA, GB, mode=pl.COMPENSATED, tau=tau).export_torch()
+    got = pl.outer_product_merged(GA if CA is None else CA, GB if CB is None else CB,
+                                  mode=pl.COMPENSATED, tau=tau).export_torch()
     for k in ("x", "z", "fp"):
         if not torch.equal(ref[k], got[k]):
             raise SystemExit("precision form produced different strings than plain FP64")
     r = ref["coef"]
     g = got["coef"].to(torch.complex128)
+    mag = r.abs()
+    sel = mag >= 1e-6 * mag.max()
+    return float(((g - r).abs()[sel] / mag[sel]).max())
+
+
+def _batched(pl, torch, args):
+    """Batched form: 256 products in calls of 32, compensated and autotuned,
+    against the same products as single plain launches."""
+    import numpy as np
+    import synth
+    plan = synth.workload4_plan()
+    pairs = [synth.workload4_batch(b, n, m1, m2) for b, (n, m1, m2) in enumerate(plan)]
+    GA = [pl.PauliSum.from_dict(A) for A, _ in pairs]
+    GB = [pl.PauliSum.from_dict(B) for _, B in pairs]
+    P = sum(m1 * m2 for _, m1, m2 in plan)
+    chunk = 32
+    _log("batched: %d products in %d pairs" % (P, len(plan)))
+
+    def run_batched():
+        U = 0
+        for c0 in range(0, len(plan), chunk):
+            outs = pl.outer_product_batched(GA[c0:c0 + chunk], GB[c0:c0 + chunk],
+                                            mode=pl.COMPENSATED, tau=COMP_TAU)
+            for o in outs:
+                U += o.m
+                o.destroy()
+        return U
+
+    def run_single():
+        for a, b in zip(GA, GB):
+            pl.outer_product_merged(a, b).destroy()
+
+    for _ in range(max(1, args.warmup)):  # also tunes every class
+        run_batched()
+        run_single()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        U = run_batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_single()
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / args.steps
+    # error of the compensated products against plain FP64 on the same
+    # (complex64) inputs, on every 16th pair
+    err = 0.0
+    for b in range(0, len(plan), 16):
+        A, B = pairs[b]
+        A64 = dict(A, coef=A["coef"].astype(np.complex128))
+        B64 = dict(B, coef=B["coef"].astype(np.complex128))
+        g64a, g64b = pl.PauliSum.from_dict(A64), pl.PauliSum.from_dict(B64)
+        err = max(err, _rel_err(pl, torch, g64a, g64b, COMP_TAU, GA[b], GB[b]))
+    return {
+        "metric": "Pauli products/s incl. sort-merge, batched form",
+        "value": P / tb, "unit": "products/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * tb, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (compensated)",
+        "data": "synthetic (seeded generators of the workload's shape)",
+        "config": {"workload": WORKLOADS[4], "products": P, "merged_terms": U},
+        "single_plain_launches": {"value": P / ts, "unit": "products/s",
+                                  "ms_per_step": round(1e3 * ts, 3), "dtype": "f32"},
+        "max_rel_err_vs_fp64": err,
+        "err_definition": "max over every 16th pair of |c32 - c64| / |c64|, |c64| >= 1e-6 max|c64|",
+    }
+
+
+def _propagation(pl, torch, args):
+    """Propagation loop: 64 conjugation steps (FP64 and compensated) and the
+    literal left-multiplication for its first 8 steps."""
+    import synth
+    S = synth.workload5_state()
+    theta, px, pz = synth.workload5_rotations()
+    G = pl.PauliSum.from_dict(S)
+    drop = 1e-10
+    res = {}
+    for name, rot, steps, mode in (("conjugate_fp64", pl.ROTATE_CONJUGATE, 64, pl.PLAIN),
+                                   ("conjugate_compensated", pl.ROTATE_CONJUGATE, 64,
+                                    pl.COMPENSATED),
+                                   ("product_fp64_8_steps", pl.ROTATE_PRODUCT, 8, pl.PLAIN)):
+        pl.propagate(G, px[:1], pz[:1], theta[:1], rotate_mode=rot, mode=mode,
+                     drop_abs=drop).destroy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = pl.propagate(G, px[:steps], pz[:steps], theta[:steps], rotate_mode=rot, mode=mode,
+                           drop_abs=drop, tau=COMP_TAU)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"steps": steps, "seconds": round(dt, 4), "final_terms": out.m,
+                     "ms_per_step": round(1e3 * dt / steps, 3)}
+        res[name + "_out"] = out
+        _log("%s: %.3f s for %d steps, %d terms" % (name, dt, steps, out.m))
+    # literal steps: products = 2 * terms entering each step
+    m, prods = S["x"].shape[0], 0
+    cur = G
+    for t in range(8):
+        prods += 2 * cur.m
+        nxt = pl.propagate(cur, px[t:t + 1], pz[t:t + 1], theta[t:t + 1],
+                           rotate_mode=pl.ROTATE_PRODUCT, drop_abs=drop)
+        if cur is not G:
+            cur.destroy()
+        cur = nxt
+    cur.destroy()
+    lit = res["product_fp64_8_steps"]
+    # compensated vs FP64 after 64 conjugation steps, on common strings
+    a = res.pop("conjugate_fp64_out").export_torch()
+    b = res.pop("conjugate_compensated_out").export_torch()
+    res.pop("product_fp64_8_steps_out").destroy()
+    err = _common_rel_err(torch, a, b)
+    return {
+        "metric": "Pauli products/s incl. sort-merge, propagation loop",
+        "value": prods / lit["seconds"], "unit": "products/s", "n_gpus": 1, "steps": 8,
+        "warmup": 1, "ms_per_step": lit["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators of the workload's shape)",
+        "config": {"workload": WORKLOADS[5], "products": prods, "merged_terms": lit["final_terms"]},
+        "runs": res,
+        "compensated_max_rel_err_vs_fp64_after_64_steps": err,
+        "err_definition": "strings present in both, |c64| >= 1e-6 max|c64|",
+    }
+
+
+def _common_rel_err(torch, a, b):
+    import numpy as np
+    fa, fb = a["fp"].cpu().numpy(), b["fp"].cpu().numpy()
+    _, ia, ib = np.intersect1d(fa, fb, return_indices=True)
+    ia = torch.from_numpy(ia).to(a["fp"].device)
+    ib = torch.from_numpy(ib).to(b["fp"].device)
+    same = (a["x"][ia] == b["x"][ib]).all(1) & (a["z"][ia] == b["z"][ib]).all(1)
+    r = a["coef"][ia][same]
+    g = b["coef"][ib][same].to(torch.complex128)
     mag = r.abs()
     sel = mag >= 1e-6 * mag.max()
     return float(((g - r).abs()[sel] / mag[sel]).max())
@@ -176,6 +315,10 @@ def main():
     import paper_2605_25974_amd as pl
 
     torch.cuda.set_device(0)
+    if args.workload in (4, 5):
+        rec = (_batched if args.workload == 4 else _propagation)(pl, torch, args)
+        print(json.dumps(rec), flush=True)
+        return
     A, B = _inputs(args.workload)
     GA = pl.PauliSum.from_dict(A)
     GB = GA if B is A else pl.PauliSum.from_dict(B)

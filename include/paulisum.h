@@ -192,8 +192,10 @@ pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
                                const pauli_merge_opts_t* opts, paulisum_t* out, void* stream);
 
 /* Replaces the device allocator used for every buffer the library makes
- * (NULL, NULL restores the default, hipMallocAsync / hipFreeAsync on the
- * call's stream).  alloc returns NULL on failure.  Not thread-safe with
+ * (NULL, NULL restores the default: the library's own arena, which reserves
+ * memory from the runtime in chunks of at least 256 MiB, hands out blocks by
+ * best fit per device and stream, and keeps the chunks until the runtime
+ * refuses a new one).  alloc returns NULL on failure.  Not thread-safe with
  * concurrent calls. */
 typedef void* (*pauli_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*pauli_free_fn)(void* ptr, void* stream, void* ctx);

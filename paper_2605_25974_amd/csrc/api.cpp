@@ -23,52 +23,11 @@ pauli_free_fn g_free = nullptr;
 void* g_alloc_ctx = nullptr;
 std::atomic<uint64_t> g_in_use{0};
 std::atomic<uint64_t> g_budget{0};
-std::once_flag g_pool_once[64];
-
-// Blocks released by the library are kept per (device, stream, size class)
-// and handed out again to later requests on the same stream, which are
-// ordered after the release.  Calls of identical shape (a benchmark loop, a
-// propagation step) then allocate nothing.  At most kCacheLimit bytes stay
-// cached; beyond that blocks go back to the runtime pool.
-constexpr uint64_t kCacheLimit = uint64_t(48) << 30;
-struct CacheKey {
-  int dev;
-  hipStream_t s;
-  size_t bytes;
-  bool operator<(const CacheKey& o) const {
-    if (dev != o.dev) return dev < o.dev;
-    if (s != o.s) return s < o.s;
-    return bytes < o.bytes;
-  }
-};
-std::mutex g_cache_mu;
-std::map<CacheKey, std::vector<void*>> g_cache;
-uint64_t g_cached = 0;
-
-size_t size_class(size_t b) {
-  if (b <= (size_t(1) << 20)) {
-    size_t c = 256;
-    while (c < b) c <<= 1;
-    return c;
-  }
-  const size_t g = size_t(1) << 20;  // 1 MiB granules above 1 MiB
-  return (b + g - 1) / g * g;
-}
 
 struct Fail {
   pauli_status_t status;
 };
 
-void init_pool(int dev) {
-  if (dev < 0 || dev >= 64) return;
-  std::call_once(g_pool_once[dev], [dev] {
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t threshold = UINT64_MAX;  // keep freed blocks cached in the pool
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
-    }
-  });
-}
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -86,9 +45,11 @@ void hip_check(hipError_t e, const char* what) {
   }
 }
 
+// Returns the cached blocks of device dev of at least min_bytes to the
+// runtime pool, each on the stream it was released on.
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
-  bytes = size_class(bytes);
+  bytes = (bytes + 255) & ~size_t(255);
   const uint64_t budget = g_budget.load();
   if (budget && g_in_use.load() + bytes > budget)
     fail(PAULI_ERR_OOM, "device memory budget exceeded (" + std::to_string(bytes) +
@@ -101,23 +62,7 @@ void* dalloc(size_t bytes, hipStream_t s) {
   } else {
     int dev = 0;
     PAULI_HIP(hipGetDevice(&dev));
-    {
-      std::lock_guard<std::mutex> lk(g_cache_mu);
-      auto it = g_cache.find(CacheKey{dev, s, bytes});
-      if (it != g_cache.end() && !it->second.empty()) {
-        p = it->second.back();
-        it->second.pop_back();
-        g_cached -= bytes;
-        g_in_use += bytes;
-        return p;
-      }
-    }
-    init_pool(dev);
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess || !p) {
-      (void)hipGetLastError();
-      fail(PAULI_ERR_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
-    }
+    p = arena_alloc(dev, s, bytes);
   }
   g_in_use += bytes;
   return p;
@@ -125,22 +70,13 @@ void* dalloc(size_t bytes, hipStream_t s) {
 
 void dfree(void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
-  bytes = size_class(bytes);
+  bytes = (bytes + 255) & ~size_t(255);
   g_in_use -= bytes;
   if (g_alloc) {
     if (g_free) g_free(p, s, g_alloc_ctx);
     return;
   }
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    if (g_cached + bytes <= kCacheLimit) {
-      g_cache[CacheKey{dev, s, bytes}].push_back(p);
-      g_cached += bytes;
-      return;
-    }
-  }
-  (void)hipFreeAsync(p, s);
+  arena_free(p, s);
 }
 
 paulisum* new_sum(int n, int64_t m, int64_t ld, pauli_dtype_t dt, hipStream_t s) {

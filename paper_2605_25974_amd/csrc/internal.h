@@ -41,6 +41,10 @@ void hip_check(hipError_t e, const char* what);
 #define PAULI_HIP(call) ::pauli::hip_check((call), #call)
 
 // ------------------------------------------------------------------ memory
+// alloc.cpp: the library's device arena (one per device and stream).
+void* arena_alloc(int dev, hipStream_t s, size_t bytes);
+void arena_free(void* p, hipStream_t s);
+
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, size_t bytes, hipStream_t s);
 

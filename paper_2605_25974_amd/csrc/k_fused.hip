@@ -142,10 +142,16 @@ __global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restri
   }
 }
 
+// Terms per class from the class-sorted keys: a class occupies one run, so
+// its first term adds -start and its last term adds end + 1 (two atomics per
+// class, none per term).  g must be zero.
 __global__ void k_class_count(const uint64_t* __restrict__ cls, uint32_t m,
                               uint32_t* __restrict__ g) {
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
-    atomicAdd(&g[cls[t]], 1u);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+    const uint64_t c = cls[t];
+    if (t == 0 || cls[t - 1] != c) atomicAdd(&g[c], 0u - t);
+    if (t + 1 == m || cls[t + 1] != c) atomicAdd(&g[c], t + 1);
+  }
 }
 
 __global__ void k_gather_keys(const uint64_t* __restrict__ key, const uint32_t* __restrict__ sidx,
