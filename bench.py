@@ -88,7 +88,7 @@ def _traffic(stage, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(A, B, target_s=15.0):
+def cpu_baseline(A, B, target_s=10.0):
     """The CPU oracle timed on a bounded block of the same pair space."""
     from oracle import oracle as O
     SA = O.Sum(A["n"], A["x"], A["z"], A["phase"], A["coef"])
@@ -299,8 +299,10 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compensated", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--pcie", action="store_true",
+                    help="also time one call from host inputs to the merged sum in host memory")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -372,6 +374,19 @@ def main():
             "err_definition": "max |c32 - c64| / |c64| over strings with |c64| >= 1e-6 max|c64|",
             "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in cst.items()},
         }
+    if args.pcie:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ha = pl.PauliSum.from_dict(A)
+        hb = ha if B is A else pl.PauliSum.from_dict(B)
+        out = pl.outer_product_merged(ha, hb)
+        host = out.export()
+        dt = time.perf_counter() - t0
+        rec["pcie_inclusive"] = {
+            "value": P / dt, "unit": "products/s", "ms": round(1e3 * dt, 2),
+            "note": "host inputs uploaded, fused product, merged sum (%d terms) copied back "
+                    "to host memory" % host["x"].shape[0]}
+        out.destroy()
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle")
         rec["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
