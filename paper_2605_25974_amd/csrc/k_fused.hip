@@ -840,34 +840,39 @@ struct Meta {
   uint32_t mi[kSplit ? 1 : kRun];
 };
 
+// Every lane issues the same loads whatever the chunk's position (indices
+// past the bucket are clamped to its last record), so a chunk issues a fixed
+// number of memory operations.  The loaded words are kept as loaded; the
+// past-the-end substitutions happen in unpack_meta, one chunk later, so the
+// loads are not waited for (together with older stores) when they are issued.
+// n >= 1.
 template <int G>
 __device__ __forceinline__ Meta<G> fetch_meta(const ExpandArgs& E, uint32_t lo, uint32_t n,
                                               uint32_t p0, int gl) {
   Meta<G> m;
+  const uint32_t last = n - 1;
+  auto at = [&](uint32_t q) { return lo + (q < n ? q : last); };
   if (Meta<G>::kSplit) {
-    // lane gl: segment index of record p0 + gl (gl <= kRun), its id
-    // (gl < kRun), the segment index before the run (gl == kRun + 1)
-    m.ms[0] = 0xFFFFFFFEu;
-    m.mi[0] = 0u;
-    if (gl <= kRun) {
-      if (p0 + gl < n) m.ms[0] = E.segidx[lo + p0 + gl];
-      if (gl < kRun && p0 + gl < n) m.mi[0] = E.vals[lo + p0 + gl];
-    } else if (gl == kRun + 1) {
-      m.ms[0] = (p0 && p0 < n) ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
-    }
+    // lane gl: record p0 + gl (gl <= kRun), or the record before the run
+    const uint32_t q = gl <= kRun ? p0 + gl : (p0 ? p0 - 1 : 0u);
+    m.ms[0] = E.segidx[at(q)];
+    m.mi[0] = E.vals[at(q)];
   } else {
 #pragma unroll
-    for (int t = 0; t <= kRun; ++t) m.ms[t] = p0 + t < n ? E.segidx[lo + p0 + t] : 0xFFFFFFFEu;
-    m.ms[kRun + 1] = (p0 && p0 < n) ? E.segidx[lo + p0 - 1] : 0xFFFFFFFFu;
+    for (int t = 0; t <= kRun; ++t) m.ms[t] = E.segidx[at(p0 + t)];
+    m.ms[kRun + 1] = E.segidx[at(p0 ? p0 - 1 : 0u)];
 #pragma unroll
-    for (int t = 0; t < kRun; ++t) m.mi[t] = p0 + t < n ? E.vals[lo + p0 + t] : 0u;
+    for (int t = 0; t < kRun; ++t) m.mi[t] = E.vals[at(p0 + t)];
   }
   return m;
 }
 
+// Segment indices sid[0..kRun] of the run's records (0xFFFFFFFE past the
+// bucket), their ids (0 past the bucket: a valid pair) and the segment index
+// of the record before the run (0xFFFFFFFF at the bucket's start).
 template <int G>
-__device__ __forceinline__ void unpack_meta(const Meta<G>& m, int gl, uint32_t* sid,
-                                            uint32_t* ids, uint32_t& sprev) {
+__device__ __forceinline__ void unpack_meta(const Meta<G>& m, int gl, uint32_t n, uint32_t p0,
+                                            uint32_t* sid, uint32_t* ids, uint32_t& sprev) {
   if (Meta<G>::kSplit) {
     const int base = (threadIdx.x & 63) - gl;
 #pragma unroll
@@ -881,6 +886,68 @@ __device__ __forceinline__ void unpack_meta(const Meta<G>& m, int gl, uint32_t* 
 #pragma unroll
     for (int t = 0; t < kRun; ++t) ids[t] = m.mi[t];
     sprev = m.ms[kRun + 1];
+  }
+#pragma unroll
+  for (int t = 0; t <= kRun; ++t)
+    if (p0 + t >= n) sid[t] = 0xFFFFFFFEu;
+#pragma unroll
+  for (int t = 0; t < kRun; ++t)
+    if (p0 + t >= n) ids[t] = 0u;
+  if (!(p0 && p0 < n)) sprev = 0xFFFFFFFFu;
+}
+
+// Buffer stores: a lane whose offset is beyond the resource's byte range
+// writes nothing, so every chunk issues the same store instructions whatever
+// it holds.  Resource word 3 for gfx9-family buffers; cache policy bit 1 =
+// non-temporal (the output is not read again by this kernel).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;
+constexpr uint32_t kOff = 0x40000000u;  // beyond every range used here
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes),
+                                           kRsrcWord3);
+}
+
+__device__ __forceinline__ u32x2 halves(uint64_t v) {
+  return u32x2{static_cast<unsigned>(v), static_cast<unsigned>(v >> 32)};
+}
+
+// Stores the cnt staged terms of a chunk at output positions ob, ob+1, ...
+// (cnt == 0 issues the same instructions and writes nothing).
+template <int WT, typename TV, int RB>
+__device__ __forceinline__ void store_chunk(const ExpandArgs& E, const Stage<WT, TV, RB>& st,
+                                            int nw, int64_t ob, uint32_t cnt, int lane) {
+#pragma unroll
+  for (int r = 0; r < (RB + 63) / 64; ++r) {
+    const uint32_t kk = static_cast<uint32_t>(r * 64 + lane);
+    const uint32_t ks = kk < static_cast<uint32_t>(RB) ? kk : 0u;
+    const bool live = kk < cnt && st.valid[ks];
+    const uint32_t o8 = live ? kk * 8u : kOff;
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+      const uint32_t bytes = w < nw ? cnt * 8u : 0u;
+      __builtin_amdgcn_raw_buffer_store_b64(halves(st.x[w][ks]), out_rsrc(E.OX + w * E.ldo + ob, bytes),
+                                            o8, 0, kNonTemporal);
+      __builtin_amdgcn_raw_buffer_store_b64(halves(st.z[w][ks]), out_rsrc(E.OZ + w * E.ldo + ob, bytes),
+                                            o8, 0, kNonTemporal);
+    }
+    __builtin_amdgcn_raw_buffer_store_b8(static_cast<unsigned char>(0), out_rsrc(E.Oph + ob, cnt),
+                                         live ? kk : kOff, 0, kNonTemporal);
+    const cplx<TV> c = st.c[ks];
+    cplx<TV>* oc = static_cast<cplx<TV>*>(E.Oc) + ob;
+    if constexpr (sizeof(TV) == 8) {
+      const u32x2 re = halves(to_word<TV>(c.re)), im = halves(to_word<TV>(c.im));
+      __builtin_amdgcn_raw_buffer_store_b128(u32x4{re.x, re.y, im.x, im.y}, out_rsrc(oc, cnt * 16u),
+                                             live ? kk * 16u : kOff, 0, kNonTemporal);
+    } else {
+      const u32x2 v{static_cast<unsigned>(to_word<TV>(c.re)), static_cast<unsigned>(to_word<TV>(c.im))};
+      __builtin_amdgcn_raw_buffer_store_b64(v, out_rsrc(oc, cnt * 8u), o8, 0, kNonTemporal);
+    }
+    __builtin_amdgcn_raw_buffer_store_b64(halves(st.fp[ks]), out_rsrc(E.Ofp + ob, cnt * 8u), o8, 0,
+                                          kNonTemporal);
   }
 }
 
@@ -912,6 +979,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
   Stage<WT, TV, RB>& st = stage[wave];
   const int g = lane / G, gl = lane % G;
   const int nw = op.nw;
+  uint64_t coll = 0;
   for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
     const uint32_t obase = E.segoff[b];
@@ -922,12 +990,16 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
     Meta<G> m_cur = fetch_meta<G>(E, lo, n, r0 + goff, gl);
     Meta<G> m_next = fetch_meta<G>(E, lo, n, r0 + STEP + goff, gl);
     uint32_t sid[kRun + 1], ids[kRun], sprev;
-    unpack_meta<G>(m_cur, gl, sid, ids, sprev);
+    unpack_meta<G>(m_cur, gl, n, r0 + goff, sid, ids, sprev);
     // ids past the bucket's end read as 0, a valid pair: the gathers are
     // issued unconditionally so that no stale registers stay live
     Raw<G> raw[kRun];
 #pragma unroll
     for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
+    // the same stores as a chunk's, writing nothing: the loop is entered with
+    // the memory operations after the gathers that every iteration has, so
+    // waiting for the gathers never waits for earlier stores
+    store_chunk<WT, TV, RB>(E, st, nw, static_cast<int64_t>(obase), 0u, lane);
     for (; r0 < n; r0 += STEP) {
       const uint32_t p0 = r0 + goff;
       const Meta<G> m_after = fetch_meta<G>(E, lo, n, r0 + 2 * STEP + goff, gl);
@@ -1005,43 +1077,19 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
           }
           if (!is_long) emit(s_cur - sfirst, p0 + t_head, q);
         }
-        // an equal key must be an equal string
-#pragma unroll
-        for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
-        if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
+        coll |= diff;  // an equal key must be an equal string
       }
       // gathers of the next chunk go out before this chunk's stores
-      unpack_meta<G>(m_next, gl, sid, ids, sprev);
+      unpack_meta<G>(m_next, gl, n, r0 + STEP + goff, sid, ids, sprev);
 #pragma unroll
       for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
       m_next = m_after;
       wave_sync();
-      const int64_t ob = static_cast<int64_t>(obase) + sfirst;
-      // two arrays per store instruction when the chunk has at most 32 terms
-      constexpr int kPer = RB <= 32 ? 2 : 1;
-      const uint32_t k = RB <= 32 ? static_cast<uint32_t>(lane & 31) : static_cast<uint32_t>(lane);
-      const int sub = RB <= 32 ? (lane >> 5) : 0;
-      // the output is not read again here: streaming stores keep it from
-      // evicting the operand rows out of L2
-      for (int w0 = 0; w0 < nw; w0 += kPer) {
-        const int w = w0 + sub;
-        for (uint32_t kk = k; kk < cnt; kk += 64 / kPer)
-          if (w < nw && st.valid[kk]) {
-            __builtin_nontemporal_store(st.x[w][kk], &E.OX[w * E.ldo + ob + kk]);
-            __builtin_nontemporal_store(st.z[w][kk], &E.OZ[w * E.ldo + ob + kk]);
-          }
-      }
-      for (uint32_t kk = static_cast<uint32_t>(lane); kk < cnt; kk += 64)
-        if (st.valid[kk]) {
-          __builtin_nontemporal_store(uint8_t(0), &E.Oph[ob + kk]);
-          TV* oc = reinterpret_cast<TV*>(static_cast<cplx<TV>*>(E.Oc) + ob + kk);
-          __builtin_nontemporal_store(st.c[kk].re, oc);
-          __builtin_nontemporal_store(st.c[kk].im, oc + 1);
-          __builtin_nontemporal_store(st.fp[kk], &E.Ofp[ob + kk]);
-        }
+      store_chunk<WT, TV, RB>(E, st, nw, static_cast<int64_t>(obase) + sfirst, cnt, lane);
       wave_sync();  // the stage is reused by the next chunk
     }
   }
+  if (__any(coll != 0) && lane == 0) atomicOr(E.err, kErrCollision);
 }
 
 template <int G, typename TO, typename TV>
