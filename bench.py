@@ -132,6 +132,7 @@ def _rel_err(pl, torch, GA, GB, tau, CA=None, CB=None):
     GPU, over strings with |c| >= 1e-6 max |c| (both outputs hold the same
     strings in the same order).  CA, CB: the operands of the precision form
     when they differ from the FP64 ones (complex64 copies)."""
+    pl.trim_memory()  # torch needs device memory for the comparison
     ref = pl.outer_product_merged(GA, GB).export_torch()
     got = pl.outer_product_merged(GA if CA is None else CA, GB if CB is None else CB,
                                   mode=pl.COMPENSATED, tau=tau).export_torch()
@@ -247,6 +248,7 @@ def _propagation(pl, torch, args):
     cur.destroy()
     lit = res["product_fp64_8_steps"]
     # compensated vs FP64 after 64 conjugation steps, on common strings
+    pl.trim_memory()  # torch needs device memory for the comparison
     a = res.pop("conjugate_fp64_out").export_torch()
     b = res.pop("conjugate_compensated_out").export_torch()
     res.pop("product_fp64_8_steps_out").destroy()

@@ -201,6 +201,12 @@ typedef void* (*pauli_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*pauli_free_fn)(void* ptr, void* stream, void* ctx);
 pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, void* ctx);
 
+/* Returns the device memory the library's arena holds but does not use, on
+ * the current device, to the runtime (for callers that share the device with
+ * another allocator).  Waits for the device.  No effect with an allocator
+ * hook. */
+pauli_status_t pauli_trim_memory(void);
+
 /* Upper bound on device bytes the library may hold at once for temporaries
  * and results made by later calls (0 = no limit).  Exceeding it gives OOM. */
 pauli_status_t pauli_set_memory_budget(uint64_t bytes);

@@ -29,6 +29,7 @@ EXPORTS = (
     "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
+    "pauli_trim_memory",
 )
 STAGES = ("outer_product", "prep", "sort", "segment", "write", "long")
 
@@ -98,6 +99,8 @@ def lib():
     L.pauli_outer_product_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
                                               ctypes.POINTER(_vp), ctypes.POINTER(MergeOpts),
                                               ctypes.POINTER(Tune), ctypes.POINTER(_vp), _vp]
+    L.pauli_trim_memory.restype = st
+    L.pauli_trim_memory.argtypes = []
     L.pauli_propagate.restype = st
     L.pauli_propagate.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32,
                                   ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
@@ -312,6 +315,11 @@ def outer_product_batched(a_list, b_list, mode=PLAIN, drop_abs=-1.0, tau=0.0, ke
                                              ctypes.byref(t) if t is not None else None, O,
                                              _stream(stream)))
     return [PauliSum(O[i]) for i in range(nb)]
+
+
+def trim_memory():
+    """Return the device memory the library holds but does not use."""
+    _check(lib().pauli_trim_memory())
 
 
 def set_memory_budget(nbytes: int):

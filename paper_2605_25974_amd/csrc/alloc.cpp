@@ -6,14 +6,18 @@
 // stream is handed out again only to later requests on that stream, which
 // the stream orders after every use of the old contents.  A block released
 // on another stream than the one it came from waits for that stream first.
-// Chunks stay reserved until the runtime refuses a new chunk; then every
-// chunk with nothing in use is returned and the request is retried once.
+// Chunks stay reserved until pauli_trim_memory; a new chunk is at least half
+// the size of what the arena already holds, up to 1/16 of the device beyond
+// the request (so growing sizes need few reservations).  When the runtime
+// refuses a chunk, every idle chunk is returned and the request is retried
+// once at the size it needs.
 //
 // The runtime's stream-ordered pool is not used: with outputs of many
 // different sizes (batches, a growing propagation state) its allocation and
 // release calls were seen to stall for seconds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -127,12 +131,25 @@ void* arena_alloc(int dev, hipStream_t s, size_t bytes) {
   Arena& a = arena_for(dev, s);
   auto it = a.free_by_size.lower_bound(bytes);
   if (it == a.free_by_size.end()) {
-    const size_t cb = chunk_bytes(bytes);
+    // chunks grow with the arena (at least half of what it holds), so sizes
+    // that keep growing need few reservations
+    size_t held = 0;
+    for (size_t c = 0; c < a.chunk_size.size(); ++c) held += a.chunk_size[c];
+    size_t cb = chunk_bytes(bytes);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      (void)hipGetLastError();
+      total_b = 0;
+    }
+    const size_t grow = std::min(held / 2, total_b / 16);  // at most 1/16 of the device beyond need
+    if (grow > cb) cb = chunk_bytes(grow);
     void* base = nullptr;
     hipError_t e = hipMalloc(&base, cb);
     if (e != hipSuccess || !base) {
+      // return every idle chunk and ask for exactly what is needed
       (void)hipGetLastError();
       release_idle_chunks(dev);
+      cb = chunk_bytes(bytes);
       base = nullptr;
       e = hipMalloc(&base, cb);
     }
@@ -156,6 +173,11 @@ void* arena_alloc(int dev, hipStream_t s, size_t bytes) {
   a.chunk_used[f.chunk] += bytes;
   g_live[p] = Live{&a, bytes, f.chunk};
   return p;
+}
+
+void arena_trim(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  release_idle_chunks(dev);
 }
 
 void arena_free(void* ptr, hipStream_t s) {

@@ -528,6 +528,14 @@ pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, 
   });
 }
 
+pauli_status_t pauli_trim_memory(void) {
+  return guarded([&] {
+    int dev = 0;
+    PAULI_HIP(hipGetDevice(&dev));
+    arena_trim(dev);
+  });
+}
+
 pauli_status_t pauli_set_memory_budget(uint64_t bytes) {
   return guarded([&] { g_budget = bytes; });
 }

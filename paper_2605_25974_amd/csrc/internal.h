@@ -44,6 +44,7 @@ void hip_check(hipError_t e, const char* what);
 // alloc.cpp: the library's device arena (one per device and stream).
 void* arena_alloc(int dev, hipStream_t s, size_t bytes);
 void arena_free(void* p, hipStream_t s);
+void arena_trim(int dev);  // returns the idle chunks of device dev
 
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, size_t bytes, hipStream_t s);

@@ -916,7 +916,8 @@ __device__ __forceinline__ u32x2 halves(uint64_t v) {
 }
 
 // Stores the cnt staged terms of a chunk at output positions ob, ob+1, ...
-// (cnt == 0 issues the same instructions and writes nothing).
+// (cnt == 0 issues the same instructions and writes nothing).  The phase
+// bytes of the output (all zero) are filled separately.
 template <int WT, typename TV, int RB>
 __device__ __forceinline__ void store_chunk(const ExpandArgs& E, const Stage<WT, TV, RB>& st,
                                             int nw, int64_t ob, uint32_t cnt, int lane) {
@@ -934,8 +935,6 @@ __device__ __forceinline__ void store_chunk(const ExpandArgs& E, const Stage<WT,
       __builtin_amdgcn_raw_buffer_store_b64(halves(st.z[w][ks]), out_rsrc(E.OZ + w * E.ldo + ob, bytes),
                                             o8, 0, kNonTemporal);
     }
-    __builtin_amdgcn_raw_buffer_store_b8(static_cast<unsigned char>(0), out_rsrc(E.Oph + ob, cnt),
-                                         live ? kk : kOff, 0, kNonTemporal);
     const cplx<TV> c = st.c[ks];
     cplx<TV>* oc = static_cast<cplx<TV>*>(E.Oc) + ob;
     if constexpr (sizeof(TV) == 8) {
@@ -952,141 +951,161 @@ __device__ __forceinline__ void store_chunk(const ExpandArgs& E, const Stage<WT,
 }
 
 // Buckets are spread over blocks; inside a bucket every wave independently
-// takes chunks of RB consecutive records (no block barriers).  Group g of a
-// wave takes kRun records of the chunk and handles every segment whose first
-// record lies there (continuing past the run when the segment does), except
-// segments longer than kLong, which k_expand_long sums.  The terms of a
-// chunk's segments form one contiguous output range: they are staged in the
-// wave's LDS region and stored coalesced, array by array.
+// takes super-chunks of RS consecutive records (no block barriers).  A
+// super-chunk is SUB sub-chunks of RB records (RS >= 64, so that every store
+// instruction has a term per lane); group g of the wave takes kRun records of
+// each sub-chunk and handles every segment whose first record lies there
+// (continuing past the run when the segment does), except segments longer
+// than kLong, which k_expand_long sums.  The terms of a super-chunk's
+// segments form one contiguous output range: they are staged in the wave's
+// LDS region and stored coalesced, array by array.
 //
 // Loads and stores share one in-order completion counter per wave, so a wait
 // for a load also waits for every store issued before it.  The loop is
-// therefore pipelined: the ids of chunk c+2 and the row/metadata gathers of
-// chunk c+1 are issued before the stores of chunk c, and no wait ever has an
-// older store ahead of it.
-// With MODE == kComp a segment whose compensated FP32 sum cancels is summed
-// again in FP64 (remerge64) before it is staged.
+// therefore pipelined: the ids two sub-chunks ahead and the row/metadata
+// gathers of the next sub-chunk are issued before the current one is
+// processed, and the stores of a super-chunk are issued after the gathers of
+// the next one.  Every iteration issues the same memory operations, so no
+// wait for a gather ever waits for an older store.
 template <int G, int WT, typename T, int MODE>
 __global__ void __launch_bounds__(kB, 3)
 k_expand(ExpandArgs E, Operands<WT, T> op) {
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
   constexpr int NG = 64 / G;  // groups per wave
   constexpr int RB = NG * kRun;
+  constexpr int SUB = RB >= 64 ? 1 : 64 / RB;
+  constexpr int RS = RB * SUB;
   constexpr int NW = kB / 64;
-  constexpr uint32_t STEP = NW * RB;
-  __shared__ Stage<WT, TV, RB> stage[NW];
+  constexpr uint32_t STEP = NW * RS;
+  __shared__ Stage<WT, TV, RS> stage[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  Stage<WT, TV, RB>& st = stage[wave];
+  Stage<WT, TV, RS>& st = stage[wave];
   const int g = lane / G, gl = lane % G;
   const int nw = op.nw;
+  const uint32_t goff = static_cast<uint32_t>(g) * kRun;
   uint64_t coll = 0;
   for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
     const uint32_t obase = E.segoff[b];
-    uint32_t r0 = static_cast<uint32_t>(wave) * RB;
-    if (r0 >= n) continue;
-    const uint32_t goff = static_cast<uint32_t>(g) * kRun;
-    // pipeline prologue: metadata of chunks 0 and 1, gathers of chunk 0
-    Meta<G> m_cur = fetch_meta<G>(E, lo, n, r0 + goff, gl);
-    Meta<G> m_next = fetch_meta<G>(E, lo, n, r0 + STEP + goff, gl);
+    uint32_t R0 = static_cast<uint32_t>(wave) * RS;
+    if (R0 >= n) continue;
+    // start of the k-th sub-chunk counted from the super-chunk at R
+    auto sub_at = [&](uint32_t R, int k) {
+      return R + static_cast<uint32_t>(k / SUB) * STEP + static_cast<uint32_t>(k % SUB) * RB;
+    };
+    // pipeline prologue: ids of sub-chunks 0 and 1, gathers of sub-chunk 0
+    Meta<G> m_cur = fetch_meta<G>(E, lo, n, sub_at(R0, 0) + goff, gl);
+    Meta<G> m_next = fetch_meta<G>(E, lo, n, sub_at(R0, 1) + goff, gl);
     uint32_t sid[kRun + 1], ids[kRun], sprev;
-    unpack_meta<G>(m_cur, gl, n, r0 + goff, sid, ids, sprev);
+    unpack_meta<G>(m_cur, gl, n, R0 + goff, sid, ids, sprev);
     // ids past the bucket's end read as 0, a valid pair: the gathers are
     // issued unconditionally so that no stale registers stay live
     Raw<G> raw[kRun];
 #pragma unroll
     for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
-    // the same stores as a chunk's, writing nothing: the loop is entered with
-    // the memory operations after the gathers that every iteration has, so
-    // waiting for the gathers never waits for earlier stores
-    store_chunk<WT, TV, RB>(E, st, nw, static_cast<int64_t>(obase), 0u, lane);
-    for (; r0 < n; r0 += STEP) {
-      const uint32_t p0 = r0 + goff;
-      const Meta<G> m_after = fetch_meta<G>(E, lo, n, r0 + 2 * STEP + goff, gl);
-      for (int kk = lane; kk < RB; kk += 64) st.valid[kk] = 0;
-      // first segment with its first record in the chunk, and the chunk's
-      // last segment (from groups 0 and NG-1)
-      const uint32_t s_at0 = __shfl(sid[0], 0, 64);
-      const uint32_t s_before = __shfl(sprev, 0, 64);
-      const uint32_t sfirst = s_at0 == s_before ? s_at0 + 1 : s_at0;
-      const uint32_t rl = (r0 + RB < n ? r0 + RB : n) - 1 - r0;  // last record, chunk-relative
-      uint32_t s_mine = sid[0];
+    // the same stores as a super-chunk's, writing nothing: the loop is
+    // entered with the memory operations after the gathers that every
+    // iteration has
+    store_chunk<WT, TV, RS>(E, st, nw, static_cast<int64_t>(obase), 0u, lane);
+    for (; R0 < n; R0 += STEP) {
+      for (int kk = lane; kk < RS; kk += 64) st.valid[kk] = 0;
+      // the super-chunk's last record
+      const uint32_t last = (R0 + RS < n ? R0 + RS : n) - 1;
+      uint32_t sfirst = 0, cnt = 0;
 #pragma unroll
-      for (int t = 1; t < kRun; ++t)
-        if (static_cast<int>(rl % kRun) == t) s_mine = sid[t];
-      const uint32_t s_last = __shfl(s_mine, static_cast<int>((rl / kRun) * G), 64);
-      const uint32_t cnt = s_last + 1 > sfirst ? s_last + 1 - sfirst : 0u;
-      Rec<G, TV> rec[kRun];
-#pragma unroll
-      for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl);
-      wave_sync();  // valid[] cleared before any stage_out
-      if (p0 < n) {
-        Acc<MODE, TV> acc;
-        acc.zero();
-        uint64_t h0 = 0, h1 = 0, diff = 0;
-        bool open = false;
-        int t_head = 0;
-        Rec<G, TV> first;
-        // stages segment [q0, q1) (bucket positions) once its sum is known
-        auto emit = [&](uint32_t slot, uint32_t q0, uint32_t q1) {
-          TV vr = acc.value_re(), vi = acc.value_im();
-          if (MODE == kComp && acc.cancels(E.tau)) {
-            const cplx<double> c = remerge64<G, WT, T>(E, op, lo, q0, q1, gl);
-            vr = static_cast<TV>(c.re);
-            vi = static_cast<TV>(c.im);
-          }
-          stage_out<G, WT, TV, RB, TV>(st, nw, gl, slot, first, vr, vi);
-        };
-#pragma unroll
-        for (int t = 0; t < kRun; ++t) {
-          if (p0 + t >= n) break;
-          const bool head = sid[t] != (t ? sid[t - 1] : sprev);
-          if (head) {
-            open = true;
-            t_head = t;
-            acc.begin(rec[t].re, rec[t].im);
-            first = rec[t];
-            h0 = rec[t].w0;
-            h1 = rec[t].w1;
-          } else if (open) {
-            acc.add(rec[t].re, rec[t].im);
-            diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
-          }
-          const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
-          if (open && ends) {
-            emit(sid[t] - sfirst, p0 + t_head, p0 + t + 1);
-            open = false;
-          }
+      for (int sub = 0; sub < SUB; ++sub) {
+        const uint32_t c0 = R0 + static_cast<uint32_t>(sub) * RB;
+        const uint32_t p0 = c0 + goff;
+        const Meta<G> m_after = fetch_meta<G>(E, lo, n, sub_at(R0, sub + 2) + goff, gl);
+        if (sub == 0) {
+          // first segment with its first record in the super-chunk
+          const uint32_t s_at0 = __shfl(sid[0], 0, 64);
+          const uint32_t s_before = __shfl(sprev, 0, 64);
+          sfirst = s_at0 == s_before ? s_at0 + 1 : s_at0;
         }
-        if (open) {
-          // the run's last segment continues past the run: follow it, unless
-          // it is longer than kLong (then k_expand_long sums it)
-          const uint32_t s_cur = sid[kRun - 1];
-          uint32_t len = static_cast<uint32_t>(kRun - t_head);
-          uint32_t q = p0 + kRun;
-          bool is_long = false;
-          while (q < n && E.segidx[lo + q] == s_cur) {
-            if (++len > static_cast<uint32_t>(kLong)) {
-              is_long = true;
-              break;
+        if (last >= c0 && last < c0 + RB) {
+          // the super-chunk's last segment, from the group holding its last record
+          const uint32_t rl = last - c0;
+          uint32_t s_mine = sid[0];
+#pragma unroll
+          for (int t = 1; t < kRun; ++t)
+            if (static_cast<int>(rl % kRun) == t) s_mine = sid[t];
+          const uint32_t s_last = __shfl(s_mine, static_cast<int>((rl / kRun) * G), 64);
+          cnt = s_last + 1 > sfirst ? s_last + 1 - sfirst : 0u;
+        }
+        Rec<G, TV> rec[kRun];
+#pragma unroll
+        for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl);
+        wave_sync();  // valid[] cleared before any stage_out
+        if (p0 < n) {
+          Acc<MODE, TV> acc;
+          acc.zero();
+          uint64_t h0 = 0, h1 = 0, diff = 0;
+          bool open = false;
+          int t_head = 0;
+          Rec<G, TV> first;
+          // stages segment [q0, q1) (bucket positions) once its sum is known
+          auto emit = [&](uint32_t slot, uint32_t q0, uint32_t q1) {
+            TV vr = acc.value_re(), vi = acc.value_im();
+            if (MODE == kComp && acc.cancels(E.tau)) {
+              const cplx<double> c = remerge64<G, WT, T>(E, op, lo, q0, q1, gl);
+              vr = static_cast<TV>(c.re);
+              vi = static_cast<TV>(c.im);
             }
-            const Rec<G, TV> r = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
-            acc.add(r.re, r.im);
-            diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
-            ++q;
-          }
-          if (!is_long) emit(s_cur - sfirst, p0 + t_head, q);
-        }
-        coll |= diff;  // an equal key must be an equal string
-      }
-      // gathers of the next chunk go out before this chunk's stores
-      unpack_meta<G>(m_next, gl, n, r0 + STEP + goff, sid, ids, sprev);
+            stage_out<G, WT, TV, RS, TV>(st, nw, gl, slot, first, vr, vi);
+          };
 #pragma unroll
-      for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
-      m_next = m_after;
+          for (int t = 0; t < kRun; ++t) {
+            if (p0 + t >= n) break;
+            const bool head = sid[t] != (t ? sid[t - 1] : sprev);
+            if (head) {
+              open = true;
+              t_head = t;
+              acc.begin(rec[t].re, rec[t].im);
+              first = rec[t];
+              h0 = rec[t].w0;
+              h1 = rec[t].w1;
+            } else if (open) {
+              acc.add(rec[t].re, rec[t].im);
+              diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
+            }
+            const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
+            if (open && ends) {
+              emit(sid[t] - sfirst, p0 + t_head, p0 + t + 1);
+              open = false;
+            }
+          }
+          if (open) {
+            // the run's last segment continues past the run: follow it,
+            // unless it is longer than kLong (then k_expand_long sums it)
+            const uint32_t s_cur = sid[kRun - 1];
+            uint32_t len = static_cast<uint32_t>(kRun - t_head);
+            uint32_t q = p0 + kRun;
+            bool is_long = false;
+            while (q < n && E.segidx[lo + q] == s_cur) {
+              if (++len > static_cast<uint32_t>(kLong)) {
+                is_long = true;
+                break;
+              }
+              const Rec<G, TV> r = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
+              acc.add(r.re, r.im);
+              diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
+              ++q;
+            }
+            if (!is_long) emit(s_cur - sfirst, p0 + t_head, q);
+          }
+          coll |= diff;  // an equal key must be an equal string
+        }
+        // gathers of the next sub-chunk
+        const uint32_t pn = sub_at(R0, sub + 1) + goff;
+        unpack_meta<G>(m_next, gl, n, pn, sid, ids, sprev);
+#pragma unroll
+        for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
+        m_next = m_after;
+      }
       wave_sync();
-      store_chunk<WT, TV, RB>(E, st, nw, static_cast<int64_t>(obase) + sfirst, cnt, lane);
-      wave_sync();  // the stage is reused by the next chunk
+      store_chunk<WT, TV, RS>(E, st, nw, static_cast<int64_t>(obase) + sfirst, cnt, lane);
+      wave_sync();  // the stage is reused by the next super-chunk
     }
   }
   if (__any(coll != 0) && lane == 0) atomicOr(E.err, kErrCollision);
@@ -1358,6 +1377,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   {
     StageScope sc(PAULI_STAGE_WRITE, s,
                   U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + P * 8.0);
+    // merged terms carry phase 0 (the block of phase bytes is padded to 256)
+    if (U > 0)
+      hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((U + 3) / 4)), dim3(kB), 0, s,
+                         reinterpret_cast<uint32_t*>(out->ph), (U + 3) / 4, 0u);
     hipLaunchKernelGGL((k_expand<G, WT, T, MODE>), dim3(grid_for(nbk, 1, 4096)), dim3(kB), 0, s, E,
                        op);
     PAULI_HIP(hipGetLastError());

@@ -99,6 +99,7 @@ def test_fullsize_1e8_products():
     GA, GB = pl.PauliSum.from_dict(A), pl.PauliSum.from_dict(B)
     out = pl.outer_product_merged(GA, GB)
     print("n=500 10,000 x 10,000: %d merged terms" % out.m, flush=True)
+    pl.trim_memory()  # torch allocates the exported copy
     T = out.export_torch()
     out.destroy()
     _check_order_and_distinct(T)
@@ -112,6 +113,7 @@ def test_fullsize_hermitian_square_4e8_products():
     G = pl.PauliSum.from_dict(H)
     out = pl.outer_product_merged(G, G)
     print("H*H with 20,000 terms: %d merged terms" % out.m, flush=True)
+    pl.trim_memory()  # torch allocates the exported copy
     T = out.export_torch()
     out.destroy()
     _check_order_and_distinct(T)
