@@ -49,7 +49,7 @@ constexpr int kSortWaves = kSortNT / 64;
 constexpr int kCap = 8192;  // records of a bucket sorted in LDS
 constexpr int kSortRounds = kCap / kSortWaves / 64;
 constexpr int kMaxBits = 16;
-constexpr double kTargetBucket = 4096.0;
+constexpr double kTargetBucket = 7000.0;  // records per bucket; the LDS sort takes up to kCap
 constexpr int kLong = 32;  // segments longer than this are reduced by a block
 constexpr int kRun = 4;    // records per lane group per chunk of the expand kernel
 
