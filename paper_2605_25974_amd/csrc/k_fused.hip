@@ -333,6 +333,173 @@ k_pscatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
   }
 }
 
+// ------------------------------ generation fused with the partition pass
+//
+// Record q of super-bucket s (in k_gen's order) belongs to the class tile
+// hA with Tt[s][hA] <= q < Tt[s][hA] + |A_hA| |B_{hA^s}|, the largest hA
+// with Tt[s][hA] <= q.  k_gcount and k_gscatter enumerate the records of
+// one partition tile that way, so the partition needs no stored copy of the
+// generated records: k_gcount histograms their digits, k_gscatter ranks
+// them and writes each record once, at its final place.
+
+struct GenSides {
+  const uint32_t* gA;
+  const uint32_t* gsA;
+  const uint32_t* sidxA;
+  const uint64_t* skeyA;
+  const uint32_t* gB;
+  const uint32_t* gsB;
+  const uint32_t* sidxB;
+  const uint64_t* skeyB;
+  const uint32_t* Tt;
+  uint32_t ma;
+  int ibits;
+  int d1;
+};
+
+// The super-bucket's tile offsets and class sizes, staged in LDS.
+struct GenRow {
+  uint32_t t[256], na[256], a0[256], nb[256], b0[256];
+};
+
+__device__ __forceinline__ void load_gen_row(const GenSides& G, uint32_t s, GenRow& R) {
+  const uint32_t nc = 1u << G.d1;
+  for (uint32_t h = threadIdx.x; h < nc; h += blockDim.x) {
+    R.t[h] = G.Tt[s * nc + h];
+    R.na[h] = G.gA[h];
+    R.a0[h] = G.gsA[h];
+    R.nb[h] = G.gB[h ^ s];
+    R.b0[h] = G.gsB[h ^ s];
+  }
+}
+
+__device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, uint32_t q,
+                                           uint64_t& key, uint32_t& val) {
+  uint32_t lo = 0, hi = 1u << G.d1;  // largest h with t[h] <= q
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (R.t[mid] <= q) lo = mid; else hi = mid;
+  }
+  const uint32_t t = q - R.t[lo], nb = R.nb[lo];
+  const uint32_t ia = t / nb, jb = t - ia * nb;
+  const uint32_t a = R.a0[lo] + ia, b = R.b0[lo] + jb;
+  const uint32_t i = G.sidxA[a], j = G.sidxB[b];
+  key = G.skeyA[a] ^ G.skeyB[b];
+  val = G.ibits >= 0 ? ((j << G.ibits) | i) : j * G.ma + i;
+}
+
+// Digit histogram of one partition tile (same count layout as k_pcount).
+__global__ void __launch_bounds__(kB)
+k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc,
+         int shift, uint32_t mask, uint32_t* __restrict__ C) {
+  __shared__ uint32_t hist[256];
+  __shared__ GenRow R;
+  uint32_t s, tl;
+  if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
+  hist[threadIdx.x] = 0;
+  load_gen_row(G, s, R);
+  __syncthreads();
+  const uint32_t lo = tl * kTile;
+  const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t q = lo + r * kB + threadIdx.x;
+    if (q < hi) {
+      uint64_t k;
+      uint32_t v;
+      gen_record(G, R, q, k, v);
+      atomicAdd(&hist[(k >> shift) & mask], 1u);
+    }
+  }
+  __syncthreads();
+  const uint32_t ns = tb[s + 1] - tb[s];
+  C[tb[s] * 256u + threadIdx.x * ns + tl] = hist[threadIdx.x];
+}
+
+// Stable scatter of one partition tile's generated records (wave-ballot
+// ranks, LDS staging, coalesced writes of each digit's run), as k_pscatter.
+__global__ void __launch_bounds__(kB)
+k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+           const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
+           uint32_t mask, const uint32_t* __restrict__ C) {
+  __shared__ uint64_t s_k[kTile];
+  __shared__ uint32_t s_v[kTile];
+  __shared__ uint32_t s_hist[256], s_start[256], s_run[256], s_goff[256];
+  __shared__ uint32_t s_wc[kB / 64][256];
+  __shared__ uint32_t sh[kB / 64];
+  __shared__ GenRow R;
+  uint32_t s, tl;
+  if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t lo = tl * kTile;
+  const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
+  const uint32_t ns = tb[s + 1] - tb[s];
+  s_hist[tid] = 0;
+  s_run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kB / 64; ++w) s_wc[w][tid] = 0;
+  s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
+  load_gen_row(G, s, R);
+  __syncthreads();
+  uint64_t k[kItems];
+  uint32_t v[kItems];
+  int d[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t q = lo + r * kB + tid;
+    if (q < hi) {
+      gen_record(G, R, q, k[r], v[r]);
+      d[r] = static_cast<int>((k[r] >> shift) & mask);
+      atomicAdd(&s_hist[d[r]], 1u);
+    } else {
+      k[r] = 0;
+      v[r] = 0;
+      d[r] = -1;
+    }
+  }
+  __syncthreads();
+  s_start[tid] = block_excl<kB / 64>(s_hist[tid], nullptr, sh);
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < kItems; ++r) {
+    const bool valid = d[r] >= 0;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool on = valid && ((d[r] >> b) & 1);
+      const uint64_t bm = __ballot(on);
+      peers &= on ? bm : ~bm;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) s_wc[wave][d[r]] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t off = s_start[d[r]] + s_run[d[r]];
+      for (int w = 0; w < wave; ++w) off += s_wc[w][d[r]];
+      off += rank;
+      s_k[off] = k[r];
+      s_v[off] = v[r];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kB / 64; ++w) {
+      add += s_wc[w][tid];
+      s_wc[w][tid] = 0;
+    }
+    s_run[tid] += add;
+    __syncthreads();
+  }
+  const uint32_t cnt = hi - lo;
+  for (uint32_t e = tid; e < cnt; e += kB) {
+    const uint64_t kk = s_k[e];
+    const uint32_t dd = static_cast<uint32_t>((kk >> shift) & mask);
+    const uint32_t g = s_goff[dd] + (e - s_start[dd]);
+    kout[g] = kk;
+    vout[g] = s_v[e];
+  }
+}
+
 // Bucket bk = (s, digit): first record.
 __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32_t* __restrict__ tb,
                                  const uint32_t* __restrict__ C, int d2, uint32_t nbk, uint32_t P,
@@ -1306,21 +1473,23 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   uint64_t* K2 = keys2.as<uint64_t>();
   uint32_t* V2 = vals2.as<uint32_t>();
   {
-    StageScope sc(PAULI_STAGE_SORT, s, P * (12.0 + (d2 ? 32.0 : 0.0)));
+    StageScope sc(PAULI_STAGE_SORT, s, P * 12.0);  // each record written once
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr32, 16u, 0u);
     hipLaunchKernelGGL(k_tile_table, dim3(nc), dim3(kB), 0, s, A.g.template as<uint32_t>(),
                        Bs.g.template as<uint32_t>(), d1, Tt.as<uint32_t>(), S.as<uint32_t>());
     DBuf w(scan_workspace_bytes(nc), s);
     scan_exclusive_u32(S.as<uint32_t>(), soff.as<uint32_t>(), nc, soff.as<uint32_t>() + nc, w.p,
                        s);
-    hipLaunchKernelGGL(k_gen, dim3(grid_for(static_cast<int64_t>(nc) * nc, 1, 16384)), dim3(kB), 0,
-                       s, A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
-                       A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
-                       Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
-                       Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, static_cast<uint32_t>(a->m),
-                       ibits, K, V);
+    if (d2 == 0)  // the super-buckets are the buckets
+      hipLaunchKernelGGL(k_gen, dim3(grid_for(static_cast<int64_t>(nc) * nc, 1, 16384)), dim3(kB),
+                         0, s, A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
+                         A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
+                         Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
+                         Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, static_cast<uint32_t>(a->m),
+                         ibits, K, V);
     PAULI_HIP(hipGetLastError());
     if (d2 > 0) {
+      // the records are generated straight into their buckets
       DBuf nt(nc * 4ull, s), tb(nc * 4ull + 4, s);
       hipLaunchKernelGGL(k_tiles_per_sb, dim3(grid_for(nc)), dim3(kB), 0, s, S.as<uint32_t>(), nc,
                          nt.as<uint32_t>());
@@ -1330,13 +1499,17 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
       DBuf C(static_cast<size_t>(gb) * 256 * 4, s);
       const int shift = kb - d;
       const uint32_t mask = (1u << d2) - 1u;
-      hipLaunchKernelGGL(k_pcount, dim3(gb), dim3(kB), 0, s, K, soff.as<uint32_t>(),
-                         S.as<uint32_t>(), tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
+      GenSides gs{A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
+                  A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
+                  Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
+                  Tt.as<uint32_t>(), static_cast<uint32_t>(a->m), ibits, d1};
+      hipLaunchKernelGGL(k_gcount, dim3(gb), dim3(kB), 0, s, gs, S.as<uint32_t>(),
+                         tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       DBuf w3(scan_workspace_bytes(static_cast<int64_t>(gb) * 256), s);
       scan_exclusive_u32(C.as<uint32_t>(), C.as<uint32_t>(), static_cast<int64_t>(gb) * 256,
                          nullptr, w3.p, s);
-      hipLaunchKernelGGL(k_pscatter, dim3(gb), dim3(kB), 0, s, K, V, K2, V2, soff.as<uint32_t>(),
-                         S.as<uint32_t>(), tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
+      hipLaunchKernelGGL(k_gscatter, dim3(gb), dim3(kB), 0, s, gs, K2, V2, S.as<uint32_t>(),
+                         tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       hipLaunchKernelGGL(k_bucket_offsets, dim3(grid_for(nbk + 1)), dim3(kB), 0, s,
                          soff.as<uint32_t>(), tb.as<uint32_t>(), C.as<uint32_t>(), d2, nbk, P,
                          boff.as<uint32_t>());
