@@ -223,116 +223,6 @@ __device__ __forceinline__ bool tile_of(uint32_t tau, const uint32_t* tb, uint32
   return true;
 }
 
-// Count layout: super-bucket s owns C[tb[s]*256, tb[s+1]*256) as [digit][tile],
-// so one exclusive scan of C gives every (s, digit, tile) its output offset.
-__global__ void __launch_bounds__(kB)
-k_pcount(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ soff,
-         const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
-         uint32_t mask, uint32_t* __restrict__ C) {
-  __shared__ uint32_t hist[256];
-  uint32_t s, tl;
-  if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
-  hist[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t lo = soff[s] + tl * kTile;
-  const uint32_t end = soff[s] + S[s];
-  const uint32_t hi = end - lo < kTile ? end : lo + kTile;
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t i = lo + r * kB + threadIdx.x;
-    if (i < hi) atomicAdd(&hist[(keys[i] >> shift) & mask], 1u);
-  }
-  __syncthreads();
-  const uint32_t ns = tb[s + 1] - tb[s];
-  C[tb[s] * 256u + threadIdx.x * ns + tl] = hist[threadIdx.x];
-}
-
-// Stable scatter of one tile (wave-ballot ranks, LDS staging, coalesced
-// writes of each digit's run).
-__global__ void __launch_bounds__(kB)
-k_pscatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-           const uint32_t* __restrict__ soff, const uint32_t* __restrict__ S,
-           const uint32_t* __restrict__ tb, uint32_t nc, int shift, uint32_t mask,
-           const uint32_t* __restrict__ C) {
-  __shared__ uint64_t s_k[kTile];
-  __shared__ uint32_t s_v[kTile];
-  __shared__ uint32_t s_hist[256], s_start[256], s_run[256], s_goff[256];
-  __shared__ uint32_t s_wc[kB / 64][256];
-  __shared__ uint32_t sh[kB / 64];
-  uint32_t s, tl;
-  if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t lo = soff[s] + tl * kTile;
-  const uint32_t end = soff[s] + S[s];
-  const uint32_t hi = end - lo < kTile ? end : lo + kTile;
-  const uint32_t ns = tb[s + 1] - tb[s];
-  s_hist[tid] = 0;
-  s_run[tid] = 0;
-#pragma unroll
-  for (int w = 0; w < kB / 64; ++w) s_wc[w][tid] = 0;
-  s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
-  __syncthreads();
-  uint64_t k[kItems];
-  uint32_t v[kItems];
-  int d[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t i = lo + r * kB + tid;
-    if (i < hi) {
-      k[r] = kin[i];
-      v[r] = vin[i];
-      d[r] = static_cast<int>((k[r] >> shift) & mask);
-      atomicAdd(&s_hist[d[r]], 1u);
-    } else {
-      k[r] = 0;
-      v[r] = 0;
-      d[r] = -1;
-    }
-  }
-  __syncthreads();
-  s_start[tid] = block_excl<kB / 64>(s_hist[tid], nullptr, sh);
-  __syncthreads();
-  const uint64_t lt = (1ull << lane) - 1ull;
-  for (int r = 0; r < kItems; ++r) {
-    const bool valid = d[r] >= 0;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool on = valid && ((d[r] >> b) & 1);
-      const uint64_t bm = __ballot(on);
-      peers &= on ? bm : ~bm;
-    }
-    const int rank = __popcll(peers & lt);
-    if (valid && rank == 0) s_wc[wave][d[r]] = static_cast<uint32_t>(__popcll(peers));
-    __syncthreads();
-    if (valid) {
-      uint32_t off = s_start[d[r]] + s_run[d[r]];
-      for (int w = 0; w < wave; ++w) off += s_wc[w][d[r]];
-      off += rank;
-      s_k[off] = k[r];
-      s_v[off] = v[r];
-    }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kB / 64; ++w) {
-      add += s_wc[w][tid];
-      s_wc[w][tid] = 0;
-    }
-    s_run[tid] += add;
-    __syncthreads();
-  }
-  const uint32_t cnt = hi - lo;
-  for (uint32_t e = tid; e < cnt; e += kB) {
-    const uint64_t kk = s_k[e];
-    const uint32_t dd = static_cast<uint32_t>((kk >> shift) & mask);
-    const uint32_t g = s_goff[dd] + (e - s_start[dd]);
-    kout[g] = kk;
-    vout[g] = s_v[e];
-  }
-}
-
 // ------------------------------ generation fused with the partition pass
 //
 // Record q of super-bucket s (in k_gen's order) belongs to the class tile
@@ -388,7 +278,9 @@ __device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, u
   val = G.ibits >= 0 ? ((j << G.ibits) | i) : j * G.ma + i;
 }
 
-// Digit histogram of one partition tile (same count layout as k_pcount).
+// Digit histogram of one partition tile.  Count layout: super-bucket s owns
+// C[tb[s]*256, tb[s+1]*256) as [digit][tile], so one exclusive scan of C
+// gives every (s, digit, tile) its output offset.
 __global__ void __launch_bounds__(kB)
 k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc,
          int shift, uint32_t mask, uint32_t* __restrict__ C) {
@@ -416,17 +308,22 @@ k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict_
   C[tb[s] * 256u + threadIdx.x * ns + tl] = hist[threadIdx.x];
 }
 
-// Stable scatter of one partition tile's generated records (wave-ballot
-// ranks, LDS staging, coalesced writes of each digit's run), as k_pscatter.
+// Stable scatter of one partition tile's generated records.  Wave w owns
+// the tile positions [w*kItems*64, (w+1)*kItems*64) in rounds of 64, so
+// ranking each wave's records by digit (ballots and a wave-private digit
+// counter, no block barrier) and adding the counts of earlier waves keeps
+// the tile's order within each digit.  The records are staged in LDS in
+// digit order and each digit's run is written coalesced.
 __global__ void __launch_bounds__(kB)
 k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
            const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
            uint32_t mask, const uint32_t* __restrict__ C) {
+  constexpr int NW = kB / 64;
   __shared__ uint64_t s_k[kTile];
   __shared__ uint32_t s_v[kTile];
-  __shared__ uint32_t s_hist[256], s_start[256], s_run[256], s_goff[256];
-  __shared__ uint32_t s_wc[kB / 64][256];
-  __shared__ uint32_t sh[kB / 64];
+  __shared__ uint32_t s_start[256], s_goff[256];
+  __shared__ uint32_t s_wc[NW][256];
+  __shared__ uint32_t sh[NW];
   __shared__ GenRow R;
   uint32_t s, tl;
   if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
@@ -434,62 +331,63 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
   const uint32_t lo = tl * kTile;
   const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
   const uint32_t ns = tb[s + 1] - tb[s];
-  s_hist[tid] = 0;
-  s_run[tid] = 0;
 #pragma unroll
-  for (int w = 0; w < kB / 64; ++w) s_wc[w][tid] = 0;
+  for (int w = 0; w < NW; ++w) s_wc[w][tid] = 0;
   s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
   load_gen_row(G, s, R);
   __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
   uint64_t k[kItems];
   uint32_t v[kItems];
   int d[kItems];
+  uint32_t rk[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const uint32_t q = lo + r * kB + tid;
+    const uint32_t q = lo + (static_cast<uint32_t>(wave) * kItems + r) * 64 + lane;
+    d[r] = -1;
+    k[r] = 0;
+    v[r] = 0;
     if (q < hi) {
       gen_record(G, R, q, k[r], v[r]);
       d[r] = static_cast<int>((k[r] >> shift) & mask);
-      atomicAdd(&s_hist[d[r]], 1u);
-    } else {
-      k[r] = 0;
-      v[r] = 0;
-      d[r] = -1;
     }
-  }
-  __syncthreads();
-  s_start[tid] = block_excl<kB / 64>(s_hist[tid], nullptr, sh);
-  __syncthreads();
-  const uint64_t lt = (1ull << lane) - 1ull;
-  for (int r = 0; r < kItems; ++r) {
     const bool valid = d[r] >= 0;
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool on = valid && ((d[r] >> b) & 1);
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = valid && ((d[r] >> bit) & 1);
       const uint64_t bm = __ballot(on);
       peers &= on ? bm : ~bm;
     }
-    const int rank = __popcll(peers & lt);
-    if (valid && rank == 0) s_wc[wave][d[r]] = static_cast<uint32_t>(__popcll(peers));
-    __syncthreads();
-    if (valid) {
-      uint32_t off = s_start[d[r]] + s_run[d[r]];
-      for (int w = 0; w < wave; ++w) off += s_wc[w][d[r]];
-      off += rank;
+    const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
+    uint32_t base = 0;
+    if (valid) base = s_wc[wave][d[r]];
+    rk[r] = base + rank;
+    if (valid && rank == 0) s_wc[wave][d[r]] = base + static_cast<uint32_t>(__popcll(peers));
+  }
+  __syncthreads();
+  // digit starts inside the tile, then each (wave, digit) start
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) tot += s_wc[w][tid];
+  const uint32_t dstart = block_excl<NW>(tot, nullptr, sh);
+  s_start[tid] = dstart;
+  uint32_t run = dstart;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t c = s_wc[w][tid];
+    s_wc[w][tid] = run;
+    run += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r)
+    if (d[r] >= 0) {
+      const uint32_t off = s_wc[wave][d[r]] + rk[r];
       s_k[off] = k[r];
       s_v[off] = v[r];
     }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kB / 64; ++w) {
-      add += s_wc[w][tid];
-      s_wc[w][tid] = 0;
-    }
-    s_run[tid] += add;
-    __syncthreads();
-  }
+  __syncthreads();
   const uint32_t cnt = hi - lo;
   for (uint32_t e = tid; e < cnt; e += kB) {
     const uint64_t kk = s_k[e];
