@@ -57,7 +57,8 @@ enum : uint32_t { kErrCollision = 1u };
 
 // Per-term data of an operand as four 64-bit words: the coefficient's real
 // and imaginary parts (one per word, in the sum's precision), the
-// fingerprint, and e = (phase + |X & Z|) mod 4.
+// fingerprint, and a word holding e = (phase + |X & Z|) mod 4 in bits 0-1,
+// the parity of |X & Z| in bit 2 and the term's class in bits 8 and up.
 template <typename T>
 struct alignas(32) Aux {
   uint64_t w[4];
@@ -133,11 +134,13 @@ __global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restri
     x.w[0] = to_word<T>(c[t].re);
     x.w[1] = to_word<T>(c[t].im);
     x.w[2] = fp[t];
-    x.w[3] = static_cast<uint64_t>((ph[t] + y) & 3);
-    aux[t] = x;
     const uint64_t k = fp[t] >> kshift;
+    const uint64_t c_id = d1 ? (k >> cshift) : 0ull;
+    x.w[3] = static_cast<uint64_t>((ph[t] + y) & 3) | (static_cast<uint64_t>(y & 1) << 2) |
+             (c_id << 8);
+    aux[t] = x;
     key[t] = k;
-    cls[t] = d1 ? (k >> cshift) : 0ull;
+    cls[t] = c_id;
     idx[t] = t;
   }
 }
@@ -166,12 +169,15 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
 }
 
 // Super-bucket s: T[s][hA] = offset of tile (hA, hA ^ s) inside s; S[s] = size.
+// With sym (a sum times itself) tiles with hA > hA ^ s are empty.
 __global__ void __launch_bounds__(kB)
-k_tile_table(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gB, int d1,
+k_tile_table(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gB, int d1, int sym,
              uint32_t* __restrict__ Tt, uint32_t* __restrict__ S) {
   __shared__ uint32_t sh[kB / 64];
   const uint32_t nc = 1u << d1, s = blockIdx.x, h = threadIdx.x;
-  const uint32_t size = h < nc ? gA[h] * gB[h ^ s] : 0u;
+  // a product of a sum with itself takes each unordered pair of classes once
+  const bool skip = sym && h > (h ^ s);
+  const uint32_t size = h < nc && !skip ? gA[h] * gB[h ^ s] : 0u;
   uint32_t tot;
   const uint32_t ex = block_excl<kB / 64>(size, &tot, sh);
   if (h < nc) Tt[s * nc + h] = ex;
@@ -184,12 +190,12 @@ k_gen(const uint32_t* __restrict__ gA, const uint32_t* __restrict__ gsA,
       const uint32_t* __restrict__ sidxA, const uint64_t* __restrict__ skeyA,
       const uint32_t* __restrict__ gB, const uint32_t* __restrict__ gsB,
       const uint32_t* __restrict__ sidxB, const uint64_t* __restrict__ skeyB,
-      const uint32_t* __restrict__ Tt, const uint32_t* __restrict__ soff, int d1, uint32_t ma,
-      int ibits, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+      const uint32_t* __restrict__ Tt, const uint32_t* __restrict__ soff, int d1, int sym,
+      uint32_t ma, int ibits, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   const uint32_t nc = 1u << d1, ntile = nc * nc;
   for (uint32_t tau = blockIdx.x; tau < ntile; tau += gridDim.x) {
     const uint32_t s = tau >> d1, hA = tau & (nc - 1), hB = hA ^ s;
-    const uint32_t na = gA[hA], nb = gB[hB], n = na * nb;
+    const uint32_t na = gA[hA], nb = gB[hB], n = sym && hA > hB ? 0u : na * nb;
     if (n == 0) continue;
     const uint32_t base = soff[s] + Tt[tau], a0 = gsA[hA], b0 = gsB[hB];
     for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
@@ -400,12 +406,12 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
 
 // Bucket bk = (s, digit): first record.
 __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32_t* __restrict__ tb,
-                                 const uint32_t* __restrict__ C, int d2, uint32_t nbk, uint32_t P,
+                                 const uint32_t* __restrict__ C, int d2, uint32_t nbk, uint32_t nc,
                                  uint32_t* __restrict__ boff) {
   const uint32_t mask = (1u << d2) - 1u;
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= nbk; b += gridDim.x * blockDim.x) {
     if (b == nbk) {
-      boff[b] = P;
+      boff[b] = soff[nc];  // all records
       continue;
     }
     const uint32_t s = b >> d2, dd = b & mask;
@@ -734,6 +740,7 @@ struct Operands {
   uint32_t ma;
   int ibits;  // pair id = (j << ibits) | i when ibits >= 0, else j*ma + i
   int nw;     // W
+  int sym;    // a sum times itself: records stand for unordered pairs
 };
 
 __device__ __forceinline__ void split_id(uint32_t id, uint32_t ma, int ibits, uint32_t& i,
@@ -764,6 +771,7 @@ struct Raw {
   static constexpr int PW = G >= 8 ? 1 : 8 / G;
   ulonglong2 a, b;
   uint64_t piece[PW];
+  int ij;  // sign of i - j
 };
 
 template <int G, int WT, typename T>
@@ -771,6 +779,7 @@ __device__ __forceinline__ Raw<G> issue_rec(const Operands<WT, T>& op, uint32_t 
   uint32_t i, j;
   split_id(id, op.ma, op.ibits, i, j);
   Raw<G> r;
+  r.ij = i < j ? -1 : (i > j ? 1 : 0);
   // a row is G 16-byte pieces, one per lane
   r.a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
   r.b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
@@ -785,7 +794,7 @@ __device__ __forceinline__ Raw<G> issue_rec(const Operands<WT, T>& op, uint32_t 
 // TS: type the operands' coefficients are stored in; TV: type the product
 // is computed in (the stored coefficients are rounded to TV first).
 template <int G, typename TS, typename TV>
-__device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl) {
+__device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl, int sym) {
   constexpr int PW = Raw<G>::PW;
   const int lane = threadIdx.x & 63, base = lane - gl;
   // metadata word k lives in lane k / PW of the group
@@ -815,19 +824,32 @@ __device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl) {
   }
   const uint64_t ar = word(0), ai = word(1), af = word(2), ae = word(3);
   const uint64_t br = word(4), bi = word(5), bf = word(6), be = word(7);
-  const int k = static_cast<int>(ae + be) + part;
+  const int k = static_cast<int>(ae + be) + part;  // bits 2 and up of e words add multiples of 4
   const cplx<TV> v =
       rot_ik(k, cmul(cplx<TV>{static_cast<TV>(from_word<TS>(ar)), static_cast<TV>(from_word<TS>(ai))},
                      cplx<TV>{static_cast<TV>(from_word<TS>(br)), static_cast<TV>(from_word<TS>(bi))}));
   r.re = v.re;
   r.im = v.im;
+  if (sym) {
+    // the pair stands for (i, j) and (j, i): their values are equal when the
+    // strings commute and opposite when they anticommute (the phases differ
+    // by 2 exactly then).  The parity of the anticommutation count is that
+    // of |X3 & Z3| + |Xa & Za| + |Xb & Zb|, and part = 2(..) - |X3 & Z3|.
+    const bool anti = ((part + static_cast<int>((ae >> 2) + (be >> 2))) & 1) != 0;
+    const bool same_class = (ae >> 8) == (be >> 8);
+    TV f = anti ? TV(0) : TV(2);
+    if (raw.ij == 0) f = TV(1);                        // i == j
+    else if (same_class && raw.ij > 0) f = TV(0);      // (j, i) of a diagonal tile: counted at (i, j)
+    r.re = f * r.re;
+    r.im = f * r.im;
+  }
   r.fp = af ^ bf;
   return r;
 }
 
 template <int G, int WT, typename TS, typename TV>
 __device__ __forceinline__ Rec<G, TV> load_rec(const Operands<WT, TS>& op, uint32_t id, int gl) {
-  return finish_rec<G, TS, TV>(issue_rec<G, WT, TS>(op, id, gl), gl);
+  return finish_rec<G, TS, TV>(issue_rec<G, WT, TS>(op, id, gl), gl, op.sym);
 }
 
 struct ExpandArgs {
@@ -1100,7 +1122,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
         }
         Rec<G, TV> rec[kRun];
 #pragma unroll
-        for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl);
+        for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl, op.sym);
         wave_sync();  // valid[] cleared before any stage_out
         if (p0 < n) {
           Acc<MODE, TV> acc;
@@ -1326,9 +1348,13 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
   const int W = a->W;
   const int Wp = G;  // G == 1 iff W == 1; otherwise the next power of two >= W
-  const uint32_t P = static_cast<uint32_t>(a->m * b->m);
+  const uint32_t P = static_cast<uint32_t>(a->m * b->m);  // bound on the records
+  // a sum times itself: one record per unordered pair (i, j), i <= j, in
+  // about half of the class tiles; the values carry the factor 2, 1 or 0
+  const bool same = a == b;
+  const double Peff = same ? 0.5 * P : double(P);
   const int kb = o.key_bits;
-  int d = o.bucket_bits > 0 ? o.bucket_bits : fused_default_bucket_bits(P, kb);
+  int d = o.bucket_bits > 0 ? o.bucket_bits : fused_default_bucket_bits(int64_t(Peff), kb);
   if (d > kMaxBits) d = kMaxBits;
   if (d > kb) d = kb;
   const int d1 = d < 8 ? d : 8;
@@ -1354,7 +1380,6 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   if ((static_cast<uint64_t>(b->m) << ibits) > 0xFFFFFFFFull) ibits = -1;
 
   SidePrep<T> A, B;
-  const bool same = a == b;
   {
     StageScope sc(PAULI_STAGE_PREP, s, (a->m + (same ? 0 : b->m)) * (16.0 * W + 32.0 * 2));
     prep_side<T>(a, Wp, kb, d1, A, s);
@@ -1371,10 +1396,11 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   uint64_t* K2 = keys2.as<uint64_t>();
   uint32_t* V2 = vals2.as<uint32_t>();
   {
-    StageScope sc(PAULI_STAGE_SORT, s, P * 12.0);  // each record written once
+    StageScope sc(PAULI_STAGE_SORT, s, Peff * 12.0);  // each record written once
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr32, 16u, 0u);
     hipLaunchKernelGGL(k_tile_table, dim3(nc), dim3(kB), 0, s, A.g.template as<uint32_t>(),
-                       Bs.g.template as<uint32_t>(), d1, Tt.as<uint32_t>(), S.as<uint32_t>());
+                       Bs.g.template as<uint32_t>(), d1, int(same), Tt.as<uint32_t>(),
+                       S.as<uint32_t>());
     DBuf w(scan_workspace_bytes(nc), s);
     scan_exclusive_u32(S.as<uint32_t>(), soff.as<uint32_t>(), nc, soff.as<uint32_t>() + nc, w.p,
                        s);
@@ -1383,8 +1409,8 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                          0, s, A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
                          A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
                          Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
-                         Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, static_cast<uint32_t>(a->m),
-                         ibits, K, V);
+                         Tt.as<uint32_t>(), soff.as<uint32_t>(), d1, int(same),
+                         static_cast<uint32_t>(a->m), ibits, K, V);
     PAULI_HIP(hipGetLastError());
     if (d2 > 0) {
       // the records are generated straight into their buckets
@@ -1409,7 +1435,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
       hipLaunchKernelGGL(k_gscatter, dim3(gb), dim3(kB), 0, s, gs, K2, V2, S.as<uint32_t>(),
                          tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       hipLaunchKernelGGL(k_bucket_offsets, dim3(grid_for(nbk + 1)), dim3(kB), 0, s,
-                         soff.as<uint32_t>(), tb.as<uint32_t>(), C.as<uint32_t>(), d2, nbk, P,
+                         soff.as<uint32_t>(), tb.as<uint32_t>(), C.as<uint32_t>(), d2, nbk, nc,
                          boff.as<uint32_t>());
       PAULI_HIP(hipGetLastError());
       std::swap(K, K2);
@@ -1423,7 +1449,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   DBuf heavy(nbk * 4ull, s), long_list(static_cast<size_t>(P / kLong + 2) * 8, s);
   SegOut so{V, segidx.as<uint32_t>(), nseg.as<uint32_t>(), long_list.as<uint32_t>(), ctr32 + 1};
   {
-    StageScope sc(PAULI_STAGE_SEGMENT, s, P * 20.0);
+    StageScope sc(PAULI_STAGE_SEGMENT, s, Peff * 20.0);
     hipLaunchKernelGGL(k_bucket_sort, dim3(nbk), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(), nbk,
                        sort_lo, passes, fmask, so, heavy.as<uint32_t>(), ctr32);
     hipLaunchKernelGGL(k_heavy_sort, dim3(64), dim3(kSortNT), 0, s, K, K2, V2, boff.as<uint32_t>(),
@@ -1444,10 +1470,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                ctr32 + 2, out->X, out->Z, out->ph, out->coef, out->fp, out->ld, o.tau};
   Operands<WT, T> op{A.rows.template as<uint64_t>(), Bs.rows.template as<uint64_t>(),
                      A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
-                     static_cast<uint32_t>(a->m), ibits, W};
+                     static_cast<uint32_t>(a->m), ibits, W, int(same)};
   {
     StageScope sc(PAULI_STAGE_WRITE, s,
-                  U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + P * 8.0);
+                  U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + Peff * 8.0);
     // merged terms carry phase 0 (the block of phase bytes is padded to 256)
     if (U > 0)
       hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((U + 3) / 4)), dim3(kB), 0, s,

@@ -142,6 +142,37 @@ def test_fused_hermitian_square():
     assert np.all(g["coef"].imag == 0)
 
 
+@pytest.mark.parametrize("n,m,pool", [(1, 40, 4), (5, 700, 300), (64, 900, 900),
+                                      (100, 1500, 1400), (200, 1100, 700), (500, 1300, 1300),
+                                      (1000, 300, 250)])
+def test_fused_self_product(n, m, pool):
+    """S*S with complex coefficients, arbitrary phases and repeated strings:
+    the fused path takes each unordered pair once (the symmetric form)."""
+    S = _dup_sum(90 + n, n, m, pool)
+    G = _gsum(S)
+    g = pl.outer_product_merged(G, G).export()
+    ref = O.product_merge(_osum(S), _osum(S))
+    parity.assert_merged_fp64(g, ref)
+    parity.assert_sorted_by_key(g)
+    g32 = pl.outer_product_merged(G, G, mode=pl.COMPENSATED, tau=0.3).export()
+    parity.assert_compensated(g32, ref)
+
+
+@pytest.mark.parametrize("n,m", [(40, 2600), (500, 3000)])
+def test_fused_self_product_matches_two_operand_form(n, m):
+    """At sizes with more than 256 buckets: S*S (symmetric form) against S*S'
+    with S' a separate copy of S (every ordered pair generated)."""
+    S = _dup_sum(95 + n, n, m, m // 2)
+    G, G2 = _gsum(S), _gsum(S)
+    sym = pl.outer_product_merged(G, G).export()
+    full = pl.outer_product_merged(G, G2).export()
+    for f in ("x", "z", "phase", "fp"):
+        assert np.array_equal(sym[f], full[f])
+    bound = 1e-12 * 64 * np.max(np.abs(S["coef"])) ** 2
+    assert np.max(np.abs(sym["coef"] - full["coef"])) <= bound
+    pl.trim_memory()
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 5])
 def test_fused_small_n_heavy_duplicates(n):
     A, B = _rand(20 + n, n, 4 ** n, wmax=n), _dup_sum(30 + n, n, 300, min(4 ** n, 10))
