@@ -7,29 +7,34 @@
 // the product XORs the symplectic bits, Section III-E).  The top d bits of
 // the key name the product's bucket.  Stages:
 //
-//  1 prep      per operand: row-major words, coefficient + phase + fp, key,
-//              and a stable sort of its terms by class (top d1 key bits).
-//  2 gen       records (key, pair id) written straight in top-d1-bit order:
-//              the products of class hA of a and class hB of b all have
-//              top bits hA ^ hB, so super-bucket s is the union of the
-//              class tiles (hA, hA ^ s), whose sizes and offsets follow from
-//              the class counts.  Every block writes one contiguous range.
-//  3 partition one stable radix pass per super-bucket on the next d2 bits.
-//  4 sort      per bucket, in LDS: stable radix sort on the 16 key bits below
+//  1 prep      per operand: rows of word pairs (X_w, Z_w), coefficient +
+//              fingerprint + phase metadata, key, and a stable sort of its
+//              terms by class (top d1 key bits).
+//  2 gen       the products of class hA of a and class hB of b all have top
+//              bits hA ^ hB, so super-bucket s is the union of the class
+//              tiles (hA, hA ^ s), whose sizes and offsets follow from the
+//              class counts.  Records (key, pair id) are generated tile by
+//              tile, counted by the next d2 key bits, and generated again
+//              straight into their buckets (each record written once).  For
+//              a sum times itself only the tiles hA <= hB are generated and
+//              each record stands for an unordered pair.
+//  3 sort      per bucket, in LDS: stable radix sort on the 16 key bits below
 //              the bucket bits, runs tied on those bits finished by insertion
 //              sort on the full key; writes the sorted pair ids and each
 //              record's segment index (equal keys = one segment).  Buckets
 //              too large for LDS are sorted on all remaining key bits by
 //              one block in global memory.
-//  5 scan      segment counts -> output offsets.
-//  6 expand    per record: a group of G lanes loads the record's two operand
+//  4 scan      segment counts -> output offsets.
+//  5 expand    per record: a group of G lanes loads the record's two operand
 //              rows with one 16-byte load per lane (one cache line per row),
-//              forms the product string and phase, and the segment's value
-//              i^k c_a c_b is summed in record order; each segment writes one
-//              merged term.  Equal keys are checked to be equal strings; a
-//              fingerprint collision raises a flag and the caller redoes the
-//              call with the general pipeline.  Segments longer than kLong
-//              records are summed by a whole block in a fixed tree.
+//              forms the product string and phase (cross-lane sums and
+//              broadcasts by DPP), and the segment's value i^k c_a c_b is
+//              summed in record order; each segment stages one merged term,
+//              and staged terms are stored in aligned blocks.  Equal keys are
+//              checked to be equal strings; a fingerprint collision raises a
+//              flag and the caller redoes the call with the general pipeline.
+//              Segments longer than kLong records are summed by a whole
+//              block in a fixed tree.
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -51,7 +56,8 @@ constexpr int kSortRounds = kCap / kSortWaves / 64;
 constexpr int kMaxBits = 16;
 constexpr double kTargetBucket = 7000.0;  // records per bucket; the LDS sort takes up to kCap
 constexpr int kLong = 32;  // segments longer than this are reduced by a block
-constexpr int kRun = 4;    // records per lane group per chunk of the expand kernel
+constexpr int kBS = 32;    // terms per aligned store block of the expand kernel
+constexpr int kParts = 4;  // work items per bucket of the expand kernel
 
 enum : uint32_t { kErrCollision = 1u };
 
@@ -126,8 +132,8 @@ __global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restri
     for (int w = 0; w < Wp; ++w) {
       const uint64_t x = w < W ? X[w * ld + t] : 0ull;
       const uint64_t z = w < W ? Z[w * ld + t] : 0ull;
-      rows[static_cast<size_t>(t) * 2 * Wp + w] = x;
-      rows[static_cast<size_t>(t) * 2 * Wp + Wp + w] = z;
+      rows[static_cast<size_t>(t) * 2 * Wp + 2 * w] = x;
+      rows[static_cast<size_t>(t) * 2 * Wp + 2 * w + 1] = z;
       y += popc64(x & z);
     }
     Aux<T> x;
@@ -733,7 +739,7 @@ k_heavy_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ tkeys,
 
 template <int WT, typename T>
 struct Operands {
-  const uint64_t* ra;  // [|a|][2*G] (X words, then Z words, each half padded)
+  const uint64_t* ra;  // [|a|][2*G]: word pairs (X_w, Z_w), padded to G pairs
   const uint64_t* rb;
   const Aux<T>* xa;
   const Aux<T>* xb;
@@ -754,23 +760,60 @@ __device__ __forceinline__ void split_id(uint32_t id, uint32_t ma, int ibits, ui
   }
 }
 
-// G lanes hold one record: lane l < G/2 the X words 2l, 2l+1 of the product
-// string, lane l >= G/2 the Z words; with G == 1 one lane holds X0 and Z0.
-// TV is the arithmetic type of the value.
+// Records per lane group per chunk of the expand kernel: 2 for groups of one
+// or two lanes (so that a wave's stage stays small), else 4.
+template <int G>
+struct Run {
+  static constexpr int v = G <= 2 ? 2 : 4;
+};
+
+// DPP moves (cross-lane operands inside rows of 16 lanes, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = dpp32<CTRL>(static_cast<uint32_t>(v));
+  const uint32_t hi = dpp32<CTRL>(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+constexpr int kDppSwap1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane l <- lane 7 - l of each 8
+constexpr int kDppRowMirror = 0x140;   // lane l <- lane 15 - l of each 16
+
+// Sum of v over the G lanes of a group (groups of G <= 16 aligned lanes).
+template <int G>
+__device__ __forceinline__ int group_sum(int v) {
+  if constexpr (G >= 2) v += static_cast<int>(dpp32<kDppSwap1>(static_cast<uint32_t>(v)));
+  if constexpr (G >= 4) v += static_cast<int>(dpp32<kDppSwap2>(static_cast<uint32_t>(v)));
+  if constexpr (G >= 8) v += static_cast<int>(dpp32<kDppHalfMirror>(static_cast<uint32_t>(v)));
+  if constexpr (G >= 16) v += static_cast<int>(dpp32<kDppRowMirror>(static_cast<uint32_t>(v)));
+  return v;
+}
+
+// G lanes hold one record: lane l holds word l of the product string's X and
+// Z parts (rows are laid out as word pairs (X_w, Z_w)).  TV is the arithmetic
+// type of the value.
 template <int G, typename TV>
 struct Rec {
-  uint64_t w0, w1;  // this lane's two product words
-  TV re, im;        // value i^k c_a c_b (same in every lane of the group)
+  uint64_t w0, w1;  // X and Z word gl of the product string
+  TV re, im;        // value i^k c_a c_b (the same in every lane of the group)
   uint64_t fp;
 };
 
-// Raw loads of one record: this lane's 16-byte pieces of the two operand
-// rows, and its share of the 8 metadata words (aux of a_i, then of b_j).
+// Raw loads of one record: this lane's pieces (X_gl, Z_gl) of the two operand
+// rows, and 16-byte pieces of the two metadata records.  Metadata piece k
+// holds words 2(k & 1), 2(k & 1) + 1 of a's record (k < 2) or of b's
+// (k >= 2).  In groups of four or more lanes every lane loads piece gl & 3;
+// a pair loads pieces gl and gl + 2; a single lane loads all four.
 template <int G>
 struct Raw {
-  static constexpr int PW = G >= 8 ? 1 : 8 / G;
+  static constexpr int NP = G >= 4 ? 1 : 4 / G;
   ulonglong2 a, b;
-  uint64_t piece[PW];
+  ulonglong2 piece[NP];
   int ij;  // sign of i - j
 };
 
@@ -780,50 +823,48 @@ __device__ __forceinline__ Raw<G> issue_rec(const Operands<WT, T>& op, uint32_t 
   split_id(id, op.ma, op.ibits, i, j);
   Raw<G> r;
   r.ij = i < j ? -1 : (i > j ? 1 : 0);
-  // a row is G 16-byte pieces, one per lane
   r.a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
   r.b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
 #pragma unroll
-  for (int p = 0; p < Raw<G>::PW; ++p) {
-    const int k = gl * Raw<G>::PW + p;
-    r.piece[p] = k < 4 ? op.xa[i].w[k & 3] : (k < 8 ? op.xb[j].w[k & 3] : 0ull);
+  for (int p = 0; p < Raw<G>::NP; ++p) {
+    const int k = G >= 4 ? (gl & 3) : gl + p * G;
+    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(k < 2 ? op.xa[i].w : op.xb[j].w);
+    r.piece[p] = src[k & 1];
   }
   return r;
+}
+
+// Word H of metadata piece K in every lane of the group (its low BITS bits).
+template <int G, int K, int H, int BITS>
+__device__ __forceinline__ uint64_t meta_word(const Raw<G>& raw) {
+  if constexpr (G == 1) {
+    return H ? raw.piece[K].y : raw.piece[K].x;
+  } else {
+    const ulonglong2 p = raw.piece[G == 2 ? (K >> 1) : 0];
+    const uint64_t v = H ? p.y : p.x;
+    // from lane K & 1 of each pair, or lane K of each quad
+    constexpr int C = G == 2 ? ((K & 1) ? 0xF5 : 0xA0) : K * 0x55;
+    if constexpr (BITS == 32) return dpp32<C>(static_cast<uint32_t>(v));
+    else return dpp64<C>(v);
+  }
 }
 
 // TS: type the operands' coefficients are stored in; TV: type the product
 // is computed in (the stored coefficients are rounded to TV first).
 template <int G, typename TS, typename TV>
 __device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl, int sym) {
-  constexpr int PW = Raw<G>::PW;
-  const int lane = threadIdx.x & 63, base = lane - gl;
-  // metadata word k lives in lane k / PW of the group
-  auto word = [&](int k) -> uint64_t {
-    if (G == 1) return raw.piece[k];
-    return __shfl(raw.piece[k % PW], base + k / PW, 64);
-  };
+  (void)gl;
   const ulonglong2 a = raw.a, b = raw.b;
   Rec<G, TV> r;
   r.w0 = a.x ^ b.x;
   r.w1 = a.y ^ b.y;
-  int part;
-  if (G == 1) {
-    // a.x = X_a, a.y = Z_a; b.x = X_b, b.y = Z_b
-    part = 2 * popc64(a.y & b.x) - popc64(r.w0 & r.w1);
-  } else {
-    constexpr int half = G / 2;
-    // the Z words of the same indices live half lanes up
-    const uint64_t za0 = __shfl(a.x, lane + half, 64), za1 = __shfl(a.y, lane + half, 64);
-    const uint64_t z30 = __shfl(r.w0, lane + half, 64), z31 = __shfl(r.w1, lane + half, 64);
-    part = 0;
-    if (gl < half)
-      part = 2 * (popc64(za0 & b.x) + popc64(za1 & b.y)) - popc64(r.w0 & z30) - popc64(r.w1 & z31);
-#pragma unroll
-    for (int off = half / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    part = __shfl(part, base, 64);
-  }
-  const uint64_t ar = word(0), ai = word(1), af = word(2), ae = word(3);
-  const uint64_t br = word(4), bi = word(5), bf = word(6), be = word(7);
+  // 2 |Z_a & X_b| - |X_3 & Z_3| over the words of the strings
+  const int part = group_sum<G>(2 * popc64(a.y & b.x) - popc64(r.w0 & r.w1));
+  constexpr int CB = static_cast<int>(sizeof(TS)) * 8;
+  const uint64_t ar = meta_word<G, 0, 0, CB>(raw), ai = meta_word<G, 0, 1, CB>(raw);
+  const uint64_t af = meta_word<G, 1, 0, 64>(raw), ae = meta_word<G, 1, 1, 32>(raw);
+  const uint64_t br = meta_word<G, 2, 0, CB>(raw), bi = meta_word<G, 2, 1, CB>(raw);
+  const uint64_t bf = meta_word<G, 3, 0, 64>(raw), be = meta_word<G, 3, 1, 32>(raw);
   const int k = static_cast<int>(ae + be) + part;  // bits 2 and up of e words add multiples of 4
   const cplx<TV> v =
       rot_ik(k, cmul(cplx<TV>{static_cast<TV>(from_word<TS>(ar)), static_cast<TV>(from_word<TS>(ai))},
@@ -859,37 +900,35 @@ struct ExpandArgs {
   const uint32_t* segoff;  // [bucket] first output index
   uint32_t nbk;
   uint32_t* err;
+  uint32_t* work;  // work-item counter of k_expand, zero at launch
   uint64_t* OX;
   uint64_t* OZ;
   uint8_t* Oph;
   void* Oc;
   uint64_t* Ofp;
-  int64_t ldo;
-  double tau;  // cancellation threshold of the compensated form
+  int64_t ldo;  // a multiple of kBS
+  double tau;   // cancellation threshold of the compensated form
 };
 
-// Merged terms of one wave chunk, staged for coalesced stores.
-template <int WT, typename T, int RB>
+// Merged terms of a wave, staged for aligned coalesced stores: a ring of CAP
+// slots, output term o in slot o mod CAP.  The x and z rows are one word
+// longer than CAP so that the words a lane group writes for one slot fall in
+// different banks.
+template <int WT, typename T, int CAP>
 struct Stage {
-  uint64_t x[WT][RB];
-  uint64_t z[WT][RB];
-  cplx<T> c[RB];
-  uint64_t fp[RB];
-  uint8_t valid[RB];
+  uint64_t x[WT][CAP + 1];
+  uint64_t z[WT][CAP + 1];
+  cplx<T> c[CAP];
+  uint64_t fp[CAP];
+  uint8_t valid[CAP];
 };
 
-template <int G, int WT, typename T, int RB, typename TV>
-__device__ __forceinline__ void stage_out(Stage<WT, T, RB>& st, int nw, int gl, uint32_t slot,
+template <int G, int WT, typename T, int CAP, typename TV>
+__device__ __forceinline__ void stage_out(Stage<WT, T, CAP>& st, int nw, int gl, uint32_t slot,
                                           const Rec<G, TV>& r, T re, T im) {
-  if (G == 1) {
-    st.x[0][slot] = r.w0;
-    st.z[0][slot] = r.w1;
-  } else {
-    constexpr int half = G / 2;
-    const int base = 2 * (gl < half ? gl : gl - half);
-    uint64_t(*D)[RB] = gl < half ? st.x : st.z;
-    if (base < nw) D[base][slot] = r.w0;
-    if (base + 1 < nw) D[base + 1][slot] = r.w1;
+  if (gl < nw) {
+    st.x[gl][slot] = r.w0;
+    st.z[gl][slot] = r.w1;
   }
   if (gl == 0) {
     st.c[slot] = cplx<T>{re, im};
@@ -918,282 +957,269 @@ __device__ __noinline__ cplx<double> remerge64(const ExpandArgs& E, const Operan
   return {re, im};
 }
 
-// Segment indices and ids of the kRun records of a lane group's run, as
+// Segment indices and ids of the KR records of a lane group's run, as
 // loaded by the lane (distributed over the group's lanes when G allows).
 template <int G>
 struct Meta {
-  static constexpr bool kSplit = G >= kRun + 2;
-  uint32_t ms[kSplit ? 1 : kRun + 2];
-  uint32_t mi[kSplit ? 1 : kRun];
+  static constexpr int KR = Run<G>::v;
+  static constexpr bool kSplit = G >= KR + 2;
+  uint32_t ms[kSplit ? 1 : KR + 2];
+  uint32_t mi[kSplit ? 1 : KR];
 };
 
 // Every lane issues the same loads whatever the chunk's position (indices
-// past the bucket are clamped to its last record), so a chunk issues a fixed
-// number of memory operations.  The loaded words are kept as loaded; the
-// past-the-end substitutions happen in unpack_meta, one chunk later, so the
-// loads are not waited for (together with older stores) when they are issued.
-// n >= 1.
+// past the bucket are clamped to its last record).  The loaded words are kept
+// as loaded; the past-the-end substitutions happen in unpack_meta, one chunk
+// later, so the loads are not waited for when they are issued.  n >= 1.
 template <int G>
 __device__ __forceinline__ Meta<G> fetch_meta(const ExpandArgs& E, uint32_t lo, uint32_t n,
                                               uint32_t p0, int gl) {
+  constexpr int KR = Run<G>::v;
   Meta<G> m;
   const uint32_t last = n - 1;
   auto at = [&](uint32_t q) { return lo + (q < n ? q : last); };
   if (Meta<G>::kSplit) {
-    // lane gl: record p0 + gl (gl <= kRun), or the record before the run
-    const uint32_t q = gl <= kRun ? p0 + gl : (p0 ? p0 - 1 : 0u);
+    // lane gl: record p0 + gl (gl <= KR), or the record before the run
+    const uint32_t q = gl <= KR ? p0 + gl : (p0 ? p0 - 1 : 0u);
     m.ms[0] = E.segidx[at(q)];
     m.mi[0] = E.vals[at(q)];
   } else {
 #pragma unroll
-    for (int t = 0; t <= kRun; ++t) m.ms[t] = E.segidx[at(p0 + t)];
-    m.ms[kRun + 1] = E.segidx[at(p0 ? p0 - 1 : 0u)];
+    for (int t = 0; t <= KR; ++t) m.ms[t] = E.segidx[at(p0 + t)];
+    m.ms[KR + 1] = E.segidx[at(p0 ? p0 - 1 : 0u)];
 #pragma unroll
-    for (int t = 0; t < kRun; ++t) m.mi[t] = E.vals[at(p0 + t)];
+    for (int t = 0; t < KR; ++t) m.mi[t] = E.vals[at(p0 + t)];
   }
   return m;
 }
 
-// Segment indices sid[0..kRun] of the run's records (0xFFFFFFFE past the
+// Segment indices sid[0..KR] of the run's records (0xFFFFFFFE past the
 // bucket), their ids (0 past the bucket: a valid pair) and the segment index
 // of the record before the run (0xFFFFFFFF at the bucket's start).
 template <int G>
 __device__ __forceinline__ void unpack_meta(const Meta<G>& m, int gl, uint32_t n, uint32_t p0,
                                             uint32_t* sid, uint32_t* ids, uint32_t& sprev) {
+  constexpr int KR = Run<G>::v;
   if (Meta<G>::kSplit) {
     const int base = (threadIdx.x & 63) - gl;
 #pragma unroll
-    for (int t = 0; t <= kRun; ++t) sid[t] = __shfl(m.ms[0], base + t, 64);
+    for (int t = 0; t <= KR; ++t) sid[t] = __shfl(m.ms[0], base + t, 64);
 #pragma unroll
-    for (int t = 0; t < kRun; ++t) ids[t] = __shfl(m.mi[0], base + t, 64);
-    sprev = __shfl(m.ms[0], base + kRun + 1, 64);
+    for (int t = 0; t < KR; ++t) ids[t] = __shfl(m.mi[0], base + t, 64);
+    sprev = __shfl(m.ms[0], base + KR + 1, 64);
   } else {
 #pragma unroll
-    for (int t = 0; t <= kRun; ++t) sid[t] = m.ms[t];
+    for (int t = 0; t <= KR; ++t) sid[t] = m.ms[t];
 #pragma unroll
-    for (int t = 0; t < kRun; ++t) ids[t] = m.mi[t];
-    sprev = m.ms[kRun + 1];
+    for (int t = 0; t < KR; ++t) ids[t] = m.mi[t];
+    sprev = m.ms[KR + 1];
   }
 #pragma unroll
-  for (int t = 0; t <= kRun; ++t)
+  for (int t = 0; t <= KR; ++t)
     if (p0 + t >= n) sid[t] = 0xFFFFFFFEu;
 #pragma unroll
-  for (int t = 0; t < kRun; ++t)
+  for (int t = 0; t < KR; ++t)
     if (p0 + t >= n) ids[t] = 0u;
   if (!(p0 && p0 < n)) sprev = 0xFFFFFFFFu;
 }
 
-// Buffer stores: a lane whose offset is beyond the resource's byte range
-// writes nothing, so every chunk issues the same store instructions whatever
-// it holds.  Resource word 3 for gfx9-family buffers; cache policy bit 1 =
-// non-temporal (the output is not read again by this kernel).
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-constexpr int kRsrcWord3 = 0x00020000;
-constexpr int kNonTemporal = 2;
-constexpr uint32_t kOff = 0x40000000u;  // beyond every range used here
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes),
-                                           kRsrcWord3);
-}
-
-__device__ __forceinline__ u32x2 halves(uint64_t v) {
-  return u32x2{static_cast<unsigned>(v), static_cast<unsigned>(v >> 32)};
-}
-
-// Stores the cnt staged terms of a chunk at output positions ob, ob+1, ...
-// (cnt == 0 issues the same instructions and writes nothing).  The phase
-// bytes of the output (all zero) are filled separately.
-template <int WT, typename TV, int RB>
-__device__ __forceinline__ void store_chunk(const ExpandArgs& E, const Stage<WT, TV, RB>& st,
-                                            int nw, int64_t ob, uint32_t cnt, int lane) {
+// Stores the staged terms o in [o_lo, o_hi) of the aligned block
+// [B, B + kBS) (every 8-byte array gets whole 128-byte lines when the block
+// is complete): lanes 0-31 write the X words and lanes 32-63 the Z words of
+// one word index per instruction; 16-byte coefficients are written as two
+// halves, lanes 0-31 the real and lanes 32-63 the imaginary parts.  Clears
+// the block's slots afterwards.
+template <int WT, typename TV, int CAP>
+__device__ __forceinline__ void store_block(const ExpandArgs& E, Stage<WT, TV, CAP>& st, int nw,
+                                            uint32_t B, uint32_t o_lo, uint32_t o_hi, int lane) {
+  const uint32_t t = static_cast<uint32_t>(lane & (kBS - 1));
+  const bool upper = lane >= kBS;
+  const uint32_t o = B + t;
+  const uint32_t slot = o & (CAP - 1);
+  const bool live = o >= o_lo && o < o_hi && st.valid[slot];
 #pragma unroll
-  for (int r = 0; r < (RB + 63) / 64; ++r) {
-    const uint32_t kk = static_cast<uint32_t>(r * 64 + lane);
-    const uint32_t ks = kk < static_cast<uint32_t>(RB) ? kk : 0u;
-    const bool live = kk < cnt && st.valid[ks];
-    const uint32_t o8 = live ? kk * 8u : kOff;
-#pragma unroll
-    for (int w = 0; w < WT; ++w) {
-      const uint32_t bytes = w < nw ? cnt * 8u : 0u;
-      __builtin_amdgcn_raw_buffer_store_b64(halves(st.x[w][ks]), out_rsrc(E.OX + w * E.ldo + ob, bytes),
-                                            o8, 0, kNonTemporal);
-      __builtin_amdgcn_raw_buffer_store_b64(halves(st.z[w][ks]), out_rsrc(E.OZ + w * E.ldo + ob, bytes),
-                                            o8, 0, kNonTemporal);
+  for (int w = 0; w < WT; ++w) {
+    if (w < nw) {
+      const uint64_t v = upper ? st.z[w][slot] : st.x[w][slot];
+      uint64_t* dst = (upper ? E.OZ : E.OX) + static_cast<int64_t>(w) * E.ldo + o;
+      if (live) __builtin_nontemporal_store(v, dst);
     }
-    const cplx<TV> c = st.c[ks];
-    cplx<TV>* oc = static_cast<cplx<TV>*>(E.Oc) + ob;
-    if constexpr (sizeof(TV) == 8) {
-      const u32x2 re = halves(to_word<TV>(c.re)), im = halves(to_word<TV>(c.im));
-      __builtin_amdgcn_raw_buffer_store_b128(u32x4{re.x, re.y, im.x, im.y}, out_rsrc(oc, cnt * 16u),
-                                             live ? kk * 16u : kOff, 0, kNonTemporal);
-    } else {
-      const u32x2 v{static_cast<unsigned>(to_word<TV>(c.re)), static_cast<unsigned>(to_word<TV>(c.im))};
-      __builtin_amdgcn_raw_buffer_store_b64(v, out_rsrc(oc, cnt * 8u), o8, 0, kNonTemporal);
-    }
-    __builtin_amdgcn_raw_buffer_store_b64(halves(st.fp[ks]), out_rsrc(E.Ofp + ob, cnt * 8u), o8, 0,
-                                          kNonTemporal);
   }
+  const cplx<TV> c = st.c[slot];
+  const uint64_t f = st.fp[slot];
+  if constexpr (sizeof(TV) == 8) {
+    uint64_t* dst = reinterpret_cast<uint64_t*>(static_cast<cplx<TV>*>(E.Oc) + o) + (upper ? 1 : 0);
+    if (live) __builtin_nontemporal_store(to_word<TV>(upper ? c.im : c.re), dst);
+    if (live && !upper) __builtin_nontemporal_store(f, E.Ofp + o);
+  } else {
+    // lanes 0-31 the coefficient (two floats), lanes 32-63 the fingerprint
+    const uint64_t cw = (to_word<TV>(c.im) << 32) | (to_word<TV>(c.re) & 0xFFFFFFFFull);
+    uint64_t* dst = upper ? E.Ofp + o : reinterpret_cast<uint64_t*>(static_cast<cplx<TV>*>(E.Oc) + o);
+    if (live) __builtin_nontemporal_store(upper ? f : cw, dst);
+  }
+  wave_sync();  // the slots are read before they are cleared
+  if (!upper) st.valid[slot] = 0;
 }
 
-// Buckets are spread over blocks; inside a bucket every wave independently
-// takes super-chunks of RS consecutive records (no block barriers).  A
-// super-chunk is SUB sub-chunks of RB records (RS >= 64, so that every store
-// instruction has a term per lane); group g of the wave takes kRun records of
-// each sub-chunk and handles every segment whose first record lies there
-// (continuing past the run when the segment does), except segments longer
-// than kLong, which k_expand_long sums.  The terms of a super-chunk's
-// segments form one contiguous output range: they are staged in the wave's
-// LDS region and stored coalesced, array by array.
+// Work items are quarters of buckets (kParts record ranges of equal length),
+// taken from a counter by each wave.  A wave handles the segments whose first
+// record lies in its range, chunk by chunk (RS records per chunk; group g of
+// the wave takes KR consecutive records of a chunk and follows a segment past
+// them when it continues, except segments longer than kLong, which
+// k_expand_long sums).  The range's terms form one contiguous output range:
+// they are staged in the wave's ring and stored in aligned blocks of kBS
+// terms as the blocks fill, so that only the range's first and last blocks
+// write partial lines.
 //
-// Loads and stores share one in-order completion counter per wave, so a wait
-// for a load also waits for every store issued before it.  The loop is
-// therefore pipelined: the ids two sub-chunks ahead and the row/metadata
-// gathers of the next sub-chunk are issued before the current one is
-// processed, and the stores of a super-chunk are issued after the gathers of
-// the next one.  Every iteration issues the same memory operations, so no
-// wait for a gather ever waits for an older store.
+// The ids two chunks ahead and the row/metadata gathers of the next chunk are
+// issued before a chunk is processed.
 template <int G, int WT, typename T, int MODE>
-__global__ void __launch_bounds__(kB, 3)
+__global__ void __launch_bounds__(kB, G >= 16 ? 2 : 3)
 k_expand(ExpandArgs E, Operands<WT, T> op) {
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
+  constexpr int KR = Run<G>::v;
   constexpr int NG = 64 / G;  // groups per wave
-  constexpr int RB = NG * kRun;
-  constexpr int SUB = RB >= 64 ? 1 : 64 / RB;
-  constexpr int RS = RB * SUB;
+  constexpr uint32_t RS = NG * KR;
+  constexpr int CAP = RS + kBS <= 64 ? 64 : (RS + kBS <= 128 ? 128 : 256);
+  static_assert(RS + kBS <= CAP, "ring too small");
   constexpr int NW = kB / 64;
-  constexpr uint32_t STEP = NW * RS;
-  __shared__ Stage<WT, TV, RS> stage[NW];
+  __shared__ Stage<WT, TV, CAP> stage[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  Stage<WT, TV, RS>& st = stage[wave];
+  Stage<WT, TV, CAP>& st = stage[wave];
   const int g = lane / G, gl = lane % G;
   const int nw = op.nw;
-  const uint32_t goff = static_cast<uint32_t>(g) * kRun;
+  const uint32_t goff = static_cast<uint32_t>(g) * KR;
+  const uint32_t items = E.nbk * kParts;
   uint64_t coll = 0;
-  for (uint32_t b = blockIdx.x; b < E.nbk; b += gridDim.x) {
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(E.work, 1u);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= items) break;
+    const uint32_t b = item / kParts, part = item % kParts;
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
+    const uint32_t q_beg = static_cast<uint32_t>(static_cast<uint64_t>(n) * part / kParts);
+    const uint32_t q_end = static_cast<uint32_t>(static_cast<uint64_t>(n) * (part + 1) / kParts);
+    if (q_beg >= q_end) continue;
     const uint32_t obase = E.segoff[b];
-    uint32_t R0 = static_cast<uint32_t>(wave) * RS;
-    if (R0 >= n) continue;
-    // start of the k-th sub-chunk counted from the super-chunk at R
-    auto sub_at = [&](uint32_t R, int k) {
-      return R + static_cast<uint32_t>(k / SUB) * STEP + static_cast<uint32_t>(k % SUB) * RB;
-    };
-    // pipeline prologue: ids of sub-chunks 0 and 1, gathers of sub-chunk 0
-    Meta<G> m_cur = fetch_meta<G>(E, lo, n, sub_at(R0, 0) + goff, gl);
-    Meta<G> m_next = fetch_meta<G>(E, lo, n, sub_at(R0, 1) + goff, gl);
-    uint32_t sid[kRun + 1], ids[kRun], sprev;
-    unpack_meta<G>(m_cur, gl, n, R0 + goff, sid, ids, sprev);
+    for (int k = lane; k < CAP; k += 64) st.valid[k] = 0;
+    // pipeline prologue: ids of chunks 0 and 1, gathers of chunk 0
+    const Meta<G> m_cur = fetch_meta<G>(E, lo, n, q_beg + goff, gl);
+    Meta<G> m_next = fetch_meta<G>(E, lo, n, q_beg + RS + goff, gl);
+    uint32_t sid[KR + 1], ids[KR], sprev;
+    unpack_meta<G>(m_cur, gl, n, q_beg + goff, sid, ids, sprev);
     // ids past the bucket's end read as 0, a valid pair: the gathers are
     // issued unconditionally so that no stale registers stay live
-    Raw<G> raw[kRun];
+    Raw<G> raw[KR];
 #pragma unroll
-    for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
-    // the same stores as a super-chunk's, writing nothing: the loop is
-    // entered with the memory operations after the gathers that every
-    // iteration has
-    store_chunk<WT, TV, RS>(E, st, nw, static_cast<int64_t>(obase), 0u, lane);
-    for (; R0 < n; R0 += STEP) {
-      for (int kk = lane; kk < RS; kk += 64) st.valid[kk] = 0;
-      // the super-chunk's last record
-      const uint32_t last = (R0 + RS < n ? R0 + RS : n) - 1;
-      uint32_t sfirst = 0, cnt = 0;
-#pragma unroll
-      for (int sub = 0; sub < SUB; ++sub) {
-        const uint32_t c0 = R0 + static_cast<uint32_t>(sub) * RB;
-        const uint32_t p0 = c0 + goff;
-        const Meta<G> m_after = fetch_meta<G>(E, lo, n, sub_at(R0, sub + 2) + goff, gl);
-        if (sub == 0) {
-          // first segment with its first record in the super-chunk
-          const uint32_t s_at0 = __shfl(sid[0], 0, 64);
-          const uint32_t s_before = __shfl(sprev, 0, 64);
-          sfirst = s_at0 == s_before ? s_at0 + 1 : s_at0;
-        }
-        if (last >= c0 && last < c0 + RB) {
-          // the super-chunk's last segment, from the group holding its last record
-          const uint32_t rl = last - c0;
-          uint32_t s_mine = sid[0];
-#pragma unroll
-          for (int t = 1; t < kRun; ++t)
-            if (static_cast<int>(rl % kRun) == t) s_mine = sid[t];
-          const uint32_t s_last = __shfl(s_mine, static_cast<int>((rl / kRun) * G), 64);
-          cnt = s_last + 1 > sfirst ? s_last + 1 - sfirst : 0u;
-        }
-        Rec<G, TV> rec[kRun];
-#pragma unroll
-        for (int t = 0; t < kRun; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl, op.sym);
-        wave_sync();  // valid[] cleared before any stage_out
-        if (p0 < n) {
-          Acc<MODE, TV> acc;
-          acc.zero();
-          uint64_t h0 = 0, h1 = 0, diff = 0;
-          bool open = false;
-          int t_head = 0;
-          Rec<G, TV> first;
-          // stages segment [q0, q1) (bucket positions) once its sum is known
-          auto emit = [&](uint32_t slot, uint32_t q0, uint32_t q1) {
-            TV vr = acc.value_re(), vi = acc.value_im();
-            if (MODE == kComp && acc.cancels(E.tau)) {
-              const cplx<double> c = remerge64<G, WT, T>(E, op, lo, q0, q1, gl);
-              vr = static_cast<TV>(c.re);
-              vi = static_cast<TV>(c.im);
-            }
-            stage_out<G, WT, TV, RS, TV>(st, nw, gl, slot, first, vr, vi);
-          };
-#pragma unroll
-          for (int t = 0; t < kRun; ++t) {
-            if (p0 + t >= n) break;
-            const bool head = sid[t] != (t ? sid[t - 1] : sprev);
-            if (head) {
-              open = true;
-              t_head = t;
-              acc.begin(rec[t].re, rec[t].im);
-              first = rec[t];
-              h0 = rec[t].w0;
-              h1 = rec[t].w1;
-            } else if (open) {
-              acc.add(rec[t].re, rec[t].im);
-              diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
-            }
-            const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
-            if (open && ends) {
-              emit(sid[t] - sfirst, p0 + t_head, p0 + t + 1);
-              open = false;
-            }
-          }
-          if (open) {
-            // the run's last segment continues past the run: follow it,
-            // unless it is longer than kLong (then k_expand_long sums it)
-            const uint32_t s_cur = sid[kRun - 1];
-            uint32_t len = static_cast<uint32_t>(kRun - t_head);
-            uint32_t q = p0 + kRun;
-            bool is_long = false;
-            while (q < n && E.segidx[lo + q] == s_cur) {
-              if (++len > static_cast<uint32_t>(kLong)) {
-                is_long = true;
-                break;
-              }
-              const Rec<G, TV> r = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
-              acc.add(r.re, r.im);
-              diff |= (r.w0 ^ h0) | (r.w1 ^ h1);
-              ++q;
-            }
-            if (!is_long) emit(s_cur - sfirst, p0 + t_head, q);
-          }
-          coll |= diff;  // an equal key must be an equal string
-        }
-        // gathers of the next sub-chunk
-        const uint32_t pn = sub_at(R0, sub + 1) + goff;
-        unpack_meta<G>(m_next, gl, n, pn, sid, ids, sprev);
-#pragma unroll
-        for (int t = 0; t < kRun; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
-        m_next = m_after;
-      }
-      wave_sync();
-      store_chunk<WT, TV, RS>(E, st, nw, static_cast<int64_t>(obase) + sfirst, cnt, lane);
-      wave_sync();  // the stage is reused by the next super-chunk
+    for (int t = 0; t < KR; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
+    // output terms [A, Ew) are staged and not yet stored; Bk = A rounded
+    // down to a block
+    uint32_t A, Bk, Ew;
+    {
+      const uint32_t s_at0 = __builtin_amdgcn_readfirstlane(__shfl(sid[0], 0, 64));
+      const uint32_t s_before = __builtin_amdgcn_readfirstlane(__shfl(sprev, 0, 64));
+      A = obase + (s_at0 == s_before ? s_at0 + 1 : s_at0);
+      Bk = A & ~static_cast<uint32_t>(kBS - 1);
+      Ew = A;
     }
+    for (uint32_t R0 = q_beg; R0 < q_end; R0 += RS) {
+      const uint32_t p0 = R0 + goff;
+      const Meta<G> m_after = fetch_meta<G>(E, lo, n, R0 + 2 * RS + goff, gl);
+      {
+        // the chunk's last record (inside the range) and its segment
+        const uint32_t rl = (R0 + RS < q_end ? R0 + RS : q_end) - 1 - R0;
+        uint32_t s_mine = sid[0];
+#pragma unroll
+        for (int t = 1; t < KR; ++t)
+          if (static_cast<int>(rl % KR) == t) s_mine = sid[t];
+        const uint32_t s_last = __builtin_amdgcn_readfirstlane(
+            __shfl(s_mine, static_cast<int>((rl / KR) * G), 64));
+        if (obase + s_last + 1 > Ew) Ew = obase + s_last + 1;
+      }
+      Rec<G, TV> rec[KR];
+#pragma unroll
+      for (int t = 0; t < KR; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl, op.sym);
+      wave_sync();  // slots cleared before any stage_out
+      if (p0 < q_end) {
+        Acc<MODE, TV> acc;
+        acc.zero();
+        uint64_t h0 = 0, h1 = 0, diff = 0;
+        bool open = false;
+        int t_head = 0;
+        Rec<G, TV> first;
+        // stages segment [q0, q1) (bucket positions) once its sum is known
+        auto emit = [&](uint32_t seg, uint32_t q0, uint32_t q1) {
+          TV vr = acc.value_re(), vi = acc.value_im();
+          if (MODE == kComp && acc.cancels(E.tau)) {
+            const cplx<double> c = remerge64<G, WT, T>(E, op, lo, q0, q1, gl);
+            vr = static_cast<TV>(c.re);
+            vi = static_cast<TV>(c.im);
+          }
+          stage_out<G, WT, TV, CAP, TV>(st, nw, gl, (obase + seg) & (CAP - 1), first, vr, vi);
+        };
+        bool next_part = false;  // a segment head past the range: the rest is not ours
+#pragma unroll
+        for (int t = 0; t < KR; ++t) {
+          if (next_part || p0 + t >= n) break;
+          const bool head = sid[t] != (t ? sid[t - 1] : sprev);
+          if (head) {
+            if (p0 + t >= q_end) {
+              next_part = true;
+              break;
+            }
+            open = true;
+            t_head = t;
+            acc.begin(rec[t].re, rec[t].im);
+            first = rec[t];
+            h0 = rec[t].w0;
+            h1 = rec[t].w1;
+          } else if (open) {
+            acc.add(rec[t].re, rec[t].im);
+            diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
+          }
+          const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
+          if (open && ends) {
+            emit(sid[t], p0 + t_head, p0 + t + 1);
+            open = false;
+          }
+        }
+        if (open) {
+          // the run's last segment continues past the run: follow it,
+          // unless it is longer than kLong (then k_expand_long sums it)
+          const uint32_t s_cur = sid[KR - 1];
+          uint32_t len = static_cast<uint32_t>(KR - t_head);
+          uint32_t q = p0 + KR;
+          bool is_long = false;
+          while (q < n && E.segidx[lo + q] == s_cur) {
+            if (++len > static_cast<uint32_t>(kLong)) {
+              is_long = true;
+              break;
+            }
+            const Rec<G, TV> r2 = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
+            acc.add(r2.re, r2.im);
+            diff |= (r2.w0 ^ h0) | (r2.w1 ^ h1);
+            ++q;
+          }
+          if (!is_long) emit(s_cur, p0 + t_head, q);
+        }
+        coll |= diff;  // an equal key must be an equal string
+      }
+      // gathers of the next chunk
+      unpack_meta<G>(m_next, gl, n, R0 + RS + goff, sid, ids, sprev);
+#pragma unroll
+      for (int t = 0; t < KR; ++t) raw[t] = issue_rec<G, WT, T>(op, ids[t], gl);
+      m_next = m_after;
+      wave_sync();  // staged terms visible to every lane
+      // blocks completed by this chunk
+      while (Bk + kBS <= Ew) {
+        store_block<WT, TV, CAP>(E, st, nw, Bk, A, Bk + kBS, lane);
+        Bk += kBS;
+        A = Bk;
+      }
+    }
+    // the range's last, partial block
+    if (A < Ew) store_block<WT, TV, CAP>(E, st, nw, Bk, A, Ew, lane);
   }
   if (__any(coll != 0) && lane == 0) atomicOr(E.err, kErrCollision);
 }
@@ -1201,15 +1227,9 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
 template <int G, typename TO, typename TV>
 __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, int64_t o,
                                           const Rec<G, TV>& r, TO re, TO im) {
-  if (G == 1) {
-    E.OX[o] = r.w0;
-    E.OZ[o] = r.w1;
-  } else {
-    constexpr int half = G / 2;
-    const int base = 2 * (gl < half ? gl : gl - half);
-    uint64_t* D = gl < half ? E.OX : E.OZ;
-    if (base < nw) D[static_cast<int64_t>(base) * E.ldo + o] = r.w0;
-    if (base + 1 < nw) D[static_cast<int64_t>(base + 1) * E.ldo + o] = r.w1;
+  if (gl < nw) {
+    E.OX[static_cast<int64_t>(gl) * E.ldo + o] = r.w0;
+    E.OZ[static_cast<int64_t>(gl) * E.ldo + o] = r.w1;
   }
   if (gl == 0) {
     E.Oph[o] = 0;
@@ -1465,9 +1485,12 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   PAULI_HIP(hipStreamSynchronize(s));
   const uint32_t U = host[3];
 
-  paulisum* out = new_sum(a->n, U, U, MODE == kComp ? PAULI_C64 : a->dtype, s);
+  // the leading dimension is a multiple of the store block, so that blocks
+  // of every output array start on a 256-byte boundary
+  const int64_t ldo = (static_cast<int64_t>(U) + kBS - 1) / kBS * kBS;
+  paulisum* out = new_sum(a->n, U, ldo, MODE == kComp ? PAULI_C64 : a->dtype, s);
   ExpandArgs E{boff.as<uint32_t>(), V, segidx.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
-               ctr32 + 2, out->X, out->Z, out->ph, out->coef, out->fp, out->ld, o.tau};
+               ctr32 + 2, ctr32 + 4, out->X, out->Z, out->ph, out->coef, out->fp, out->ld, o.tau};
   Operands<WT, T> op{A.rows.template as<uint64_t>(), Bs.rows.template as<uint64_t>(),
                      A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
                      static_cast<uint32_t>(a->m), ibits, W, int(same)};
@@ -1478,7 +1501,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
     if (U > 0)
       hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((U + 3) / 4)), dim3(kB), 0, s,
                          reinterpret_cast<uint32_t*>(out->ph), (U + 3) / 4, 0u);
-    hipLaunchKernelGGL((k_expand<G, WT, T, MODE>), dim3(grid_for(nbk, 1, 4096)), dim3(kB), 0, s, E,
+    hipLaunchKernelGGL((k_expand<G, WT, T, MODE>), dim3(nbk < 1024u ? nbk : 1024u), dim3(kB), 0, s, E,
                        op);
     PAULI_HIP(hipGetLastError());
   }
