@@ -45,7 +45,7 @@ WORKLOADS = {
 }
 # sources of the kernel each stage's traffic figure was measured on
 STAGE_SOURCES = {
-    "write": ["paper_2605_25974_amd/csrc/k_fused.hip", "paper_2605_25974_amd/csrc/common.h"],
+    "write": ["paper_2605_25974_amd/csrc/expand.h", "paper_2605_25974_amd/csrc/common.h"],
 }
 COPY_BYTES = 2 << 30
 
