@@ -405,7 +405,6 @@ __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32
 struct SortSmem {
   uint64_t key[kCap];
   uint32_t id[kCap];
-  uint16_t ord[kCap];
   uint32_t cnt[kSortWaves][256];
   uint32_t scan[kSortWaves];
   uint32_t wcount[kSortWaves];
@@ -415,13 +414,16 @@ __device__ __forceinline__ uint32_t sort_span(uint32_t N) {
   return ((N + 64 * kSortWaves - 1) / (64 * kSortWaves)) * 64;
 }
 
-// ord[0..N) = entries ordered stably by key bits [lo, lo + 8*passes).  Wave w
-// owns positions [w*span, (w+1)*span) in rounds of 64; the rank of an entry
-// among equal digits counts equal digits at earlier positions (eight ballots
-// per round and per-wave digit counters).
-__device__ void lds_sort(uint32_t N, int lo, int passes, SortSmem& S) {
-  for (uint32_t q = threadIdx.x; q < N; q += kSortNT) S.ord[q] = static_cast<uint16_t>(q);
-  __syncthreads();
+// Stable LSD radix sort of the (key, id) pairs k[], v[] of a bucket on key
+// bits [lo, lo + 8*passes).  Wave w holds positions [w*span, (w+1)*span) in
+// rounds of 64 (item r of a lane: position w*span + r*64 + lane); the rank of
+// an item among equal digits counts equal digits at earlier positions (eight
+// ballots per round and per-wave digit counters).  Each pass scatters the
+// pairs to their new positions in LDS and reads back the lane's positions;
+// on return S.key / S.id hold the bucket in sorted order and k[], v[] the
+// lane's items of it.
+__device__ void lds_sort(uint32_t N, int lo, int passes, uint64_t (&k)[kSortRounds],
+                         uint32_t (&v)[kSortRounds], SortSmem& S) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t span = sort_span(N);
@@ -430,15 +432,14 @@ __device__ void lds_sort(uint32_t N, int lo, int passes, SortSmem& S) {
     const int shift = lo + 8 * pass;
     for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortNT) (&S.cnt[0][0])[i] = 0;
     __syncthreads();
-    uint16_t ent[kSortRounds], rk[kSortRounds];
+    uint16_t rk[kSortRounds];
     uint8_t dg[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
       if (r >= rounds) break;
       const uint32_t q = wave * span + r * 64 + lane;
       const bool valid = q < N;
-      ent[r] = valid ? S.ord[q] : 0;
-      const int dgt = valid ? static_cast<int>((S.key[ent[r]] >> shift) & 255) : 0;
+      const int dgt = valid ? static_cast<int>((k[r] >> shift) & 255) : 0;
       dg[r] = static_cast<uint8_t>(dgt);
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -467,52 +468,60 @@ __device__ void lds_sort(uint32_t N, int lo, int passes, SortSmem& S) {
       }
     }
     __syncthreads();
-    uint32_t np[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
       if (r >= rounds) break;
       const uint32_t q = wave * span + r * 64 + lane;
-      np[r] = q < N ? S.cnt[wave][dg[r]] + rk[r] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-      if (r >= rounds) break;
-      const uint32_t q = wave * span + r * 64 + lane;
-      if (q < N) S.ord[np[r]] = ent[r];
+      if (q < N) {
+        const uint32_t np = S.cnt[wave][dg[r]] + rk[r];
+        S.key[np] = k[r];
+        S.id[np] = v[r];
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      if (q < N) {
+        k[r] = S.key[q];
+        v[r] = S.id[q];
+      }
+    }
   }
 }
 
 // Runs of positions tied on the radix field but holding different full keys
-// are put in (key, entry) order by the thread owning the run's first position.
-__device__ void lds_fix_runs(uint32_t N, int lo, uint64_t fmask, SortSmem& S) {
+// are put in key order (stable: equal keys keep their order) by the thread
+// owning the run's first position.  Returns whether anything moved (then the
+// lanes' register copies are stale).
+__device__ bool lds_fix_runs(uint32_t N, int lo, uint64_t fmask, SortSmem& S) {
   bool dirty = false;
   for (uint32_t q = threadIdx.x + 1; q < N; q += kSortNT) {
-    const uint64_t k1 = S.key[S.ord[q - 1]], k2 = S.key[S.ord[q]];
+    const uint64_t k1 = S.key[q - 1], k2 = S.key[q];
     if (k1 != k2 && ((k1 >> lo) & fmask) == ((k2 >> lo) & fmask)) dirty = true;
   }
-  if (!__syncthreads_or(dirty)) return;
+  if (!__syncthreads_or(dirty)) return false;
   for (uint32_t q = threadIdx.x; q < N; q += kSortNT) {
-    const uint64_t f = (S.key[S.ord[q]] >> lo) & fmask;
-    if (q > 0 && ((S.key[S.ord[q - 1]] >> lo) & fmask) == f) continue;
+    const uint64_t f = (S.key[q] >> lo) & fmask;
+    if (q > 0 && ((S.key[q - 1] >> lo) & fmask) == f) continue;
     uint32_t e = q + 1;
-    while (e < N && ((S.key[S.ord[e]] >> lo) & fmask) == f) ++e;
+    while (e < N && ((S.key[e] >> lo) & fmask) == f) ++e;
     for (uint32_t x = q + 1; x < e; ++x) {
-      const uint16_t v = S.ord[x];
-      const uint64_t kv = S.key[v];
+      const uint64_t kv = S.key[x];
+      const uint32_t iv = S.id[x];
       int y = static_cast<int>(x) - 1;
-      while (y >= static_cast<int>(q)) {
-        const uint16_t u = S.ord[y];
-        const uint64_t ku = S.key[u];
-        if (ku < kv || (ku == kv && u < v)) break;
-        S.ord[y + 1] = u;
+      while (y >= static_cast<int>(q) && S.key[y] > kv) {
+        S.key[y + 1] = S.key[y];
+        S.id[y + 1] = S.id[y];
         --y;
       }
-      S.ord[y + 1] = v;
+      S.key[y + 1] = kv;
+      S.id[y + 1] = iv;
     }
   }
   __syncthreads();
+  return true;
 }
 
 struct SegOut {
@@ -536,21 +545,59 @@ k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bo
     if (threadIdx.x == 0) heavy[atomicAdd(nheavy, 1u)] = b;
     return;
   }
-  for (uint32_t q = threadIdx.x; q < n; q += kSortNT) {
-    S.key[q] = keys[lo + q];
-    S.id[q] = out.vals[lo + q];
-  }
-  __syncthreads();
-  lds_sort(n, sort_lo, passes, S);
-  lds_fix_runs(n, sort_lo, fmask, S);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t span = sort_span(n);
+  const int rounds = static_cast<int>(span / 64);
+  uint64_t k[kSortRounds];
+  uint32_t v[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    k[r] = 0;
+    v[r] = 0;
+    if (r >= rounds) continue;
+    const uint32_t q = wave * span + r * 64 + lane;
+    if (q < n) {
+      k[r] = keys[lo + q];
+      v[r] = out.vals[lo + q];
+    }
+  }
+  if (passes > 0) {
+    lds_sort(n, sort_lo, passes, k, v, S);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      if (q < n) {
+        S.key[q] = k[r];
+        S.id[q] = v[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (lds_fix_runs(n, sort_lo, fmask, S)) {
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      if (q < n) {
+        k[r] = S.key[q];
+        v[r] = S.id[q];
+      }
+    }
+  }
+  // segment heads (a key differing from the one before), counted per wave
+  uint64_t hb[kSortRounds];
   uint32_t hc = 0;
-  for (uint32_t r = 0; r * 64 < span; ++r) {
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    hb[r] = 0;
+    if (r >= rounds) break;
     const uint32_t q = wave * span + r * 64 + lane;
     bool head = false;
-    if (q < n) head = q == 0 || S.key[S.ord[q - 1]] != S.key[S.ord[q]];
-    hc += static_cast<uint32_t>(__popcll(__ballot(head)));
+    if (q < n) head = q == 0 || S.key[q - 1] != k[r];
+    hb[r] = __ballot(head);
+    hc += static_cast<uint32_t>(__popcll(hb[r]));
   }
   if (lane == 0) S.wcount[wave] = hc;
   __syncthreads();
@@ -560,38 +607,29 @@ k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bo
     total += S.wcount[w];
   }
   const uint64_t lt = (1ull << lane) - 1ull;
-  for (uint32_t r = 0; r * 64 < span; ++r) {
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (r >= rounds) break;
     const uint32_t q = wave * span + r * 64 + lane;
-    bool head = false;
-    uint32_t e = 0;
     if (q < n) {
-      e = S.ord[q];
-      head = q == 0 || S.key[S.ord[q - 1]] != S.key[e];
-    }
-    const uint64_t hb = __ballot(head);
-    if (q < n) {
-      const uint32_t seg = run + static_cast<uint32_t>(__popcll(hb & (lt | (1ull << lane)))) - 1;
-      out.vals[lo + q] = S.id[e];
+      const uint32_t seg = run + static_cast<uint32_t>(__popcll(hb[r] & (lt | (1ull << lane)))) - 1;
+      out.vals[lo + q] = v[r];
       out.segidx[lo + q] = seg;
-    }
-    run += static_cast<uint32_t>(__popcll(hb));
-  }
-  if (threadIdx.x == 0) out.nseg[b] = total;
-  // segments longer than kLong: queued for the block-wide reduction
-  for (uint32_t r = 0; r * 64 < span; ++r) {
-    const uint32_t q = wave * span + r * 64 + lane;
-    if (q < n && (q == 0 || S.key[S.ord[q - 1]] != S.key[S.ord[q]])) {
-      const uint64_t k = S.key[S.ord[q]];
-      const uint32_t lim = q + kLong + 1 < n ? q + kLong + 1 : n;
-      uint32_t e = q + 1;
-      while (e < lim && S.key[S.ord[e]] == k) ++e;
-      if (e - q > static_cast<uint32_t>(kLong)) {
-        const uint32_t slot = atomicAdd(out.nlong, 1u);
-        out.long_list[2 * slot] = b;
-        out.long_list[2 * slot + 1] = q;
+      if ((hb[r] >> lane) & 1) {
+        // segments longer than kLong: queued for the block-wide reduction
+        const uint32_t lim = q + kLong + 1 < n ? q + kLong + 1 : n;
+        uint32_t e = q + 1;
+        while (e < lim && S.key[e] == k[r]) ++e;
+        if (e - q > static_cast<uint32_t>(kLong)) {
+          const uint32_t slot = atomicAdd(out.nlong, 1u);
+          out.long_list[2 * slot] = b;
+          out.long_list[2 * slot + 1] = q;
+        }
       }
     }
+    run += static_cast<uint32_t>(__popcll(hb[r]));
   }
+  if (threadIdx.x == 0) out.nseg[b] = total;
 }
 
 // Buckets larger than kCap: one block sorts the bucket's records on all key
