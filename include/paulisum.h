@@ -156,6 +156,21 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
                                           const pauli_merge_opts_t* opts, paulisum_t* out,
                                           void* stream);
 
+/* pauli_commutator: [a, b] = a*b - b*a, merged.  A pair of strings
+ * commutes or anticommutes by the parity of its symplectic product
+ * (Section III-F); a_i b_j - b_j a_i is 2 a_i b_j for an anticommuting pair
+ * and zero for a commuting one (the commutator evaluation the conclusion
+ * lists as planned work).  The output holds one term per string that at
+ * least one anticommuting pair gives, with coefficient
+ * sum over those pairs of 2 i^k c_a c_b, in the order and form of
+ * pauli_merge (phase 0, zeros kept unless opts->drop_abs removes them).
+ * Strings that only commuting pairs give are absent; [a, a] holds every
+ * string of an anticommuting pair of a with coefficient exactly 0.
+ * opts as pauli_merge (the compensated mode applies as in
+ * pauli_outer_product_merged).  Errors as pauli_outer_product. */
+pauli_status_t pauli_commutator(paulisum_t a, paulisum_t b, const pauli_merge_opts_t* opts,
+                                paulisum_t* out, void* stream);
+
 /* pauli_outer_product_batched: nb independent fused products
  * out[t] = merge(a[t] * b[t]) with one set of merge options; the pairs may
  * differ in qubit count and term counts but a[t], b[t] must agree with each

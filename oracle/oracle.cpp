@@ -357,6 +357,36 @@ void* oracle_product_merge(int n, int64_t m1, const uint64_t* x1, const uint64_t
   return finish(n, acc, drop_abs);
 }
 
+// The commutator [H1, H2] = H1*H2 - H2*H1, merged.  For each pair both
+// orders are multiplied letter by letter; when the two products differ (the
+// strings anticommute, Section II-C, and the phases differ by 2), the pair
+// contributes a_i b_j - b_j a_i to the product's string, summed exactly.
+// Pairs whose two orders agree contribute nothing and create no term.
+void* oracle_commutator(int n, int64_t m1, const uint64_t* x1, const uint64_t* z1,
+                        const uint8_t* ph1, const double* c1, int64_t m2, const uint64_t* x2,
+                        const uint64_t* z2, const uint8_t* ph2, const double* c2,
+                        double drop_abs) {
+  const Sum A{n, m1, x1, z1, ph1, c1}, B{n, m2, x2, z2, ph2, c2};
+  std::vector<std::string> la;
+  for (int64_t i = 0; i < m1; ++i) la.push_back(A.letters(i));
+  std::map<std::string, Acc> acc;
+  std::string ab, ba;
+  for (int64_t j = 0; j < m2; ++j) {
+    const std::string lb = B.letters(j);
+    for (int64_t i = 0; i < m1; ++i) {
+      const int kab = multiply(la[static_cast<size_t>(i)], lb, ab);
+      const int kba = multiply(lb, la[static_cast<size_t>(i)], ba);
+      if (ab != ba) return nullptr;  // both orders give one string; cannot fail
+      if (((kab - kba) & 3) == 0) continue;  // the orders agree: no contribution
+      const int k = A.phase(i) + B.phase(j);
+      Acc& a = acc[ab];
+      add_product(a, kab + k, c1[2 * i], c1[2 * i + 1], c2[2 * j], c2[2 * j + 1]);
+      add_product(a, kba + k + 2, c1[2 * i], c1[2 * i + 1], c2[2 * j], c2[2 * j + 1]);  // minus b_j a_i
+    }
+  }
+  return finish(n, acc, drop_abs);
+}
+
 // A sequence of rotation steps (Section II-D eq. (5)) applied to the merged
 // input sum.  Step s uses the string (px, pz)[s] and angle theta[s]; mode 0
 // multiplies every term on the left by cos(theta) I - i sin(theta) P, mode 1

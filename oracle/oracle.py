@@ -72,6 +72,9 @@ def lib():
         L.oracle_product_coeff.restype = _int
         L.oracle_product_coeff.argtypes = (
             [_int] + [_i64, _u64p, _u64p, _u8p, _f64p] * 2 + [_i64, _u64p, _u64p, _f64p, _f64p, _i64p])
+        L.oracle_commutator.restype = ctypes.c_void_p
+        L.oracle_commutator.argtypes = (
+            [_int] + [_i64, _u64p, _u64p, _u8p, _f64p] * 2 + [ctypes.c_double])
         L.oracle_propagate.restype = ctypes.c_void_p
         L.oracle_propagate.argtypes = (
             [_int, _i64, _u64p, _u64p, _u8p, _f64p, _int, _u64p, _u64p, _f64p, _int,
@@ -193,6 +196,16 @@ def product_merge(a: Sum, b: Sum, drop_abs: float = -1.0, i_range=None, j_range=
     i0, i1 = i_range if i_range is not None else (0, a.m)
     j0, j1 = j_range if j_range is not None else (0, b.m)
     h = lib().oracle_product_merge(a.n, *a._args(), *b._args(), float(drop_abs), i0, i1, j0, j1)
+    return _take(a.n, h)
+
+
+def commutator(a: Sum, b: Sum, drop_abs: float = -1.0) -> Merged:
+    """[H1, H2] = H1*H2 - H2*H1 merged exactly: the strings that an
+    anticommuting pair gives, each with the exact sum of a_i b_j - b_j a_i."""
+    assert a.n == b.n
+    h = lib().oracle_commutator(a.n, *a._args(), *b._args(), float(drop_abs))
+    if not h:
+        raise RuntimeError("oracle_commutator failed")
     return _take(a.n, h)
 
 

@@ -29,7 +29,7 @@ EXPORTS = (
     "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
-    "pauli_trim_memory",
+    "pauli_trim_memory", "pauli_commutator",
 )
 STAGES = ("outer_product", "prep", "sort", "segment", "write", "long")
 
@@ -95,6 +95,8 @@ def lib():
     L.pauli_outer_product_merged.restype = st
     L.pauli_outer_product_merged.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts),
                                              ctypes.POINTER(_vp), _vp]
+    L.pauli_commutator.restype = st
+    L.pauli_commutator.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
     L.pauli_outer_product_batched.restype = st
     L.pauli_outer_product_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
                                               ctypes.POINTER(_vp), ctypes.POINTER(MergeOpts),
@@ -278,6 +280,17 @@ def outer_product_merged(a: PauliSum, b: PauliSum, mode=PLAIN, drop_abs=-1.0, ta
     o = _opts(mode, drop_abs, tau, key_bits)
     _check(lib().pauli_outer_product_merged(a.handle, b.handle, ctypes.byref(o),
                                             ctypes.byref(out), _stream(stream)))
+    return PauliSum(out)
+
+
+def commutator(a: PauliSum, b: PauliSum, mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0,
+               stream=None) -> PauliSum:
+    """[a, b] = a*b - b*a, merged (pauli_commutator): one term per string that
+    an anticommuting pair gives, coefficient sum of 2 i^k c_a c_b."""
+    out = _vp()
+    o = _opts(mode, drop_abs, tau, key_bits)
+    _check(lib().pauli_commutator(a.handle, b.handle, ctypes.byref(o), ctypes.byref(out),
+                                  _stream(stream)))
     return PauliSum(out)
 
 

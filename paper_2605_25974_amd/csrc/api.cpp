@@ -447,6 +447,38 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
   });
 }
 
+pauli_status_t pauli_commutator(paulisum_t a, paulisum_t b, const pauli_merge_opts_t* opts,
+                                paulisum_t* out, void* stream) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_pair(a, b);
+    MergeArgs m = merge_args(opts);
+    use_device(a);
+    hipStream_t s = as_stream(stream);
+    a->last_stream = b->last_stream = s;
+    paulisum* r = nullptr;
+    if (a->m > 0 && b->m > 0) {
+      MergeArgs mc = m;
+      mc.comm = 1;
+      r = fused_bucket(a, b, mc, s);
+      if (!r) {
+        // a fingerprint collision: merge the materialised anticommuting products
+        paulisum* prods = commutator_products(a, b, s);
+        try {
+          r = merge_generic(prods, nullptr, m, s);
+        } catch (...) {
+          free_sum(prods);
+          throw;
+        }
+        free_sum(prods);
+      }
+    } else {
+      r = merge_generic(a, b, m, s);  // empty
+    }
+    *out = r;
+  });
+}
+
 pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
                                            const pauli_merge_opts_t* opts,
                                            const pauli_tune_t* tune, paulisum_t* out,

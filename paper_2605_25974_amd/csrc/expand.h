@@ -20,6 +20,13 @@ constexpr int kParts = 4;  // work items per bucket of the expand kernel
 
 enum : uint32_t { kErrCollision = 1u };
 
+// What a record stands for.
+//   kFormProduct: the product a_i b_j;
+//   kFormSym:     a sum times itself, one record per unordered pair;
+//   kFormComm:    the commutator [a, b] = ab - ba: a_i b_j - b_j a_i is
+//                 2 a_i b_j for an anticommuting pair and nothing otherwise.
+enum : int { kFormProduct = 0, kFormSym = 1, kFormComm = 2 };
+
 // Per-term data of an operand as four 64-bit words: the coefficient's real
 // and imaginary parts (one per word, in the sum's precision), the
 // fingerprint, and a word holding e = (phase + |X & Z|) mod 4 in bits 0-1,
@@ -50,7 +57,7 @@ struct Operands {
   uint32_t ma;
   int ibits;  // pair id = (j << ibits) | i when ibits >= 0, else j*ma + i
   int nw;     // W
-  int sym;    // a sum times itself: records stand for unordered pairs
+  int form;   // kFormProduct, kFormSym or kFormComm
 };
 
 __device__ __forceinline__ void split_id(uint32_t id, uint32_t ma, int ibits, uint32_t& i,
@@ -106,6 +113,7 @@ struct Rec {
   uint64_t w0, w1;  // X and Z word gl of the product string
   TV re, im;        // value i^k c_a c_b (the same in every lane of the group)
   uint64_t fp;
+  bool keep;        // the record gives its string a term (false: a commuting pair of [a, b])
 };
 
 // Raw loads of one record: this lane's pieces (X_gl, Z_gl) of the two operand
@@ -156,7 +164,7 @@ __device__ __forceinline__ uint64_t meta_word(const Raw<G>& raw) {
 // TS: type the operands' coefficients are stored in; TV: type the product
 // is computed in (the stored coefficients are rounded to TV first).
 template <int G, typename TS, typename TV>
-__device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl, int sym) {
+__device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl, int form) {
   (void)gl;
   const ulonglong2 a = raw.a, b = raw.b;
   Rec<G, TV> r;
@@ -175,16 +183,24 @@ __device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl, int 
                      cplx<TV>{static_cast<TV>(from_word<TS>(br)), static_cast<TV>(from_word<TS>(bi))}));
   r.re = v.re;
   r.im = v.im;
-  if (sym) {
-    // the pair stands for (i, j) and (j, i): their values are equal when the
-    // strings commute and opposite when they anticommute (the phases differ
-    // by 2 exactly then).  The parity of the anticommutation count is that
-    // of |X3 & Z3| + |Xa & Za| + |Xb & Zb|, and part = 2(..) - |X3 & Z3|.
+  r.keep = true;
+  if (form != kFormProduct) {
+    // The values of a_i b_j and b_j a_i are equal when the strings commute
+    // and opposite when they anticommute (the phases differ by 2 exactly
+    // then).  The parity of the anticommutation count is that of
+    // |X3 & Z3| + |Xa & Za| + |Xb & Zb|, and part = 2(..) - |X3 & Z3|.
     const bool anti = ((part + static_cast<int>((ae >> 2) + (be >> 2))) & 1) != 0;
-    const bool same_class = (ae >> 8) == (be >> 8);
-    TV f = anti ? TV(0) : TV(2);
-    if (raw.ij == 0) f = TV(1);                        // i == j
-    else if (same_class && raw.ij > 0) f = TV(0);      // (j, i) of a diagonal tile: counted at (i, j)
+    TV f;
+    if (form == kFormComm) {
+      f = anti ? TV(2) : TV(0);
+      r.keep = anti;
+    } else {
+      // the pair stands for (i, j) and (j, i)
+      const bool same_class = (ae >> 8) == (be >> 8);
+      f = anti ? TV(0) : TV(2);
+      if (raw.ij == 0) f = TV(1);                        // i == j
+      else if (same_class && raw.ij > 0) f = TV(0);      // (j, i) of a diagonal tile: counted at (i, j)
+    }
     r.re = f * r.re;
     r.im = f * r.im;
   }
@@ -194,7 +210,7 @@ __device__ __forceinline__ Rec<G, TV> finish_rec(const Raw<G>& raw, int gl, int 
 
 template <int G, int WT, typename TS, typename TV>
 __device__ __forceinline__ Rec<G, TV> load_rec(const Operands<WT, TS>& op, uint32_t id, int gl) {
-  return finish_rec<G, TS, TV>(issue_rec<G, WT, TS>(op, id, gl), gl, op.sym);
+  return finish_rec<G, TS, TV>(issue_rec<G, WT, TS>(op, id, gl), gl, op.form);
 }
 
 struct ExpandArgs {
@@ -212,6 +228,7 @@ struct ExpandArgs {
   uint64_t* Ofp;
   int64_t ldo;  // a multiple of kBS
   double tau;   // cancellation threshold of the compensated form
+  int marks;    // phase byte 1 marks a term no record kept (commutator), for a later compaction
 };
 
 // Merged terms of a wave, staged for aligned coalesced stores: a ring of CAP
@@ -227,9 +244,10 @@ struct Stage {
   uint8_t valid[CAP];
 };
 
+// valid: 1 = a staged term, 2 = a staged term that no record kept.
 template <int G, int WT, typename T, int CAP, typename TV>
 __device__ __forceinline__ void stage_out(Stage<WT, T, CAP>& st, int nw, int gl, uint32_t slot,
-                                          const Rec<G, TV>& r, T re, T im) {
+                                          const Rec<G, TV>& r, T re, T im, bool kept) {
   if (gl < nw) {
     st.x[gl][slot] = r.w0;
     st.z[gl][slot] = r.w1;
@@ -237,7 +255,7 @@ __device__ __forceinline__ void stage_out(Stage<WT, T, CAP>& st, int nw, int gl,
   if (gl == 0) {
     st.c[slot] = cplx<T>{re, im};
     st.fp[slot] = r.fp;
-    st.valid[slot] = 1;
+    st.valid[slot] = kept ? 1 : 2;
   }
 }
 
@@ -340,7 +358,8 @@ __device__ __forceinline__ void store_block(const ExpandArgs& E, Stage<WT, TV, C
   const bool upper = lane >= kBS;
   const uint32_t o = B + t;
   const uint32_t slot = o & (CAP - 1);
-  const bool live = o >= o_lo && o < o_hi && st.valid[slot];
+  const uint8_t vflag = st.valid[slot];
+  const bool live = o >= o_lo && o < o_hi && vflag != 0;
 #pragma unroll
   for (int w = 0; w < WT; ++w) {
     if (w < nw) {
@@ -361,6 +380,7 @@ __device__ __forceinline__ void store_block(const ExpandArgs& E, Stage<WT, TV, C
     uint64_t* dst = upper ? E.Ofp + o : reinterpret_cast<uint64_t*>(static_cast<cplx<TV>*>(E.Oc) + o);
     if (live) __builtin_nontemporal_store(upper ? f : cw, dst);
   }
+  if (E.marks && live && vflag == 2 && !upper) E.Oph[o] = 1;
   wave_sync();  // the slots are read before they are cleared
   if (!upper) st.valid[slot] = 0;
 }
@@ -443,13 +463,13 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
       }
       Rec<G, TV> rec[KR];
 #pragma unroll
-      for (int t = 0; t < KR; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl, op.sym);
+      for (int t = 0; t < KR; ++t) rec[t] = finish_rec<G, T, TV>(raw[t], gl, op.form);
       wave_sync();  // slots cleared before any stage_out
       if (p0 < q_end) {
         Acc<MODE, TV> acc;
         acc.zero();
         uint64_t h0 = 0, h1 = 0, diff = 0;
-        bool open = false;
+        bool open = false, kept = false;
         int t_head = 0;
         Rec<G, TV> first;
         // stages segment [q0, q1) (bucket positions) once its sum is known
@@ -460,7 +480,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
             vr = static_cast<TV>(c.re);
             vi = static_cast<TV>(c.im);
           }
-          stage_out<G, WT, TV, CAP, TV>(st, nw, gl, (obase + seg) & (CAP - 1), first, vr, vi);
+          stage_out<G, WT, TV, CAP, TV>(st, nw, gl, (obase + seg) & (CAP - 1), first, vr, vi, kept);
         };
         bool next_part = false;  // a segment head past the range: the rest is not ours
 #pragma unroll
@@ -473,6 +493,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
               break;
             }
             open = true;
+            kept = rec[t].keep;
             t_head = t;
             acc.begin(rec[t].re, rec[t].im);
             first = rec[t];
@@ -480,6 +501,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
             h1 = rec[t].w1;
           } else if (open) {
             acc.add(rec[t].re, rec[t].im);
+            kept = kept || rec[t].keep;
             diff |= (rec[t].w0 ^ h0) | (rec[t].w1 ^ h1);
           }
           const bool ends = p0 + t + 1 >= n || sid[t + 1] != sid[t];
@@ -502,6 +524,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
             }
             const Rec<G, TV> r2 = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
             acc.add(r2.re, r2.im);
+            kept = kept || r2.keep;
             diff |= (r2.w0 ^ h0) | (r2.w1 ^ h1);
             ++q;
           }
@@ -530,13 +553,13 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
 
 template <int G, typename TO, typename TV>
 __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, int64_t o,
-                                          const Rec<G, TV>& r, TO re, TO im) {
+                                          const Rec<G, TV>& r, TO re, TO im, bool kept) {
   if (gl < nw) {
     E.OX[static_cast<int64_t>(gl) * E.ldo + o] = r.w0;
     E.OZ[static_cast<int64_t>(gl) * E.ldo + o] = r.w1;
   }
   if (gl == 0) {
-    E.Oph[o] = 0;
+    E.Oph[o] = E.marks && !kept ? 1 : 0;
     static_cast<cplx<TO>*>(E.Oc)[o] = cplx<TO>{re, im};
     E.Ofp[o] = r.fp;
   }
@@ -555,12 +578,14 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
   __shared__ Acc<MODE, TV> s_acc[NG];
   __shared__ double s_re[NG], s_im[NG];
   __shared__ uint32_t s_end;
+  __shared__ int s_kept;
   const int g = threadIdx.x / G, gl = threadIdx.x % G;
   const uint32_t L = *nlong;
   for (uint32_t x = blockIdx.x; x < L; x += gridDim.x) {
     const uint32_t b = long_list[2 * x], q0 = long_list[2 * x + 1];
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
     const uint32_t s0 = E.segidx[lo + q0];
+    if (threadIdx.x == 0) s_kept = 0;
     if (threadIdx.x == 0) {  // segment indices grow along the bucket: binary search
       uint32_t l = q0, h = n;    // first position past the segment is in (l, h]
       while (h - l > 1) {
@@ -575,11 +600,14 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
     Acc<MODE, TV> acc;
     acc.zero();
     uint64_t diff = 0;
+    bool kept = false;
     for (uint32_t q = q0 + g; q < q1; q += NG) {
       const Rec<G, TV> r = load_rec<G, WT, T, TV>(op, E.vals[lo + q], gl);
       acc.add(r.re, r.im);
+      kept = kept || r.keep;
       diff |= (r.w0 ^ first.w0) | (r.w1 ^ first.w1);
     }
+    if (gl == 0 && kept) atomicOr(&s_kept, 1);
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
     if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
@@ -611,7 +639,8 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
       vi = static_cast<TV>(ti);
     }
     if (threadIdx.x < G)
-      write_out<G, TV, TV>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, vr, vi);
+      write_out<G, TV, TV>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, vr, vi,
+                           s_kept != 0);
     __syncthreads();
   }
 }

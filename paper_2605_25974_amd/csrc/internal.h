@@ -134,13 +134,20 @@ struct MergeArgs {
   double tau = 1e-3;
   int key_bits = 64;
   int bucket_bits = 0;  // fused pipeline: 0 = the size heuristic
+  int comm = 0;         // the commutator [a, b] instead of the product
 };
 // merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
 
-// The terms of s whose modulus is not below drop_abs (strict drop), in
-// their order, as a new container.
-paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st);
+// The terms of s whose modulus is not below drop_abs (strict drop; none
+// dropped when drop_abs < 0), in their order, as a new container.  With
+// marked, terms whose phase byte is nonzero are removed too (the expand
+// kernel marks the strings of a commutator that no anticommuting pair gave).
+paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st, bool marked = false);
+
+// k_basic.hip: the unmerged products 2 a_i b_j of the anticommuting pairs
+// of a and b (the terms of [a, b] before merging), in pair order.
+paulisum* commutator_products(const paulisum* a, const paulisum* b, hipStream_t s);
 
 // k_rotate.hip: one rotation step (product or conjugation semantics),
 // followed by the merge o.  px, pz: host words of the rotation string.

@@ -152,6 +152,111 @@ void outer_product_t(const paulisum* a, const paulisum* b, paulisum* o, hipStrea
   PAULI_HIP(hipGetLastError());
 }
 
+// flag[p] = 1 if the pair p = j*|a| + i anticommutes: the parity of
+// sum over words of |X_a & Z_b| + |Z_a & X_b| (Section III-F).
+template <int WT>
+__global__ void k_comm_flags(const uint64_t* __restrict__ AX, const uint64_t* __restrict__ AZ,
+                             int64_t ma, int64_t lda, const uint64_t* __restrict__ BX,
+                             const uint64_t* __restrict__ BZ, int64_t ldb, int nw, int64_t P,
+                             uint32_t* __restrict__ flag) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = p / ma;
+    const int64_t i = p - j * ma;
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+      if (WT > 8 && w >= nw) break;
+      s += popc64((AX[w * lda + i] & BZ[w * ldb + j]) ^ (AZ[w * lda + i] & BX[w * ldb + j]));
+    }
+    flag[p] = static_cast<uint32_t>(s & 1);
+  }
+}
+
+// The anticommuting products at their compacted positions off[p], each with
+// coefficient 2 c_a c_b (a_i b_j - b_j a_i = 2 a_i b_j for such a pair).
+template <int WT, typename T>
+__global__ void k_comm_write(const uint64_t* __restrict__ AX, const uint64_t* __restrict__ AZ,
+                             const uint8_t* __restrict__ Aph, const cplx<T>* __restrict__ Ac,
+                             const uint64_t* __restrict__ Afp, int64_t ma, int64_t lda,
+                             const uint64_t* __restrict__ BX, const uint64_t* __restrict__ BZ,
+                             const uint8_t* __restrict__ Bph, const cplx<T>* __restrict__ Bc,
+                             const uint64_t* __restrict__ Bfp, int64_t ldb, int nw, int64_t P,
+                             const uint32_t* __restrict__ flag, const uint32_t* __restrict__ off,
+                             uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
+                             uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc,
+                             uint64_t* __restrict__ Ofp, int64_t ldo) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[p]) continue;
+    const int64_t j = p / ma;
+    const int64_t i = p - j * ma;
+    const int64_t o = off[p];
+    int acc = Aph[i] + Bph[j];
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+      if (WT > 8 && w >= nw) break;
+      const uint64_t xa = AX[w * lda + i], za = AZ[w * lda + i];
+      const uint64_t xb = BX[w * ldb + j], zb = BZ[w * ldb + j];
+      const uint64_t x = xa ^ xb, z = za ^ zb;
+      acc += popc64(xa & za) + popc64(xb & zb) + 2 * popc64(za & xb) - popc64(x & z);
+      OX[w * ldo + o] = x;
+      OZ[w * ldo + o] = z;
+    }
+    Oph[o] = static_cast<uint8_t>(acc & 3);
+    const cplx<T> v = cmul(Ac[i], Bc[j]);
+    Oc[o] = cplx<T>{v.re + v.re, v.im + v.im};
+    Ofp[o] = Afp[i] ^ Bfp[j];
+  }
+}
+
+template <typename T>
+paulisum* commutator_products_t(const paulisum* a, const paulisum* b, hipStream_t s) {
+  const int64_t P = a->m * b->m;
+  DBuf flag((P + 1) * 4, s), off((P + 1) * 4, s), tot(4, s), work(scan_workspace_bytes(P), s);
+  const unsigned g = grid_for(P);
+#define PAULI_CF_CASE(WW)                                                                     \
+  case WW:                                                                                    \
+    hipLaunchKernelGGL((k_comm_flags<WW>), dim3(g), dim3(kBlock), 0, s, a->X, a->Z, a->m,      \
+                       a->ld, b->X, b->Z, b->ld, a->W, P, flag.as<uint32_t>());               \
+    break;
+  switch (a->W) {
+    PAULI_CF_CASE(1) PAULI_CF_CASE(2) PAULI_CF_CASE(4) PAULI_CF_CASE(8)
+    default:
+      hipLaunchKernelGGL((k_comm_flags<kMaxWords>), dim3(g), dim3(kBlock), 0, s, a->X, a->Z,
+                         a->m, a->ld, b->X, b->Z, b->ld, a->W, P, flag.as<uint32_t>());
+  }
+#undef PAULI_CF_CASE
+  PAULI_HIP(hipGetLastError());
+  scan_exclusive_u32(flag.as<uint32_t>(), off.as<uint32_t>(), P, tot.as<uint32_t>(), work.p, s);
+  uint32_t M = 0;
+  PAULI_HIP(hipMemcpyAsync(&M, tot.p, 4, hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipStreamSynchronize(s));
+  paulisum* o = new_sum(a->n, M, M, a->dtype, s);
+  if (M == 0) return o;
+  auto Ac = static_cast<const cplx<T>*>(a->coef);
+  auto Bc = static_cast<const cplx<T>*>(b->coef);
+  auto Oc = static_cast<cplx<T>*>(o->coef);
+#define PAULI_CW_CASE(WW)                                                                     \
+  case WW:                                                                                    \
+    hipLaunchKernelGGL((k_comm_write<WW, T>), dim3(g), dim3(kBlock), 0, s, a->X, a->Z, a->ph,  \
+                       Ac, a->fp, a->m, a->ld, b->X, b->Z, b->ph, Bc, b->fp, b->ld, a->W, P,   \
+                       flag.as<uint32_t>(), off.as<uint32_t>(), o->X, o->Z, o->ph, Oc, o->fp, \
+                       o->ld);                                                                \
+    break;
+  switch (a->W) {
+    PAULI_CW_CASE(1) PAULI_CW_CASE(2) PAULI_CW_CASE(4) PAULI_CW_CASE(8)
+    default:
+      hipLaunchKernelGGL((k_comm_write<kMaxWords, T>), dim3(g), dim3(kBlock), 0, s, a->X, a->Z,
+                         a->ph, Ac, a->fp, a->m, a->ld, b->X, b->Z, b->ph, Bc, b->fp, b->ld,
+                         a->W, P, flag.as<uint32_t>(), off.as<uint32_t>(), o->X, o->Z, o->ph, Oc,
+                         o->fp, o->ld);
+  }
+#undef PAULI_CW_CASE
+  PAULI_HIP(hipGetLastError());
+  return o;
+}
+
 }  // namespace
 
 void launch_rows_to_soa(const uint64_t* rows, int W, int64_t m, uint64_t* soa, int64_t ld,
@@ -191,6 +296,11 @@ void launch_prep_side(const paulisum* t, uint64_t* rows, uint8_t* e, hipStream_t
   hipLaunchKernelGGL(k_prep_side, dim3(grid_for(t->m)), dim3(kBlock), 0, s, t->X, t->Z, t->ph,
                      t->W, t->m, t->ld, rows, e);
   PAULI_HIP(hipGetLastError());
+}
+
+paulisum* commutator_products(const paulisum* a, const paulisum* b, hipStream_t s) {
+  if (a->dtype == PAULI_C128) return commutator_products_t<double>(a, b, s);
+  return commutator_products_t<float>(a, b, s);
 }
 
 void launch_outer_product(const paulisum* a, const paulisum* b, paulisum* o, hipStream_t s) {

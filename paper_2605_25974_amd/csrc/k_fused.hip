@@ -806,7 +806,9 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   const uint32_t P = static_cast<uint32_t>(a->m * b->m);  // bound on the records
   // a sum times itself: one record per unordered pair (i, j), i <= j, in
   // about half of the class tiles; the values carry the factor 2, 1 or 0
-  const bool same = a == b;
+  // (a commutator takes every ordered pair: [a, a] sums to zero pair by pair)
+  const bool same = a == b && !o.comm;
+  const int form = o.comm ? kFormComm : (same ? kFormSym : kFormProduct);
   const double Peff = same ? 0.5 * P : double(P);
   const int kb = o.key_bits;
   int d = o.bucket_bits > 0 ? o.bucket_bits : fused_default_bucket_bits(int64_t(Peff), kb);
@@ -925,10 +927,11 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   const int64_t ldo = (static_cast<int64_t>(U) + kBS - 1) / kBS * kBS;
   paulisum* out = new_sum(a->n, U, ldo, MODE == kComp ? PAULI_C64 : a->dtype, s);
   ExpandArgs E{boff.as<uint32_t>(), V, segidx.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
-               ctr32 + 2, ctr32 + 4, out->X, out->Z, out->ph, out->coef, out->fp, out->ld, o.tau};
+               ctr32 + 2, ctr32 + 4, out->X, out->Z, out->ph, out->coef, out->fp, out->ld, o.tau,
+               o.comm};
   Operands<WT, T> op{A.rows.template as<uint64_t>(), Bs.rows.template as<uint64_t>(),
                      A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
-                     static_cast<uint32_t>(a->m), ibits, W, int(same)};
+                     static_cast<uint32_t>(a->m), ibits, W, form};
   {
     StageScope sc(PAULI_STAGE_WRITE, s,
                   U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + Peff * 8.0);
@@ -987,11 +990,12 @@ paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o,
   else
     r = a->dtype == PAULI_C128 ? fused_w<double, kPlain>(a, b, o, s)
                                : fused_w<float, kPlain>(a, b, o, s);
-  if (r && o.drop_abs >= 0.0) {
+  if (r && (o.drop_abs >= 0.0 || o.comm)) {
+    // the strict drop, and for a commutator the terms no record kept
     StageScope sc(PAULI_STAGE_LONG, s, r->m * (16.0 * r->W + coef_bytes(r->dtype) + 9) * 2);
     paulisum* kept = nullptr;
     try {
-      kept = drop_terms(r, o.drop_abs, s);
+      kept = drop_terms(r, o.drop_abs, s, o.comm != 0);
     } catch (...) {
       free_sum(r);
       throw;

@@ -402,11 +402,11 @@ paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
 }
 
 template <typename T>
-__global__ void k_keep_flags(const cplx<T>* __restrict__ c, int64_t m, double drop2,
-                             uint32_t* __restrict__ keep) {
+__global__ void k_keep_flags(const cplx<T>* __restrict__ c, const uint8_t* __restrict__ ph,
+                             int64_t m, double drop2, int marked, uint32_t* __restrict__ keep) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x)
-    keep[t] = keep_value(c[t], drop2) ? 1u : 0u;
+    keep[t] = keep_value(c[t], drop2) && !(marked && ph[t] != 0) ? 1u : 0u;
 }
 
 template <typename T>
@@ -432,13 +432,14 @@ __global__ void k_gather_kept(const uint64_t* __restrict__ X, const uint64_t* __
 }
 
 template <typename T>
-paulisum* drop_t(const paulisum* a, double drop_abs, hipStream_t s) {
+paulisum* drop_t(const paulisum* a, double drop_abs, bool marked, hipStream_t s) {
   const int64_t m = a->m;
   DBuf keep((m + 1) * 4, s), idx((m + 1) * 4, s), tot(4, s);
   DBuf work(scan_workspace_bytes(m), s);
   const unsigned g = grid_for(m);
   hipLaunchKernelGGL(k_keep_flags<T>, dim3(g), dim3(kBlock), 0, s,
-                     static_cast<const cplx<T>*>(a->coef), m, drop_abs * drop_abs,
+                     static_cast<const cplx<T>*>(a->coef), a->ph, m,
+                     drop_abs >= 0.0 ? drop_abs * drop_abs : -1.0, marked ? 1 : 0,
                      keep.as<uint32_t>());
   scan_exclusive_u32(keep.as<uint32_t>(), idx.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, s);
   uint32_t kept = 0;
@@ -456,10 +457,10 @@ paulisum* drop_t(const paulisum* a, double drop_abs, hipStream_t s) {
 
 }  // namespace
 
-paulisum* drop_terms(const paulisum* a, double drop_abs, hipStream_t s) {
+paulisum* drop_terms(const paulisum* a, double drop_abs, hipStream_t s, bool marked) {
   if (a->m == 0) return new_sum(a->n, 0, 0, a->dtype, s);
-  if (a->dtype == PAULI_C128) return drop_t<double>(a, drop_abs, s);
-  return drop_t<float>(a, drop_abs, s);
+  if (a->dtype == PAULI_C128) return drop_t<double>(a, drop_abs, marked, s);
+  return drop_t<float>(a, drop_abs, marked, s);
 }
 
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
