@@ -42,6 +42,10 @@ WORKLOADS = {
        "to [100, 20,000]), complex64, compensated, autotuned, in calls of 32",
     5: "1e6 terms at n=500 (weight 1..20, |c| log-uniform in [1e-8, 1]) through 64 "
        "rotations, drop |c| < 1e-10",
+    6: "commutator [A, B] of the n=500 10,000 x 10,000 Jordan-Wigner-shaped sums, "
+       "complex128 (1e8 pairs)",
+    7: "Clifford circuit of 112 random gates (H, S, S^dag, X, Y, Z, CX, CZ, SWAP) on the "
+       "1e6-term n=500 propagation state, complex128",
 }
 # sources of the kernel each stage's traffic figure was measured on
 STAGE_SOURCES = {
@@ -280,6 +284,136 @@ def _common_rel_err(torch, a, b):
     return float(((g - r).abs()[sel] / mag[sel]).max())
 
 
+def _commutator(pl, torch, args):
+    """[A, B] of the metric workload's sums: pairs/s including the
+    commutation filter, sort, merge and compaction."""
+    import synth
+    A, B = synth.workload2()
+    GA, GB = pl.PauliSum.from_dict(A), pl.PauliSum.from_dict(B)
+    P = A["x"].shape[0] * B["x"].shape[0]
+    for _ in range(args.warmup):
+        pl.commutator(GA, GB).destroy()
+    torch.cuda.synchronize()
+    pl.profile_enable(True)
+    t0 = time.perf_counter()
+    U = 0
+    for _ in range(args.steps):
+        out = pl.commutator(GA, GB)
+        U = out.m
+        out.destroy()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = pl.profile_read()
+    pl.profile_enable(False)
+    ms, launches, by = stages["write"]
+    achieved = (by / launches) / (ms / launches * 1e-3) / 1e9
+    rec = {
+        "metric": "Pauli pairs/s of the commutator incl. sort-merge",
+        "value": P * args.steps / elapsed, "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators of the workload's shape)",
+        "config": {"workload": WORKLOADS[6], "pairs": P, "merged_terms": U},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_expand", "stage": "write",
+                     "launch_ms": round(ms / launches, 4),
+                     "algorithmic_bytes_per_launch": by / launches},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        rows = 2
+        SB = O.Sum(B["n"], B["x"], B["z"], B["phase"], B["coef"])
+
+        def sample(r):
+            SA = O.Sum(A["n"], A["x"][:r], A["z"][:r], A["phase"][:r], A["coef"][:r])
+            t = time.perf_counter()
+            O.commutator(SA, SB)
+            return time.perf_counter() - t
+
+        dt = sample(rows)
+        rows = max(1, min(A["x"].shape[0], int(rows * args.cpu_seconds / max(dt, 1e-3))))
+        dt = sample(rows)
+        rec["cpu_baseline"] = {
+            "value": rows * B["x"].shape[0] / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %d left terms times all %d right terms (%d pairs), both "
+                      "orders multiplied and merged exactly, %.1f s, one thread"
+                      % (rows, B["x"].shape[0], rows * B["x"].shape[0], dt)}
+    return rec
+
+
+def _clifford_gates(n, count):
+    import synth
+    rng = synth.rng_for(7, 0)
+    gates = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 9))
+        if kind >= 6:
+            q0, q1 = rng.choice(n, size=2, replace=False)
+            gates.append((kind, int(q0), int(q1)))
+        else:
+            gates.append((kind, int(rng.integers(0, n))))
+    return gates
+
+
+def _clifford(pl, torch, args):
+    """Gate application on the SoA: terms/s through a circuit (two launches
+    of 56 gates each), HBM-bound streaming."""
+    import synth
+    S = synth.workload5_state()
+    G = pl.PauliSum.from_dict(S)
+    gates = _clifford_gates(S["n"], 112)
+    m = S["x"].shape[0]
+    for _ in range(args.warmup):
+        pl.apply_clifford(G, gates).destroy()
+    torch.cuda.synchronize()
+    pl.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pl.apply_clifford(G, gates).destroy()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = pl.profile_read()
+    pl.profile_enable(False)
+    ms, launches, by = stages["clifford"]
+    achieved = (by / launches) / (ms / launches * 1e-3) / 1e9
+    rec = {
+        "metric": "Pauli terms/s through a Clifford circuit",
+        "value": m * args.steps / elapsed, "unit": "terms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64 (strings), f64 (copied)",
+        "data": "synthetic (seeded generators of the workload's shape)",
+        "config": {"workload": WORKLOADS[7], "terms": m, "gates": len(gates)},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_clifford", "stage": "clifford",
+                     "launch_ms": round(ms / launches, 4),
+                     "algorithmic_bytes_per_launch": by / launches},
+    }
+    if not args.no_cpu_baseline:
+        import numpy as np
+        from oracle import clifford as C
+        from oracle import oracle as O
+        so = O.Sum(S["n"], S["x"], S["z"], S.get("phase"), S["coef"])
+        terms = 200
+        t = time.perf_counter()
+        C.apply(so, gates, terms=np.arange(terms))
+        dt = time.perf_counter() - t
+        terms = max(1, min(m, int(terms * args.cpu_seconds / max(dt, 1e-3))))
+        t = time.perf_counter()
+        C.apply(so, gates, terms=np.arange(terms))
+        dt = time.perf_counter() - t
+        rec["cpu_baseline"] = {
+            "value": terms / dt, "unit": "terms/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %d terms through the same %d gates, letter images from the "
+                      "gate matrices, %.1f s, one thread" % (terms, len(gates), dt)}
+    return rec
+
+
 def copy_calibration(steps):
     import torch
     n = COPY_BYTES // 4
@@ -319,8 +453,9 @@ def main():
     import paper_2605_25974_amd as pl
 
     torch.cuda.set_device(0)
-    if args.workload in (4, 5):
-        rec = (_batched if args.workload == 4 else _propagation)(pl, torch, args)
+    if args.workload in (4, 5, 6, 7):
+        rec = {4: _batched, 5: _propagation, 6: _commutator,
+               7: _clifford}[args.workload](pl, torch, args)
         print(json.dumps(rec), flush=True)
         return
     A, B = _inputs(args.workload)

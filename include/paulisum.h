@@ -171,6 +171,40 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
 pauli_status_t pauli_commutator(paulisum_t a, paulisum_t b, const pauli_merge_opts_t* opts,
                                 paulisum_t* out, void* stream);
 
+/* Gate kinds of pauli_apply_clifford (Section V-B lists H, S, CNOT, CZ;
+ * S^dagger, the Pauli gates and SWAP are Cliffords of the same form). */
+typedef enum {
+  PAULI_GATE_H = 0,
+  PAULI_GATE_S = 1,    /* diag(1, i) */
+  PAULI_GATE_SDG = 2,  /* diag(1, -i) */
+  PAULI_GATE_X = 3,
+  PAULI_GATE_Y = 4,
+  PAULI_GATE_Z = 5,
+  PAULI_GATE_CX = 6,   /* control q0, target q1 */
+  PAULI_GATE_CZ = 7,
+  PAULI_GATE_SWAP = 8
+} pauli_gate_kind_t;
+
+typedef struct {
+  int32_t kind; /* pauli_gate_kind_t */
+  int32_t q0;   /* qubit (0-based) */
+  int32_t q1;   /* second qubit of CX, CZ, SWAP; ignored otherwise */
+} pauli_gate_t;
+
+/* pauli_apply_clifford: conjugation of every term by a Clifford circuit
+ * (Section II-B, Clifford paragraph: a Clifford maps each string to a single
+ * string, so the number of terms does not change; Section V-B, "Gate
+ * Application").  Term t of the output is C (i^k c P) C^dagger with
+ * C = G_{n_gates-1} ... G_1 G_0 (gates[0] conjugates first): its string is
+ * relabelled, its phase exponent gains 2 for every sign flip, its
+ * coefficient is unchanged and its fingerprint is updated.  The output keeps
+ * the input's term order (it is not re-sorted; pauli_merge restores the
+ * canonical order).  gates is a host array; n_gates = 0 copies s.  Errors:
+ * INVALID for an unknown kind, a qubit outside [0, n), or a two-qubit gate
+ * on one qubit. */
+pauli_status_t pauli_apply_clifford(paulisum_t s, int32_t n_gates, const pauli_gate_t* gates,
+                                    paulisum_t* out, void* stream);
+
 /* pauli_outer_product_batched: nb independent fused products
  * out[t] = merge(a[t] * b[t]) with one set of merge options; the pairs may
  * differ in qubit count and term counts but a[t], b[t] must agree with each
@@ -241,7 +275,8 @@ typedef enum {
   PAULI_STAGE_SEGMENT = 3,       /* bucket sorts, segment heads, segmented reduction */
   PAULI_STAGE_WRITE = 4,         /* output of the merged terms (fused: the expand kernel) */
   PAULI_STAGE_LONG = 5,          /* fused: long segments, drop compaction */
-  PAULI_STAGE_COUNT = 6
+  PAULI_STAGE_CLIFFORD = 6,      /* Clifford gate application */
+  PAULI_STAGE_COUNT = 7
 } pauli_stage_t;
 pauli_status_t pauli_profile_enable(int32_t on);
 pauli_status_t pauli_profile_read(int32_t stage, double* total_ms, int64_t* launches,

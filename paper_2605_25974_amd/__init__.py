@@ -29,9 +29,9 @@ EXPORTS = (
     "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
-    "pauli_trim_memory", "pauli_commutator",
+    "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford",
 )
-STAGES = ("outer_product", "prep", "sort", "segment", "write", "long")
+STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford")
 
 
 class PauliLibraryMissing(RuntimeError):
@@ -95,6 +95,8 @@ def lib():
     L.pauli_outer_product_merged.restype = st
     L.pauli_outer_product_merged.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts),
                                              ctypes.POINTER(_vp), _vp]
+    L.pauli_apply_clifford.restype = st
+    L.pauli_apply_clifford.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.POINTER(_vp), _vp]
     L.pauli_commutator.restype = st
     L.pauli_commutator.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
     L.pauli_outer_product_batched.restype = st
@@ -291,6 +293,21 @@ def commutator(a: PauliSum, b: PauliSum, mode=PLAIN, drop_abs=-1.0, tau=0.0, key
     o = _opts(mode, drop_abs, tau, key_bits)
     _check(lib().pauli_commutator(a.handle, b.handle, ctypes.byref(o), ctypes.byref(out),
                                   _stream(stream)))
+    return PauliSum(out)
+
+
+GATE_H, GATE_S, GATE_SDG, GATE_X, GATE_Y, GATE_Z, GATE_CX, GATE_CZ, GATE_SWAP = range(9)
+
+
+def apply_clifford(s: PauliSum, gates, stream=None) -> PauliSum:
+    """Every term conjugated by the gates in order (pauli_apply_clifford).
+    gates: sequence of (kind, q0[, q1]); the output keeps the term order."""
+    g = np.zeros((len(gates), 3), dtype=np.int32)
+    for i, gate in enumerate(gates):
+        g[i, :len(gate)] = gate
+    out = _vp()
+    _check(lib().pauli_apply_clifford(s.handle, int(len(gates)), g.ctypes.data if len(gates) else None,
+                                      ctypes.byref(out), _stream(stream)))
     return PauliSum(out)
 
 

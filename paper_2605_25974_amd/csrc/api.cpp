@@ -479,6 +479,29 @@ pauli_status_t pauli_commutator(paulisum_t a, paulisum_t b, const pauli_merge_op
   });
 }
 
+pauli_status_t pauli_apply_clifford(paulisum_t s, int32_t n_gates, const pauli_gate_t* gates,
+                                    paulisum_t* out, void* stream) {
+  return guarded([&] {
+    if (!s || !out) fail(PAULI_ERR_INVALID, "s and out must not be NULL");
+    if (n_gates < 0) fail(PAULI_ERR_INVALID, "n_gates is negative");
+    if (n_gates > 0 && !gates) fail(PAULI_ERR_INVALID, "gates is NULL");
+    for (int32_t i = 0; i < n_gates; ++i) {
+      const pauli_gate_t& g = gates[i];
+      if (g.kind < PAULI_GATE_H || g.kind > PAULI_GATE_SWAP)
+        fail(PAULI_ERR_INVALID, "gate " + std::to_string(i) + ": unknown kind");
+      if (g.q0 < 0 || g.q0 >= s->n)
+        fail(PAULI_ERR_INVALID, "gate " + std::to_string(i) + ": qubit outside [0, n)");
+      if (g.kind >= PAULI_GATE_CX && (g.q1 < 0 || g.q1 >= s->n || g.q1 == g.q0))
+        fail(PAULI_ERR_INVALID,
+             "gate " + std::to_string(i) + ": second qubit outside [0, n) or equal to the first");
+    }
+    use_device(s);
+    hipStream_t st = as_stream(stream);
+    s->last_stream = st;
+    *out = apply_clifford(s, gates, n_gates, st);
+  });
+}
+
 pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
                                            const pauli_merge_opts_t* opts,
                                            const pauli_tune_t* tune, paulisum_t* out,

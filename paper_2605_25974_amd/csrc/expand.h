@@ -359,7 +359,9 @@ __device__ __forceinline__ void store_block(const ExpandArgs& E, Stage<WT, TV, C
   const uint32_t o = B + t;
   const uint32_t slot = o & (CAP - 1);
   const uint8_t vflag = st.valid[slot];
-  const bool live = o >= o_lo && o < o_hi && vflag != 0;
+  // a term no record kept (commutator) is removed later: only its mark is stored
+  const bool live = o >= o_lo && o < o_hi && vflag == 1;
+  const bool mark = o >= o_lo && o < o_hi && vflag == 2;
 #pragma unroll
   for (int w = 0; w < WT; ++w) {
     if (w < nw) {
@@ -380,7 +382,7 @@ __device__ __forceinline__ void store_block(const ExpandArgs& E, Stage<WT, TV, C
     uint64_t* dst = upper ? E.Ofp + o : reinterpret_cast<uint64_t*>(static_cast<cplx<TV>*>(E.Oc) + o);
     if (live) __builtin_nontemporal_store(upper ? f : cw, dst);
   }
-  if (E.marks && live && vflag == 2 && !upper) E.Oph[o] = 1;
+  if (mark && !upper) E.Oph[o] = 1;
   wave_sync();  // the slots are read before they are cleared
   if (!upper) st.valid[slot] = 0;
 }
@@ -554,12 +556,16 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
 template <int G, typename TO, typename TV>
 __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, int64_t o,
                                           const Rec<G, TV>& r, TO re, TO im, bool kept) {
+  if (E.marks && !kept) {  // removed later: only the mark
+    if (gl == 0) E.Oph[o] = 1;
+    return;
+  }
   if (gl < nw) {
     E.OX[static_cast<int64_t>(gl) * E.ldo + o] = r.w0;
     E.OZ[static_cast<int64_t>(gl) * E.ldo + o] = r.w1;
   }
   if (gl == 0) {
-    E.Oph[o] = E.marks && !kept ? 1 : 0;
+    E.Oph[o] = 0;
     static_cast<cplx<TO>*>(E.Oc)[o] = cplx<TO>{re, im};
     E.Ofp[o] = r.fp;
   }

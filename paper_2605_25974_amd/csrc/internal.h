@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "paulisum.h"
 
@@ -148,6 +149,11 @@ paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st, bool ma
 // k_basic.hip: the unmerged products 2 a_i b_j of the anticommuting pairs
 // of a and b (the terms of [a, b] before merging), in pair order.
 paulisum* commutator_products(const paulisum* a, const paulisum* b, hipStream_t s);
+
+// k_clifford.hip: the sum with every term conjugated by the gates in order
+// (validated by the caller).
+paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n_gates,
+                         hipStream_t st);
 
 // k_rotate.hip: one rotation step (product or conjugation semantics),
 // followed by the merge o.  px, pz: host words of the rotation string.

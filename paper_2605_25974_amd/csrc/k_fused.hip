@@ -933,8 +933,12 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                      A.aux.template as<Aux<T>>(), Bs.aux.template as<Aux<T>>(),
                      static_cast<uint32_t>(a->m), ibits, W, form};
   {
+    // HBM bytes: ids and segment indices read per record, and per segment
+    // the merged term written; a commutator writes only the phase byte of
+    // the segments it removes later (their number is not known here, so its
+    // count is the lower bound of one byte per segment)
     StageScope sc(PAULI_STAGE_WRITE, s,
-                  U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8) + Peff * 8.0);
+                  (o.comm ? U * 1.0 : U * (16.0 * W + sizeof(cplx<TV>) + 1 + 8)) + Peff * 8.0);
     // merged terms carry phase 0 (the block of phase bytes is padded to 256)
     if (U > 0)
       hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((U + 3) / 4)), dim3(kB), 0, s,

@@ -406,7 +406,7 @@ __global__ void k_keep_flags(const cplx<T>* __restrict__ c, const uint8_t* __res
                              int64_t m, double drop2, int marked, uint32_t* __restrict__ keep) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x)
-    keep[t] = keep_value(c[t], drop2) && !(marked && ph[t] != 0) ? 1u : 0u;
+    keep[t] = !(marked && ph[t] != 0) && (drop2 < 0.0 || keep_value(c[t], drop2)) ? 1u : 0u;
 }
 
 template <typename T>
