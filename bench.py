@@ -50,6 +50,7 @@ WORKLOADS = {
 # sources of the kernel each stage's traffic figure was measured on
 STAGE_SOURCES = {
     "write": ["paper_2605_25974_amd/csrc/expand.h", "paper_2605_25974_amd/csrc/common.h"],
+    "clifford": ["paper_2605_25974_amd/csrc/k_clifford.hip", "paper_2605_25974_amd/csrc/common.h"],
 }
 COPY_BYTES = 2 << 30
 
@@ -359,8 +360,8 @@ def _clifford_gates(n, count):
 
 
 def _clifford(pl, torch, args):
-    """Gate application on the SoA: terms/s through a circuit (two launches
-    of 56 gates each), HBM-bound streaming."""
+    """Gate application on the SoA: terms/s through a 112-gate circuit in one
+    streaming pass over the sum."""
     import synth
     S = synth.workload5_state()
     G = pl.PauliSum.from_dict(S)
@@ -389,7 +390,8 @@ def _clifford(pl, torch, args):
         "config": {"workload": WORKLOADS[7], "terms": m, "gates": len(gates)},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic("clifford", 7),
                      "kernel": "k_clifford", "stage": "clifford",
                      "launch_ms": round(ms / launches, 4),
                      "algorithmic_bytes_per_launch": by / launches},

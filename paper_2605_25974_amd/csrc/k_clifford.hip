@@ -16,15 +16,10 @@ namespace pauli {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kGateChunk = 56;  // gates per launch (kernel argument space)
 
 struct DevGate {
   int kind, q0, q1, pad;
   uint64_t col[4];  // fingerprint columns of x_q0, z_q0, x_q1, z_q1
-};
-struct GateChunk {
-  DevGate g[kGateChunk];
-  int count;
 };
 
 // The words of the term a thread works on, in LDS: x[w][threadIdx.x].
@@ -110,7 +105,8 @@ template <int WT, typename T>
 __global__ void __launch_bounds__(kBlock)
 k_clifford(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
            const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
-           const uint64_t* __restrict__ fp, int64_t m, int64_t ld, int nw, GateChunk gc,
+           const uint64_t* __restrict__ fp, int64_t m, int64_t ld, int nw,
+           const DevGate* __restrict__ gates, int ngates,
            uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ, uint8_t* __restrict__ Oph,
            cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp, int64_t ldo) {
   __shared__ Words<WT> s;
@@ -124,7 +120,8 @@ k_clifford(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
     }
     uint64_t f = fp[t];
     uint32_t flips = 0;
-    for (int i = 0; i < gc.count; ++i) flips += apply_gate<WT>(s, gc.g[i], f);
+    // every thread reads the same gate: uniform (scalar) loads
+    for (int i = 0; i < ngates; ++i) flips += apply_gate<WT>(s, gates[i], f);
 #pragma unroll
     for (int w = 0; w < WT; ++w)
       if (w < nw) {
@@ -132,44 +129,32 @@ k_clifford(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
         OZ[w * ldo + t] = s.z[w][tid];
       }
     Oph[t] = static_cast<uint8_t>((ph[t] + 2 * flips) & 3);
-    if (Oc != c) Oc[t] = c[t];
+    Oc[t] = c[t];
     Ofp[t] = f;
   }
 }
 
 template <typename T>
-void clifford_t(const paulisum* s, const std::vector<DevGate>& gates, paulisum* o, hipStream_t st) {
+void clifford_t(const paulisum* s, const DevGate* dg, int ngates, paulisum* o, hipStream_t st) {
   const int64_t m = s->m;
   int64_t g = (m + kBlock - 1) / kBlock;
   if (g > 65536) g = 65536;
   if (g < 1) g = 1;
   const int W = s->W;
-  for (size_t off = 0; off < gates.size() || off == 0; off += kGateChunk) {
-    GateChunk gc{};
-    const size_t cnt = gates.size() - off < static_cast<size_t>(kGateChunk)
-                           ? gates.size() - off
-                           : static_cast<size_t>(kGateChunk);
-    for (size_t i = 0; i < cnt; ++i) gc.g[i] = gates[off + i];
-    gc.count = static_cast<int>(cnt);
-    // the first launch reads the input; later ones update the output in place
-    const paulisum* in = off == 0 ? s : o;
-    StageScope sc(PAULI_STAGE_CLIFFORD, st,
-                  m * 2.0 * (16.0 * W + 1 + 8) + (off == 0 ? m * 2.0 * sizeof(cplx<T>) : 0.0));
-    auto Ic = static_cast<const cplx<T>*>(in->coef);
-    auto Oc = static_cast<cplx<T>*>(o->coef);
+  StageScope sc(PAULI_STAGE_CLIFFORD, st, m * 2.0 * (16.0 * W + 1 + 8 + sizeof(cplx<T>)));
+  auto Ic = static_cast<const cplx<T>*>(s->coef);
+  auto Oc = static_cast<cplx<T>*>(o->coef);
 #define PAULI_CL_CASE(WW)                                                                     \
   case WW:                                                                                    \
     hipLaunchKernelGGL((k_clifford<WW, T>), dim3(static_cast<unsigned>(g)), dim3(kBlock), 0,   \
-                       st, in->X, in->Z, in->ph, Ic, in->fp, m, in->ld, W, gc, o->X, o->Z,     \
+                       st, s->X, s->Z, s->ph, Ic, s->fp, m, s->ld, W, dg, ngates, o->X, o->Z,  \
                        o->ph, Oc, o->fp, o->ld);                                              \
     break;
-    switch (W <= 1 ? 1 : W <= 2 ? 2 : W <= 4 ? 4 : W <= 8 ? 8 : 16) {
-      PAULI_CL_CASE(1) PAULI_CL_CASE(2) PAULI_CL_CASE(4) PAULI_CL_CASE(8) PAULI_CL_CASE(16)
-    }
-#undef PAULI_CL_CASE
-    PAULI_HIP(hipGetLastError());
-    if (gates.empty()) break;
+  switch (W <= 1 ? 1 : W <= 2 ? 2 : W <= 4 ? 4 : W <= 8 ? 8 : 16) {
+    PAULI_CL_CASE(1) PAULI_CL_CASE(2) PAULI_CL_CASE(4) PAULI_CL_CASE(8) PAULI_CL_CASE(16)
   }
+#undef PAULI_CL_CASE
+  PAULI_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -192,10 +177,16 @@ paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n
   paulisum* o = new_sum(s->n, s->m, s->m, s->dtype, st);
   if (s->m == 0) return o;
   try {
+    DBuf gbuf(dg.size() * sizeof(DevGate) + 16, st);
+    if (!dg.empty()) {
+      PAULI_HIP(hipMemcpyAsync(gbuf.p, dg.data(), dg.size() * sizeof(DevGate),
+                               hipMemcpyHostToDevice, st));
+      PAULI_HIP(hipStreamSynchronize(st));  // the host gate list goes out of scope
+    }
     if (s->dtype == PAULI_C128)
-      clifford_t<double>(s, dg, o, st);
+      clifford_t<double>(s, gbuf.as<DevGate>(), n_gates, o, st);
     else
-      clifford_t<float>(s, dg, o, st);
+      clifford_t<float>(s, gbuf.as<DevGate>(), n_gates, o, st);
   } catch (...) {
     free_sum(o);
     throw;
