@@ -298,15 +298,16 @@ k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict_
 // the tile positions [w*kItems*64, (w+1)*kItems*64) in rounds of 64, so
 // ranking each wave's records by digit (ballots and a wave-private digit
 // counter, no block barrier) and adding the counts of earlier waves keeps
-// the tile's order within each digit.  The records are staged in LDS in
-// digit order and each digit's run is written coalesced.
+// the tile's order within each digit.  Only each record's tile position is
+// staged in LDS, in digit order; the record is generated again when its
+// digit's run is written (coalesced), which keeps the kernel small enough
+// for many resident blocks.
 __global__ void __launch_bounds__(kB)
 k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
            const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
            uint32_t mask, const uint32_t* __restrict__ C) {
   constexpr int NW = kB / 64;
-  __shared__ uint64_t s_k[kTile];
-  __shared__ uint32_t s_v[kTile];
+  __shared__ uint16_t s_pos[kTile];
   __shared__ uint32_t s_start[256], s_goff[256];
   __shared__ uint32_t s_wc[NW][256];
   __shared__ uint32_t sh[NW];
@@ -323,33 +324,31 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
   load_gen_row(G, s, R);
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
-  uint64_t k[kItems];
-  uint32_t v[kItems];
-  int d[kItems];
-  uint32_t rk[kItems];
+  // digit in bits 0-7 and rank among the wave's equal digits above, or ~0
+  uint32_t dr[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t q = lo + (static_cast<uint32_t>(wave) * kItems + r) * 64 + lane;
-    d[r] = -1;
-    k[r] = 0;
-    v[r] = 0;
+    int d = -1;
     if (q < hi) {
-      gen_record(G, R, q, k[r], v[r]);
-      d[r] = static_cast<int>((k[r] >> shift) & mask);
+      uint64_t k;
+      uint32_t v;
+      gen_record(G, R, q, k, v);
+      d = static_cast<int>((k >> shift) & mask);
     }
-    const bool valid = d[r] >= 0;
+    const bool valid = d >= 0;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
-      const bool on = valid && ((d[r] >> bit) & 1);
+      const bool on = valid && ((d >> bit) & 1);
       const uint64_t bm = __ballot(on);
       peers &= on ? bm : ~bm;
     }
     const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
     uint32_t base = 0;
-    if (valid) base = s_wc[wave][d[r]];
-    rk[r] = base + rank;
-    if (valid && rank == 0) s_wc[wave][d[r]] = base + static_cast<uint32_t>(__popcll(peers));
+    if (valid) base = s_wc[wave][d];
+    dr[r] = valid ? static_cast<uint32_t>(d) | ((base + rank) << 8) : 0xFFFFFFFFu;
+    if (valid && rank == 0) s_wc[wave][d] = base + static_cast<uint32_t>(__popcll(peers));
   }
   __syncthreads();
   // digit starts inside the tile, then each (wave, digit) start
@@ -368,19 +367,20 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r)
-    if (d[r] >= 0) {
-      const uint32_t off = s_wc[wave][d[r]] + rk[r];
-      s_k[off] = k[r];
-      s_v[off] = v[r];
+    if (dr[r] != 0xFFFFFFFFu) {
+      const uint32_t off = s_wc[wave][dr[r] & 255u] + (dr[r] >> 8);
+      s_pos[off] = static_cast<uint16_t>((static_cast<uint32_t>(wave) * kItems + r) * 64 + lane);
     }
   __syncthreads();
   const uint32_t cnt = hi - lo;
   for (uint32_t e = tid; e < cnt; e += kB) {
-    const uint64_t kk = s_k[e];
+    uint64_t kk;
+    uint32_t vv;
+    gen_record(G, R, lo + s_pos[e], kk, vv);
     const uint32_t dd = static_cast<uint32_t>((kk >> shift) & mask);
     const uint32_t g = s_goff[dd] + (e - s_start[dd]);
     kout[g] = kk;
-    vout[g] = s_v[e];
+    vout[g] = vv;
   }
 }
 
