@@ -560,8 +560,10 @@ pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
     paulisum* cur = s;
     try {
       for (int32_t t = 0; t < steps; ++t) {
+        // after the first step the state is a merge's output, in key order
         paulisum* next = rotate_step(cur, p_x + static_cast<size_t>(t) * W,
-                                     p_z + static_cast<size_t>(t) * W, theta[t], rotate_mode, m, st);
+                                     p_z + static_cast<size_t>(t) * W, theta[t], rotate_mode, m,
+                                     t > 0, st);
         if (cur != s) free_sum(cur);
         cur = next;
       }

@@ -140,6 +140,12 @@ struct MergeArgs {
 // merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
 
+// merge(a) from records (key = fingerprint >> (64 - o.key_bits), index of a
+// term of a), one per term, already in key order (equal keys adjacent).
+// keys and vals are device arrays of a->m entries, used as scratch.
+paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals,
+                               const MergeArgs& o, hipStream_t s);
+
 // The terms of s whose modulus is not below drop_abs (strict drop; none
 // dropped when drop_abs < 0), in their order, as a new container.  With
 // marked, terms whose phase byte is nonzero are removed too (the expand
@@ -158,7 +164,7 @@ paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n
 // k_rotate.hip: one rotation step (product or conjugation semantics),
 // followed by the merge o.  px, pz: host words of the rotation string.
 paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
-                      int mode, const MergeArgs& o, hipStream_t st);
+                      int mode, const MergeArgs& o, bool sorted_input, hipStream_t st);
 
 // k_fused.hip: merge(a*b) by the staged fused pipeline; nullptr when a
 // fingerprint collision asks for merge_generic instead.

@@ -268,21 +268,23 @@ k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __res
 
 // -------------------------------------------------------------- pipeline
 
+// presorted: the records are already in key order (equal keys adjacent).
 template <int WT, typename T, int MODE, typename Src>
-paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, DBuf& keys_buf,
-                       DBuf& vals_buf, const MergeArgs& o, hipStream_t s) {
+paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, uint64_t* keys,
+                       uint32_t* vals, const MergeArgs& o, hipStream_t s, bool presorted = false) {
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
   if (MODE == kComp) dt = PAULI_C64;
-  uint64_t* keys = keys_buf.as<uint64_t>();
-  uint32_t* vals = vals_buf.as<uint32_t>();
-  DBuf keys_alt(N * sizeof(uint64_t), s), vals_alt(N * sizeof(uint32_t), s);
-  DBuf rwork(radix_workspace_bytes(N), s);
-  if (radix_sort_pairs(keys, vals, keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(), N,
-                       o.key_bits, rwork.p, s)) {
-    keys = keys_alt.as<uint64_t>();
-    vals = vals_alt.as<uint32_t>();
+  DBuf keys_alt, vals_alt;
+  if (!presorted) {
+    keys_alt = DBuf(N * sizeof(uint64_t), s);
+    vals_alt = DBuf(N * sizeof(uint32_t), s);
+    DBuf rwork(radix_workspace_bytes(N), s);
+    if (radix_sort_pairs(keys, vals, keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(), N,
+                         o.key_bits, rwork.p, s)) {
+      keys = keys_alt.as<uint64_t>();
+      vals = vals_alt.as<uint32_t>();
+    }
   }
-  rwork.reset();
 
   // counters: [0] dirty, [1] segments, [2] kept, [3] long segments
   DBuf ctr_buf(64, s);
@@ -363,8 +365,10 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
     PAULI_HIP(hipGetLastError());
     TermSrc<WT, T> src{a->X, a->Z, a->ph, static_cast<const cplx<T>*>(a->coef), a->fp, a->ld, a->W};
     return o.mode == PAULI_MERGE_COMPENSATED
-               ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s)
-               : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s);
+               ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
+                                            vals.as<uint32_t>(), o, s)
+               : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
+                                             vals.as<uint32_t>(), o, s);
   }
   const int64_t N = a->m * b->m;
   const int W = a->W;
@@ -382,8 +386,36 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                      a->fp, rb.as<uint64_t>(), eb.as<uint8_t>(),
                      static_cast<const cplx<T>*>(b->coef), b->fp, static_cast<uint32_t>(a->m), W};
   return o.mode == PAULI_MERGE_COMPENSATED
-             ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s)
-             : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s);
+             ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
+                                          vals.as<uint32_t>(), o, s)
+             : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
+                                           vals.as<uint32_t>(), o, s);
+}
+
+// merge(a) from records (key, term index) of a that are already in key order.
+template <int WT, typename T>
+paulisum* merge_sorted_t(const paulisum* a, uint64_t* keys, uint32_t* vals, const MergeArgs& o,
+                         hipStream_t s) {
+  TermSrc<WT, T> src{a->X, a->Z, a->ph, static_cast<const cplx<T>*>(a->coef), a->fp, a->ld, a->W};
+  return o.mode == PAULI_MERGE_COMPENSATED
+             ? run_pipeline<WT, T, kComp>(src, a->n, a->m, a->dtype, keys, vals, o, s, true)
+             : run_pipeline<WT, T, kPlain>(src, a->n, a->m, a->dtype, keys, vals, o, s, true);
+}
+
+template <typename T>
+paulisum* merge_sorted_w(const paulisum* a, uint64_t* keys, uint32_t* vals, const MergeArgs& o,
+                         hipStream_t s) {
+  switch (a->W) {  // the term source reads exactly WT words when WT <= 8
+    case 1: return merge_sorted_t<1, T>(a, keys, vals, o, s);
+    case 2: return merge_sorted_t<2, T>(a, keys, vals, o, s);
+    case 3: return merge_sorted_t<3, T>(a, keys, vals, o, s);
+    case 4: return merge_sorted_t<4, T>(a, keys, vals, o, s);
+    case 5: return merge_sorted_t<5, T>(a, keys, vals, o, s);
+    case 6: return merge_sorted_t<6, T>(a, keys, vals, o, s);
+    case 7: return merge_sorted_t<7, T>(a, keys, vals, o, s);
+    case 8: return merge_sorted_t<8, T>(a, keys, vals, o, s);
+    default: return merge_sorted_t<kMaxWords, T>(a, keys, vals, o, s);
+  }
 }
 
 template <typename T>
@@ -461,6 +493,13 @@ paulisum* drop_terms(const paulisum* a, double drop_abs, hipStream_t s, bool mar
   if (a->m == 0) return new_sum(a->n, 0, 0, a->dtype, s);
   if (a->dtype == PAULI_C128) return drop_t<double>(a, drop_abs, marked, s);
   return drop_t<float>(a, drop_abs, marked, s);
+}
+
+paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals,
+                               const MergeArgs& o, hipStream_t s) {
+  if (a->m == 0) return new_sum(a->n, 0, 0, o.mode == PAULI_MERGE_COMPENSATED ? PAULI_C64 : a->dtype, s);
+  if (a->dtype == PAULI_C128) return merge_sorted_w<double>(a, keys, vals, o, s);
+  return merge_sorted_w<float>(a, keys, vals, o, s);
 }
 
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {

@@ -85,6 +85,103 @@ __global__ void k_rot_write(const uint64_t* __restrict__ X, const uint64_t* __re
   }
 }
 
+// Records of the conjugated sum when the input sum is in key order: the
+// kept strings (every input term, in input order, so already sorted) and
+// the new strings P Q of the anticommuting terms (compacted, to be sorted).
+__global__ void k_rot_records(const uint64_t* __restrict__ mfp, const uint32_t* __restrict__ cnt,
+                              const uint32_t* __restrict__ off, int64_t m, int kshift,
+                              uint64_t* __restrict__ kk, uint32_t* __restrict__ kv,
+                              uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = off[t];
+    kk[t] = mfp[o] >> kshift;
+    kv[t] = o;
+    if (cnt[t] == 2) {
+      const uint32_t j = o - static_cast<uint32_t>(t);  // anticommuting terms before t
+      nk[j] = mfp[o + 1] >> kshift;
+      nv[j] = o + 1;
+    }
+  }
+}
+
+// Merge of two key-ordered record lists a (first on equal keys) and b into
+// o: each block takes kMergeOut consecutive outputs, finds where they start
+// in a and b by a co-rank search (merge path), stages both input ranges in
+// LDS and merges them there; each thread then finds its own kMergePer
+// outputs' start the same way inside the block's ranges.
+constexpr int kMergePer = 8;
+constexpr int kMergeOut = kBlock * kMergePer;
+
+__device__ __forceinline__ int64_t corank(const uint64_t* a, int64_t na, const uint64_t* b,
+                                          int64_t nb, int64_t d) {
+  // smallest i with a[i] > b[d - 1 - i]: the first d outputs take i from a
+  int64_t lo = d - nb > 0 ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] <= b[d - 1 - mid]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_merge_path(const uint64_t* __restrict__ ak, const uint32_t* __restrict__ av, int64_t na,
+             const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, int64_t nb,
+             uint64_t* __restrict__ ok, uint32_t* __restrict__ ov) {
+  __shared__ uint64_t sk[kMergeOut];
+  __shared__ uint32_t sv[kMergeOut];
+  __shared__ uint64_t so_k[kMergeOut];
+  __shared__ uint32_t so_v[kMergeOut];
+  __shared__ int64_t s_split[2];
+  const int64_t total = na + nb;
+  for (int64_t d0 = static_cast<int64_t>(blockIdx.x) * kMergeOut; d0 < total;
+       d0 += static_cast<int64_t>(gridDim.x) * kMergeOut) {
+    const int64_t d1 = d0 + kMergeOut < total ? d0 + kMergeOut : total;
+    if (threadIdx.x == 0) s_split[0] = corank(ak, na, bk, nb, d0);
+    if (threadIdx.x == 1) s_split[1] = corank(ak, na, bk, nb, d1);
+    __syncthreads();
+    const int64_t i0 = s_split[0], i1 = s_split[1];
+    const int64_t j0 = d0 - i0, j1 = d1 - i1;
+    const int la = static_cast<int>(i1 - i0), lb = static_cast<int>(j1 - j0);  // la + lb <= kMergeOut
+    for (int e = threadIdx.x; e < la + lb; e += kBlock) {
+      if (e < la) {
+        sk[e] = ak[i0 + e];
+        sv[e] = av[i0 + e];
+      } else {
+        sk[e] = bk[j0 + e - la];
+        sv[e] = bv[j0 + e - la];
+      }
+    }
+    __syncthreads();
+    // this thread's outputs [e0, e1) of the block's la + lb
+    const int e0 = static_cast<int>(threadIdx.x) * kMergePer;
+    const int n = la + lb;
+    if (e0 < n) {
+      const int e1 = e0 + kMergePer < n ? e0 + kMergePer : n;
+      const int i = static_cast<int>(corank(sk, la, sk + la, lb, e0));
+      int x = i, y = e0 - i;
+      for (int e = e0; e < e1; ++e) {
+        const bool take_a = y >= lb || (x < la && sk[x] <= sk[la + y]);
+        if (take_a) {
+          so_k[e] = sk[x];
+          so_v[e] = sv[x];
+          ++x;
+        } else {
+          so_k[e] = sk[la + y];
+          so_v[e] = sv[la + y];
+          ++y;
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += kBlock) {
+      ok[d0 + e] = so_k[e];
+      ov[d0 + e] = so_v[e];
+    }
+    __syncthreads();
+  }
+}
+
 RotString rot_string(int n, const uint64_t* px, const uint64_t* pz) {
   RotString P{};
   P.W = words_for(n);
@@ -102,9 +199,10 @@ RotString rot_string(int n, const uint64_t* px, const uint64_t* pz) {
   return P;
 }
 
+// sorted_input: s is in key order (a merge's output with the same key bits).
 template <typename T>
 paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const MergeArgs& o,
-                      hipStream_t st) {
+                      bool sorted_input, hipStream_t st) {
   const int64_t m = s->m;
   DBuf cnt((m + 1) * 4, st), off((m + 1) * 4, st), tot(4, st), work(scan_workspace_bytes(m), st);
   const unsigned g = grid_for(m);
@@ -127,7 +225,41 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
   }
   paulisum* r = nullptr;
   try {
-    r = merge_generic(mat, nullptr, o, st);
+    if (!sorted_input) {
+      r = merge_generic(mat, nullptr, o, st);
+    } else {
+      // the kept strings are in key order already: sort only the new ones
+      // and merge the two lists instead of sorting every record
+      const int64_t M2 = mat->m, na = m, nb = M2 - m;
+      const int kshift = 64 - o.key_bits;
+      DBuf keys(M2 * 8, st), vals(M2 * 4, st), kk(m * 8, st), kv(m * 4, st);
+      DBuf nk(nb * 8 + 8, st), nv(nb * 4 + 4, st), nk2(nb * 8 + 8, st), nv2(nb * 4 + 4, st);
+      {
+        StageScope sc(PAULI_STAGE_SORT, st, m * 24.0 + nb * 12.0 * 2 + M2 * 36.0);
+        hipLaunchKernelGGL(k_rot_records, dim3(g), dim3(kBlock), 0, st, mat->fp,
+                           cnt.as<uint32_t>(), off.as<uint32_t>(), m, kshift, kk.as<uint64_t>(),
+                           kv.as<uint32_t>(), nk.as<uint64_t>(), nv.as<uint32_t>());
+        PAULI_HIP(hipGetLastError());
+        uint64_t* bk = nk.as<uint64_t>();
+        uint32_t* bv = nv.as<uint32_t>();
+        if (nb > 1) {
+          DBuf rwork(radix_workspace_bytes(nb), st);
+          if (radix_sort_pairs(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), nb, o.key_bits,
+                               rwork.p, st)) {
+            bk = nk2.as<uint64_t>();
+            bv = nv2.as<uint32_t>();
+          }
+        }
+        int64_t blocks = (M2 + kMergeOut - 1) / kMergeOut;
+        if (blocks > 65536) blocks = 65536;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
+                           kk.as<uint64_t>(), kv.as<uint32_t>(), na, bk, bv, nb,
+                           keys.as<uint64_t>(), vals.as<uint32_t>());
+        PAULI_HIP(hipGetLastError());
+      }
+      r = merge_sorted_records(mat, keys.as<uint64_t>(), vals.as<uint32_t>(), o, st);
+    }
   } catch (...) {
     free_sum(mat);
     throw;
@@ -171,12 +303,12 @@ paulisum* rotation_sum(const paulisum* s, const RotString& P, double theta, hipS
 }  // namespace
 
 paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
-                      int mode, const MergeArgs& o, hipStream_t st) {
+                      int mode, const MergeArgs& o, bool sorted_input, hipStream_t st) {
   const RotString P = rot_string(s->n, px, pz);
   if (mode == PAULI_ROTATE_CONJUGATE) {
     if (s->m == 0) return merge_generic(s, nullptr, o, st);
-    return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, st)
-                                  : conjugate_t<float>(s, P, theta, o, st);
+    return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, sorted_input, st)
+                                  : conjugate_t<float>(s, P, theta, o, sorted_input, st);
   }
   paulisum* R = rotation_sum(s, P, theta, st);
   paulisum* r = nullptr;

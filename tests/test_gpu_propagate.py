@@ -95,3 +95,37 @@ def test_propagate_small_n_many_merges():
     for rm in (pl.ROTATE_CONJUGATE, pl.ROTATE_PRODUCT):
         g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, rotate_mode=rm).export()
         parity.assert_merged_fp64(g, O.propagate(_osum(S), x, z, th, mode=rm))
+
+
+@pytest.mark.parametrize("key_bits", [6, 20])
+def test_conjugation_merge_path_with_truncated_keys(key_bits):
+    """After the first step the conjugation merges the kept (already sorted)
+    strings with the sorted new strings instead of sorting everything.
+    Truncated keys make many distinct strings share a key across the two
+    lists; every step must still match the oracle and stay in key order."""
+    S = _state(2000)
+    th, x, z = _rots(6)
+    g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, rotate_mode=pl.ROTATE_CONJUGATE,
+                     key_bits=key_bits).export()
+    ref = O.propagate(_osum(S), x, z, th, mode=O.CONJUGATE)
+    parity.assert_merged_fp64(g, ref)
+    parity.assert_sorted_by_key(g, key_bits=key_bits)
+
+
+def test_conjugation_steps_without_anticommuting_terms():
+    """A rotation string that commutes with every term (Z-only strings on a
+    Z-only state) leaves the state unchanged step after step."""
+    rng = synth.rng_for(731)
+    n, m = 80, 500
+    W = 2
+    zs = rng.integers(0, 2 ** 62, size=(m, W), dtype=np.uint64)
+    zs[:, 1] &= np.uint64((1 << 16) - 1)
+    S = {"n": n, "x": np.zeros_like(zs), "z": zs, "phase": np.zeros(m, np.uint8),
+         "coef": rng.standard_normal(m) + 1j * rng.standard_normal(m)}
+    px = np.zeros((3, W), np.uint64)
+    pz = rng.integers(0, 2 ** 62, size=(3, W), dtype=np.uint64)
+    pz[:, 1] &= np.uint64((1 << 16) - 1)
+    g = pl.propagate(pl.PauliSum.from_dict(S), px, pz, [0.3, 0.7, 1.1],
+                     rotate_mode=pl.ROTATE_CONJUGATE).export()
+    ref = O.merge(_osum(S))
+    parity.assert_merged_fp64(g, ref)
