@@ -32,21 +32,6 @@ struct Words {
   uint64_t z[WT][kBlock];
 };
 
-template <int WT>
-__device__ __forceinline__ void get_bits(const Words<WT>& s, int q, uint32_t& xb, uint32_t& zb) {
-  const int w = q >> 6, b = q & 63, t = threadIdx.x;
-  xb = static_cast<uint32_t>(s.x[w][t] >> b) & 1u;
-  zb = static_cast<uint32_t>(s.z[w][t] >> b) & 1u;
-}
-
-template <int WT>
-__device__ __forceinline__ void put_bits(Words<WT>& s, int q, uint32_t xb, uint32_t zb) {
-  const int w = q >> 6, b = q & 63, t = threadIdx.x;
-  const uint64_t m = 1ull << b;
-  s.x[w][t] = (s.x[w][t] & ~m) | (static_cast<uint64_t>(xb) << b);
-  s.z[w][t] = (s.z[w][t] & ~m) | (static_cast<uint64_t>(zb) << b);
-}
-
 // One gate's conjugation on the letters of its qubits (letters by Table I:
 // (x, z) = (1, 0) X, (0, 1) Z, (1, 1) Y).  Returns 1 when the string's sign
 // flips.  The rules are the images of X, Z (and Y = i X Z) under U . U^dag:
@@ -55,12 +40,21 @@ __device__ __forceinline__ void put_bits(Words<WT>& s, int q, uint32_t xb, uint3
 //   CX(c,t): X_c -> X_c X_t, Z_t -> Z_c Z_t (X_t, Z_c unchanged)
 //   CZ(a,b): X_a -> X_a Z_b, X_b -> Z_a X_b (Z unchanged)
 //   SWAP: the two letters exchange places
+// Each word the gate touches is read once from LDS and written once.
 template <int WT>
 __device__ __forceinline__ uint32_t apply_gate(Words<WT>& s, const DevGate& g, uint64_t& fp) {
-  uint32_t x0, z0, x1 = 0, z1 = 0, flip = 0;
-  get_bits<WT>(s, g.q0, x0, z0);
-  if (g.kind >= PAULI_GATE_CX) get_bits<WT>(s, g.q1, x1, z1);
-  uint32_t nx0 = x0, nz0 = z0, nx1 = x1, nz1 = z1;
+  const int t = threadIdx.x;
+  const bool two = g.kind >= PAULI_GATE_CX;
+  const int w0 = g.q0 >> 6, b0 = g.q0 & 63, w1 = g.q1 >> 6, b1 = g.q1 & 63;
+  uint64_t xw0 = s.x[w0][t], zw0 = s.z[w0][t];
+  uint64_t xw1 = xw0, zw1 = zw0;
+  if (two && w1 != w0) {
+    xw1 = s.x[w1][t];
+    zw1 = s.z[w1][t];
+  }
+  const uint32_t x0 = static_cast<uint32_t>(xw0 >> b0) & 1u, z0 = static_cast<uint32_t>(zw0 >> b0) & 1u;
+  const uint32_t x1 = static_cast<uint32_t>(xw1 >> b1) & 1u, z1 = static_cast<uint32_t>(zw1 >> b1) & 1u;
+  uint32_t nx0 = x0, nz0 = z0, nx1 = x1, nz1 = z1, flip = 0;
   switch (g.kind) {
     case PAULI_GATE_H:
       nx0 = z0; nz0 = x0; flip = x0 & z0;
@@ -90,13 +84,25 @@ __device__ __forceinline__ uint32_t apply_gate(Words<WT>& s, const DevGate& g, u
       nx0 = x1; nz0 = z1; nx1 = x0; nz1 = z0;
       break;
   }
-  if (nx0 != x0) fp ^= g.col[0];
-  if (nz0 != z0) fp ^= g.col[1];
-  put_bits<WT>(s, g.q0, nx0, nz0);
-  if (g.kind >= PAULI_GATE_CX) {
-    if (nx1 != x1) fp ^= g.col[2];
-    if (nz1 != z1) fp ^= g.col[3];
-    put_bits<WT>(s, g.q1, nx1, nz1);
+  // bit changes as XOR masks, then fingerprint columns of the changed bits
+  const uint64_t dx0 = static_cast<uint64_t>(nx0 ^ x0) << b0, dz0 = static_cast<uint64_t>(nz0 ^ z0) << b0;
+  const uint64_t dx1 = static_cast<uint64_t>(nx1 ^ x1) << b1, dz1 = static_cast<uint64_t>(nz1 ^ z1) << b1;
+  if (dx0) fp ^= g.col[0];
+  if (dz0) fp ^= g.col[1];
+  if (two) {
+    if (dx1) fp ^= g.col[2];
+    if (dz1) fp ^= g.col[3];
+  }
+  if (two && w1 == w0) {
+    s.x[w0][t] = xw0 ^ dx0 ^ dx1;
+    s.z[w0][t] = zw0 ^ dz0 ^ dz1;
+  } else {
+    s.x[w0][t] = xw0 ^ dx0;
+    s.z[w0][t] = zw0 ^ dz0;
+    if (two) {
+      s.x[w1][t] = xw1 ^ dx1;
+      s.z[w1][t] = zw1 ^ dz1;
+    }
   }
   return flip;
 }

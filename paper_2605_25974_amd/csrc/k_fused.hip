@@ -63,6 +63,14 @@ inline unsigned grid_for(int64_t n, int per = kB, int64_t cap = 65536) {
   return static_cast<unsigned>(g);
 }
 
+// Compute units of the current device.
+inline uint32_t device_cus() {
+  int dev = 0, n = 0;
+  PAULI_HIP(hipGetDevice(&dev));
+  PAULI_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+  return n > 0 ? static_cast<uint32_t>(n) : 1u;
+}
+
 __device__ __forceinline__ uint32_t wave_incl(uint32_t v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -402,12 +410,35 @@ __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32
 
 // ------------------------------------------------------------ bucket sort
 
+// Counting sort of a bucket: 2^14 bins on the key bits just below the bucket
+// bits, two 16-bit counters per word (a bucket holds at most kCap = 8192
+// records, so neither counts nor starts carry into the other half).
+constexpr int kBinBits = 14;
+constexpr int kBins = 1 << kBinBits;
+constexpr int kBinWords = kBins / 2;
+constexpr uint32_t kMaxBin = 64;  // a bucket with a larger bin takes k_heavy_sort
+constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited for
+
 struct SortSmem {
   uint64_t key[kCap];
   uint32_t id[kCap];
-  uint32_t cnt[kSortWaves][256];
+  union {
+    uint32_t cnt[kSortWaves][256];  // radix sort: per-wave digit counters
+    uint32_t bins[kBinWords + 1];   // counting sort: counts, then starts; bin kBins starts at N
+  };
+  uint16_t perm[kCap];  // counting sort: position of the p-th record in key / id
   uint32_t scan[kSortWaves];
   uint32_t wcount[kSortWaves];
+};
+
+// Bit fields of the bucket sort: the counting sort takes bits
+// [lo14, lo14 + 14) (lo14 < 0: not used), the radix sort bits
+// [lo16, lo16 + 8*passes) with ties on fmask finished on the full key.
+struct SortField {
+  int lo14;
+  int lo16;
+  int passes;
+  uint64_t fmask;
 };
 
 __device__ __forceinline__ uint32_t sort_span(uint32_t N) {
@@ -524,45 +555,126 @@ __device__ bool lds_fix_runs(uint32_t N, int lo, uint64_t fmask, SortSmem& S) {
   return true;
 }
 
-struct SegOut {
-  uint32_t* vals;    // sorted pair ids, written over the bucket's records
-  uint32_t* segidx;  // [record] segment index inside the bucket
-  uint32_t* nseg;    // [bucket] segment count
-  uint32_t* long_list;  // (bucket, first record) of segments longer than kLong
-  uint32_t* nlong;
-};
 
-// Buckets that fit in LDS.  A larger bucket is queued for k_heavy_sort.
-__global__ void __launch_bounds__(kSortNT)
-k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
-              uint32_t nbk, int sort_lo, int passes, uint64_t fmask, SegOut out,
-              uint32_t* __restrict__ heavy, uint32_t* __restrict__ nheavy) {
-  __shared__ SortSmem S;
-  const uint32_t b = blockIdx.x;
-  if (b >= nbk) return;
-  const uint32_t lo = boff[b], n = boff[b + 1] - lo;
-  if (n > static_cast<uint32_t>(kCap)) {
-    if (threadIdx.x == 0) heavy[atomicAdd(nheavy, 1u)] = b;
-    return;
+__device__ __forceinline__ uint32_t bin_start(const SortSmem& S, uint32_t d) {
+  return (S.bins[d >> 1] >> ((d & 1u) * 16u)) & 0xFFFFu;
+}
+
+// Counting sort of a bucket, first half: the (key, id) pairs k[], v[] are
+// counted in 2^14 bins of the key bits at lo (a record's place in its bin
+// comes from an LDS atomic) and scattered to S.key / S.id grouped by bin.
+// Returns false, with S.key / S.id untouched, when a bin holds more than
+// kMaxBin records (many equal keys).  k[], v[] are not read afterwards.
+__device__ bool count_scatter(uint32_t N, int lo, const uint64_t (&k)[kSortRounds],
+                              const uint32_t (&v)[kSortRounds], SortSmem& S) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t span = sort_span(N);
+  const int rounds = static_cast<int>(span / 64);
+  for (int i = threadIdx.x; i <= kBinWords; i += kSortNT) S.bins[i] = 0;
+  __syncthreads();
+  // a lane past the end adds 0 to a counter of its own
+  uint32_t dd[kSortRounds], old[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    dd[r] = 0;
+    old[r] = 0;
+    if (r >= rounds) break;
+    const uint32_t q = wave * span + r * 64 + lane;
+    const bool valid = q < N;
+    const uint32_t d = valid ? static_cast<uint32_t>(k[r] >> lo) & (kBins - 1u) : 2u * lane;
+    dd[r] = d;
+    old[r] = atomicAdd(&S.bins[d >> 1], valid ? 1u << ((d & 1u) * 16u) : 0u);
   }
+  __syncthreads();
+  // bins [16t, 16t + 16) belong to thread t (words [8t, 8t + 8))
+  static_assert(kBinWords == 8 * kSortNT, "eight words per thread");
+  uint4* mine = reinterpret_cast<uint4*>(&S.bins[8 * threadIdx.x]);
+  const uint4 w0 = mine[0], w1 = mine[1];
+  uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+  uint32_t tot = 0, mx = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t c0 = w[i] & 0xFFFFu, c1 = w[i] >> 16;
+    tot += c0 + c1;
+    mx = max(mx, max(c0, c1));
+  }
+  uint32_t run = block_excl<kSortWaves>(tot, nullptr, S.scan);
+  if (__syncthreads_or(mx > kMaxBin)) return false;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t c0 = w[i] & 0xFFFFu, c1 = w[i] >> 16;
+    w[i] = run | ((run + c0) << 16);
+    run += c0 + c1;
+  }
+  mine[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  mine[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  if (threadIdx.x == 0) S.bins[kBinWords] = N;
+  __syncthreads();
+  uint32_t np[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    np[r] = 0;
+    if (r >= rounds) break;
+    const uint32_t d = dd[r];
+    np[r] = bin_start(S, d) + ((old[r] >> ((d & 1u) * 16u)) & 0xFFFFu);
+  }
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (r >= rounds) break;
+    const uint32_t q = wave * span + r * 64 + lane;
+    if (q < N) {
+      S.key[np[r]] = k[r];
+      S.id[np[r]] = v[r];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Counting sort, second half: every bin is put in (key, id) order.  The
+// sorted position of a record is its bin's start plus the number of smaller
+// records in the bin, and S.perm[p] = where the p-th record lies in S.key /
+// S.id.  Equal keys end up ordered by pair id, so the result does not
+// depend on the order of the atomics.
+__device__ void count_order(uint32_t N, int lo, SortSmem& S) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t span = sort_span(N);
+  const int rounds = static_cast<int>(span / 64);
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (r >= rounds) break;
+    const uint32_t q = wave * span + r * 64 + lane;
+    if (q < N) {
+      const uint64_t kq = S.key[q];
+      const uint32_t iq = S.id[q];
+      const uint32_t d = static_cast<uint32_t>(kq >> lo) & (kBins - 1u);
+      const uint32_t s0 = bin_start(S, d), e0 = bin_start(S, d + 1);
+      uint32_t p = q;
+      if (e0 - s0 > 1) {
+        uint32_t rank = 0;
+        for (uint32_t y = s0; y < e0; ++y) {
+          const uint64_t ky = S.key[y];
+          const uint32_t iy = S.id[y];
+          rank += (ky < kq || (ky == kq && iy < iq)) ? 1u : 0u;
+        }
+        p = s0 + rank;
+      }
+      S.perm[p] = static_cast<uint16_t>(q);
+    }
+  }
+  __syncthreads();
+}
+
+// Radix path of a bucket (key fields narrower than the counting sort's):
+// stable LSD sort on the radix field, ties finished on the full key.
+__device__ void radix_bucket(uint32_t n, uint64_t (&k)[kSortRounds], uint32_t (&v)[kSortRounds],
+                             const SortField& f, SortSmem& S) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t span = sort_span(n);
   const int rounds = static_cast<int>(span / 64);
-  uint64_t k[kSortRounds];
-  uint32_t v[kSortRounds];
-#pragma unroll
-  for (int r = 0; r < kSortRounds; ++r) {
-    k[r] = 0;
-    v[r] = 0;
-    if (r >= rounds) continue;
-    const uint32_t q = wave * span + r * 64 + lane;
-    if (q < n) {
-      k[r] = keys[lo + q];
-      v[r] = out.vals[lo + q];
-    }
-  }
-  if (passes > 0) {
-    lds_sort(n, sort_lo, passes, k, v, S);
+  __syncthreads();  // the block's previous bucket is no longer read
+  if (f.passes > 0) {
+    lds_sort(n, f.lo16, f.passes, k, v, S);
   } else {
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
@@ -575,17 +687,51 @@ k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bo
     }
   }
   __syncthreads();
-  if (lds_fix_runs(n, sort_lo, fmask, S)) {
+  lds_fix_runs(n, f.lo16, f.fmask, S);
+}
+
+struct SegOut {
+  uint32_t* vals;    // sorted pair ids, written over the bucket's records
+  uint32_t* segidx;  // [record] segment index inside the bucket
+  uint32_t* nseg;    // [bucket] segment count
+  uint32_t* long_list;  // (bucket, first record) of segments longer than kLong
+  uint32_t* nlong;
+};
+
+// Loads the (key, id) records of a bucket of n <= kCap records starting at
+// lo into the lane's slots (position wave*span + r*64 + lane); a larger
+// bucket loads nothing.
+__device__ __forceinline__ void load_bucket(const uint64_t* __restrict__ keys,
+                                            const uint32_t* vals, uint32_t lo, uint32_t n,
+                                            uint64_t (&k)[kSortRounds],
+                                            uint32_t (&v)[kSortRounds]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool fits = n <= static_cast<uint32_t>(kCap);
+  const uint32_t span = sort_span(n);
+  const int rounds = fits ? static_cast<int>(span / 64) : 0;
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-      if (r >= rounds) break;
-      const uint32_t q = wave * span + r * 64 + lane;
-      if (q < n) {
-        k[r] = S.key[q];
-        v[r] = S.id[q];
-      }
+  for (int r = 0; r < kSortRounds; ++r) {
+    k[r] = 0;
+    v[r] = 0;
+    if (r >= rounds) continue;
+    const uint32_t q = wave * span + r * 64 + lane;
+    if (q < n) {
+      k[r] = keys[lo + q];
+      v[r] = vals[lo + q];
     }
   }
+}
+
+// Segments of a sorted bucket (the p-th record at S.key / S.id [at(p)],
+// at = S.perm with PERM, else the identity): writes the sorted pair ids, the
+// segment index of every record, the bucket's segment count and the long
+// segments.
+template <bool PERM>
+__device__ void bucket_segments(uint32_t b, uint32_t lo, uint32_t n, SortSmem& S,
+                                const SegOut& out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t span = sort_span(n);
+  const int rounds = static_cast<int>(span / 64);
   // segment heads (a key differing from the one before), counted per wave
   uint64_t hb[kSortRounds];
   uint32_t hc = 0;
@@ -595,7 +741,7 @@ k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bo
     if (r >= rounds) break;
     const uint32_t q = wave * span + r * 64 + lane;
     bool head = false;
-    if (q < n) head = q == 0 || S.key[q - 1] != k[r];
+    if (q < n) head = q == 0 || S.key[PERM ? S.perm[q - 1] : q - 1] != S.key[PERM ? S.perm[q] : q];
     hb[r] = __ballot(head);
     hc += static_cast<uint32_t>(__popcll(hb[r]));
   }
@@ -613,13 +759,15 @@ k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bo
     const uint32_t q = wave * span + r * 64 + lane;
     if (q < n) {
       const uint32_t seg = run + static_cast<uint32_t>(__popcll(hb[r] & (lt | (1ull << lane)))) - 1;
-      out.vals[lo + q] = v[r];
+      const uint32_t at = PERM ? S.perm[q] : q;
+      out.vals[lo + q] = S.id[at];
       out.segidx[lo + q] = seg;
       if ((hb[r] >> lane) & 1) {
         // segments longer than kLong: queued for the block-wide reduction
+        const uint64_t kq = S.key[at];
         const uint32_t lim = q + kLong + 1 < n ? q + kLong + 1 : n;
         uint32_t e = q + 1;
-        while (e < lim && S.key[e] == k[r]) ++e;
+        while (e < lim && S.key[PERM ? S.perm[e] : e] == kq) ++e;
         if (e - q > static_cast<uint32_t>(kLong)) {
           const uint32_t slot = atomicAdd(out.nlong, 1u);
           out.long_list[2 * slot] = b;
@@ -630,6 +778,60 @@ k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bo
     run += static_cast<uint32_t>(__popcll(hb[r]));
   }
   if (threadIdx.x == 0) out.nseg[b] = total;
+}
+
+// Buckets that fit in LDS.  One block per compute unit takes the buckets
+// blockIdx.x, blockIdx.x + gridDim.x, ...  COUNT (the counting sort): once
+// a bucket is scattered into bins, the block loads the records of its next
+// bucket, so that the loads overlap the rest of the work.  A bucket over
+// kCap records, or one the counting sort gives up on, is queued for
+// k_heavy_sort.
+template <bool COUNT>
+__global__ void __launch_bounds__(kSortNT)
+k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
+              uint32_t nbk, SortField f, SegOut out, uint32_t* __restrict__ heavy,
+              uint32_t* __restrict__ nheavy) {
+  __shared__ SortSmem S;
+  uint64_t k[kSortRounds];
+  uint32_t v[kSortRounds];
+  uint32_t b = blockIdx.x, lo = 0, n = 0;
+  if (COUNT && b < nbk) {
+    lo = boff[b];
+    n = boff[b + 1] - lo;
+    load_bucket(keys, out.vals, lo, n, k, v);
+  }
+  for (; b < nbk; b += gridDim.x) {
+    if (!COUNT) {
+      lo = boff[b];
+      n = boff[b + 1] - lo;
+      load_bucket(keys, out.vals, lo, n, k, v);
+    }
+    bool ok = n <= static_cast<uint32_t>(kCap);
+    if (COUNT) {
+      if (ok) ok = count_scatter(n, f.lo14, k, v, S);
+      // every load of this bucket has been used: the wait is free, and it
+      // keeps the compiler from waiting for the next bucket's loads when it
+      // reuses their registers
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      const uint32_t b2 = b + gridDim.x;
+      uint32_t lo2 = 0, n2 = 0;
+      if (b2 < nbk) {
+        lo2 = boff[b2];
+        n2 = boff[b2 + 1] - lo2;
+      }
+      load_bucket(keys, out.vals, lo2, n2, k, v);
+      if (ok) {
+        count_order(n, f.lo14, S);
+        bucket_segments<true>(b, lo, n, S, out);
+      }
+      lo = lo2;
+      n = n2;
+    } else if (ok) {
+      radix_bucket(n, k, v, f, S);
+      bucket_segments<false>(b, lo, n, S, out);
+    }
+    if (!ok && threadIdx.x == 0) heavy[atomicAdd(nheavy, 1u)] = b;
+  }
 }
 
 // Buckets larger than kCap: one block sorts the bucket's records on all key
@@ -819,16 +1021,16 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   const uint32_t nc = 1u << d1;
   const uint32_t nbk = 1u << d;
   const int rem = kb - d;  // key bits below the bucket bits
-  int sort_lo, passes;
-  uint64_t fmask;
+  SortField sf;
+  sf.lo14 = rem >= kBinBits ? rem - kBinBits : -1;
   if (rem >= 16) {
-    sort_lo = rem - 16;
-    passes = 2;
-    fmask = 0xFFFFull;
+    sf.lo16 = rem - 16;
+    sf.passes = 2;
+    sf.fmask = 0xFFFFull;
   } else {
-    sort_lo = 0;
-    passes = (rem + 7) / 8;
-    fmask = rem ? ((1ull << rem) - 1) : 0ull;
+    sf.lo16 = 0;
+    sf.passes = (rem + 7) / 8;
+    sf.fmask = rem ? ((1ull << rem) - 1) : 0ull;
   }
 
   // pair id: (j << ibits) | i when that fits in 32 bits, else j*|a| + i
@@ -907,8 +1109,14 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   SegOut so{V, segidx.as<uint32_t>(), nseg.as<uint32_t>(), long_list.as<uint32_t>(), ctr32 + 1};
   {
     StageScope sc(PAULI_STAGE_SEGMENT, s, Peff * 20.0);
-    hipLaunchKernelGGL(k_bucket_sort, dim3(nbk), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(), nbk,
-                       sort_lo, passes, fmask, so, heavy.as<uint32_t>(), ctr32);
+    // one block per compute unit (the LDS of a block fills most of one)
+    const uint32_t gsort = nbk < static_cast<uint32_t>(device_cus()) ? nbk : device_cus();
+    if (sf.lo14 >= 0)
+      hipLaunchKernelGGL(k_bucket_sort<true>, dim3(gsort), dim3(kSortNT), 0, s, K,
+                         boff.as<uint32_t>(), nbk, sf, so, heavy.as<uint32_t>(), ctr32);
+    else
+      hipLaunchKernelGGL(k_bucket_sort<false>, dim3(gsort), dim3(kSortNT), 0, s, K,
+                         boff.as<uint32_t>(), nbk, sf, so, heavy.as<uint32_t>(), ctr32);
     hipLaunchKernelGGL(k_heavy_sort, dim3(64), dim3(kSortNT), 0, s, K, K2, V2, boff.as<uint32_t>(),
                        rem, heavy.as<uint32_t>(), ctr32, so);
     PAULI_HIP(hipGetLastError());
