@@ -241,31 +241,52 @@ struct GenSides {
   int d1;
 };
 
-// The super-bucket's tile offsets and class sizes, staged in LDS.
+// The super-bucket's tile offsets and class sizes, staged in LDS, with
+// mb[h] = floor((2^32 - 1) / nb[h]) for the division by nb[h], and the
+// classes [h0, h1] that the block's partition tile spans.
 struct GenRow {
-  uint32_t t[256], na[256], a0[256], nb[256], b0[256];
+  uint32_t t[256], na[256], a0[256], nb[256], b0[256], mb[256];
+  uint32_t h0, h1;
 };
 
-__device__ __forceinline__ void load_gen_row(const GenSides& G, uint32_t s, GenRow& R) {
+// Every thread calls it; R is complete after the caller's next barrier.
+__device__ __forceinline__ void load_gen_row(const GenSides& G, uint32_t s, uint32_t lo,
+                                             uint32_t hi, GenRow& R) {
   const uint32_t nc = 1u << G.d1;
   for (uint32_t h = threadIdx.x; h < nc; h += blockDim.x) {
     R.t[h] = G.Tt[s * nc + h];
     R.na[h] = G.gA[h];
     R.a0[h] = G.gsA[h];
-    R.nb[h] = G.gB[h ^ s];
+    const uint32_t nb = G.gB[h ^ s];
+    R.nb[h] = nb;
+    R.mb[h] = nb ? 0xFFFFFFFFu / nb : 0u;
     R.b0[h] = G.gsB[h ^ s];
+  }
+  __syncthreads();
+  // record q lies in the largest class h with t[h] <= q
+  const uint32_t last = hi > lo ? hi - 1 : lo;
+  for (uint32_t h = threadIdx.x; h < nc; h += blockDim.x) {
+    const uint32_t t0 = R.t[h], t1 = h + 1 < nc ? R.t[h + 1] : 0xFFFFFFFFu;
+    if (t0 <= lo && lo < t1) R.h0 = h;
+    if (t0 <= last && last < t1) R.h1 = h;
   }
 }
 
 __device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, uint32_t q,
                                            uint64_t& key, uint32_t& val) {
-  uint32_t lo = 0, hi = 1u << G.d1;  // largest h with t[h] <= q
+  uint32_t lo = R.h0, hi = R.h1 + 1;  // largest h with t[h] <= q
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (R.t[mid] <= q) lo = mid; else hi = mid;
   }
   const uint32_t t = q - R.t[lo], nb = R.nb[lo];
-  const uint32_t ia = t / nb, jb = t - ia * nb;
+  // t / nb: the estimate floor(t * mb / 2^32) is the quotient or one less
+  uint32_t ia = __umulhi(t, R.mb[lo]);
+  uint32_t jb = t - ia * nb;
+  if (jb >= nb) {
+    ++ia;
+    jb -= nb;
+  }
   const uint32_t a = R.a0[lo] + ia, b = R.b0[lo] + jb;
   const uint32_t i = G.sidxA[a], j = G.sidxB[b];
   key = G.skeyA[a] ^ G.skeyB[b];
@@ -283,10 +304,10 @@ k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict_
   uint32_t s, tl;
   if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
   hist[threadIdx.x] = 0;
-  load_gen_row(G, s, R);
-  __syncthreads();
   const uint32_t lo = tl * kTile;
   const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
+  load_gen_row(G, s, lo, hi, R);
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t q = lo + r * kB + threadIdx.x;
@@ -329,9 +350,10 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
 #pragma unroll
   for (int w = 0; w < NW; ++w) s_wc[w][tid] = 0;
   s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
-  load_gen_row(G, s, R);
+  load_gen_row(G, s, lo, hi, R);
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
+  const int dbits = __popc(mask);  // digit bits (mask = 2^d2 - 1, d2 <= 8)
   // digit in bits 0-7 and rank among the wave's equal digits above, or ~0
   uint32_t dr[kItems];
 #pragma unroll
@@ -348,6 +370,7 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
+      if (bit >= dbits) break;
       const bool on = valid && ((d >> bit) & 1);
       const uint64_t bm = __ballot(on);
       peers &= on ? bm : ~bm;
