@@ -192,7 +192,7 @@ typedef struct {
 } pauli_gate_t;
 
 /* pauli_apply_clifford: conjugation of every term by a Clifford circuit
- * (Section II-B, Clifford paragraph: a Clifford maps each string to a single
+ * (Section III-B, Clifford paragraph: a Clifford maps each string to a single
  * string, so the number of terms does not change; Section V-B, "Gate
  * Application").  Term t of the output is C (i^k c P) C^dagger with
  * C = G_{n_gates-1} ... G_1 G_0 (gates[0] conjugates first): its string is
@@ -219,7 +219,7 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
                                            void* stream);
 
 /* pauli_propagate: a sequence of Pauli rotations applied to a sum (Section
- * II-D, eq. (5); Section III-B, truncation).  Step t uses the string
+ * III-B: eq. (5) and its truncation).  Step t uses the string
  * P_t = (p_x[t], p_z[t]) (packed as in paulisum_create, W words each, host
  * memory) and the angle theta[t] (host memory); R_t = cos(theta_t) I
  * - i sin(theta_t) P_t.

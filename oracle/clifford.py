@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by the tests and the benchmark's
 CPU-baseline leg, never by the product path; it shares no code with the HIP
 library.
 
-Definition followed (Section II-B, Clifford paragraph; Section V-B, "Gate
+Definition followed (Section III-B, Clifford paragraph; Section V-B, "Gate
 Application"): a Clifford U maps a Pauli string Q to the single string
 U Q U^dagger up to a sign, so a gate relabels strings and keeps the number of
 terms.  The oracle takes that definition literally: each gate's unitary is

@@ -28,9 +28,9 @@
 //    exact cancellation gives exactly zero.
 //  * Truncation, Section III-B (non-Clifford paragraph): a merged term whose
 //    modulus is strictly below a threshold is removed.
-//  * Commutation, Section II-C: two strings anticommute when the number of
+//  * Commutation, Section III-A: two strings anticommute when the number of
 //    qubits holding two different non-identity letters is odd.
-//  * Rotation step, Section II-D eq. (5): with R = cos(theta) I
+//  * Rotation step, Section III-B eq. (5): with R = cos(theta) I
 //    - i sin(theta) P, "product" mode left-multiplies every term by R;
 //    "conjugation" mode leaves a term Q that commutes with P unchanged and
 //    maps an anticommuting Q to cos(theta) Q - i sin(theta) PQ.  Each step is
@@ -249,7 +249,7 @@ struct Sum {
   int phase(int64_t t) const { return ph ? (ph[t] & 3) : 0; }
 };
 
-// Section II-C: anticommute iff an odd number of qubits hold two different
+// Section III-A: anticommute iff an odd number of qubits hold two different
 // non-identity letters.
 int anticommutes(const std::string& a, const std::string& b) {
   int c = 0;
@@ -359,7 +359,7 @@ void* oracle_product_merge(int n, int64_t m1, const uint64_t* x1, const uint64_t
 
 // The commutator [H1, H2] = H1*H2 - H2*H1, merged.  For each pair both
 // orders are multiplied letter by letter; when the two products differ (the
-// strings anticommute, Section II-C, and the phases differ by 2), the pair
+// strings anticommute, Section III-A, and the phases differ by 2), the pair
 // contributes a_i b_j - b_j a_i to the product's string, summed exactly.
 // Pairs whose two orders agree contribute nothing and create no term.
 void* oracle_commutator(int n, int64_t m1, const uint64_t* x1, const uint64_t* z1,
@@ -387,7 +387,7 @@ void* oracle_commutator(int n, int64_t m1, const uint64_t* x1, const uint64_t* z
   return finish(n, acc, drop_abs);
 }
 
-// A sequence of rotation steps (Section II-D eq. (5)) applied to the merged
+// A sequence of rotation steps (Section III-B eq. (5)) applied to the merged
 // input sum.  Step s uses the string (px, pz)[s] and angle theta[s]; mode 0
 // multiplies every term on the left by cos(theta) I - i sin(theta) P, mode 1
 // conjugates (commuting terms unchanged).  After each step equal strings are

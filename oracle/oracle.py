@@ -213,7 +213,7 @@ PRODUCT, CONJUGATE = 0, 1
 
 
 def propagate(s: Sum, px, pz, theta, mode=CONJUGATE, drop_abs: float = -1.0) -> Merged:
-    """Rotation steps of Section II-D eq. (5) on the merged sum s: step t uses
+    """Rotation steps of Section III-B eq. (5) on the merged sum s: step t uses
     the string (px[t], pz[t]) (packed words, shape (steps, W)) and angle
     theta[t].  mode PRODUCT multiplies every term on the left by
     cos(theta) I - i sin(theta) P; CONJUGATE leaves terms commuting with P

@@ -1,4 +1,4 @@
-// Clifford gates on a Pauli sum (Section II-B, Clifford paragraph: a
+// Clifford gates on a Pauli sum (Section III-B, Clifford paragraph: a
 // Clifford conjugation maps every string to one string and keeps the number
 // of terms; Section V-B: H, S, CNOT, CZ relabel strings in place; Section
 // IV-B: on the struct-of-arrays layout the update is a branch-free loop over

@@ -1,4 +1,4 @@
-// Rotation steps of a Pauli-propagation loop (Section II-D, eq. (5)).
+// Rotation steps of a Pauli-propagation loop (Section III-B, eq. (5)).
 //
 // R = cos(theta) I - i sin(theta) P.
 //   product mode:     S <- merge(R * S), the fused outer product of the

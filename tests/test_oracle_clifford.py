@@ -85,7 +85,7 @@ def test_inverse_circuit_restores_terms():
 
 def test_pauli_gate_sign_rule():
     """Conjugation by a Pauli gate P keeps the string and flips its sign
-    exactly when the letter on that qubit anticommutes with P (Section II-B,
+    exactly when the letter on that qubit anticommutes with P (Section III-B,
     theta = pi case)."""
     n = 3
     letters = ["IXY", "ZZZ", "YIX"]

@@ -1,7 +1,7 @@
 """Pins of the oracle's commutator [H1, H2] = H1*H2 - H2*H1 (no GPU).
 
 The commutator keeps one term per string that an anticommuting pair gives
-(Section II-C: P Q = -Q P exactly when the strings anticommute).  It is
+(Section III-A: P Q = -Q P exactly when the strings anticommute).  It is
 pinned against dense matrices, against the algebraic identities every
 commutator obeys, and against a planted table mistake."""
 import numpy as np

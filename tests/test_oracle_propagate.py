@@ -1,4 +1,4 @@
-"""Pins of the oracle's rotation steps (Section II-D eq. (5)) against dense
+"""Pins of the oracle's rotation steps (Section III-B eq. (5)) against dense
 matrices, the paper's special angles and the unitary-invariance of the
 Hilbert-Schmidt norm.  CPU only."""
 import numpy as np
@@ -76,7 +76,7 @@ def test_norm_is_invariant(mode):
 
 
 def test_clifford_and_pauli_angles():
-    """Section II-D: at theta = pi/2 an anticommuting Q becomes -i P Q; at
+    """Section III-B: at theta = pi/2 an anticommuting Q becomes -i P Q; at
     theta = pi it becomes -Q; commuting terms never change.  The round-off
     remnants of cos(pi/2) and sin(pi) are truncated."""
     rng = synth.rng_for(722)
