@@ -46,6 +46,8 @@ WORKLOADS = {
        "complex128 (1e8 pairs)",
     7: "Clifford circuit of 112 random gates (H, S, S^dag, X, Y, Z, CX, CZ, SWAP) on the "
        "1e6-term n=500 propagation state, complex128",
+    8: "lexicographic order of the merged product of the n=500 10,000 x 10,000 "
+       "Jordan-Wigner-shaped sums (about 1e8 terms), complex128",
 }
 # sources of the kernel each stage's traffic figure was measured on
 STAGE_SOURCES = {
@@ -416,6 +418,61 @@ def _clifford(pl, torch, args):
     return rec
 
 
+def _lex(pl, torch, args):
+    """Lexicographic order (pauli_sort_lex) of the merged 1e8-product output:
+    terms/s, the merged sum resident in HBM before timing."""
+    import synth
+    A, B = synth.workload2()
+    S = pl.outer_product_merged(pl.PauliSum.from_dict(A), pl.PauliSum.from_dict(B))
+    m = S.m
+    for _ in range(args.warmup):
+        pl.sort_lex(S).destroy()
+    torch.cuda.synchronize()
+    pl.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pl.sort_lex(S).destroy()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = pl.profile_read()
+    pl.profile_enable(False)
+    ms, launches, by = stages["lex"]
+    achieved = (by / launches) / (ms / launches * 1e-3) / 1e9
+    rec = {
+        "metric": "Pauli terms/s put in lexicographic order",
+        "value": m * args.steps / elapsed, "unit": "terms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64 (keys)",
+        "data": "synthetic (seeded generators of the workload's shape)",
+        "config": {"workload": WORKLOADS[8], "terms": m},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items()},
+        # the whole call: word gathers, radix passes and the final row gather
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "sort_lex (all kernels of the call)",
+                     "stage": "lex", "launch_ms": round(ms / launches, 4),
+                     "algorithmic_bytes_per_launch": by / launches},
+    }
+    S.destroy()
+    if not args.no_cpu_baseline:
+        from oracle import lexorder as L
+        from oracle import oracle as O
+        SA = O.Sum(A["n"], A["x"], A["z"], A["phase"], A["coef"])
+        SB = O.Sum(B["n"], B["x"], B["z"], B["phase"], B["coef"])
+        rows = 100
+        ref = O.product_merge(SA, SB, i_range=(0, rows))
+        t = time.perf_counter()
+        L.order(ref.x, ref.z)
+        dt = time.perf_counter() - t
+        rec["cpu_baseline"] = {
+            "value": ref.x.shape[0] / dt, "unit": "terms/s", "cores": 1, "kind": "oracle",
+            "sample": "the oracle's merged product of rows 0..%d of the left sum with all "
+                      "10,000 right terms (%d strings), ordered by the lexicographic oracle "
+                      "(numpy lexsort), %.2f s, one thread" % (rows - 1, ref.x.shape[0], dt)}
+    return rec
+
+
 def copy_calibration(steps):
     import torch
     n = COPY_BYTES // 4
@@ -455,9 +512,9 @@ def main():
     import paper_2605_25974_amd as pl
 
     torch.cuda.set_device(0)
-    if args.workload in (4, 5, 6, 7):
+    if args.workload in (4, 5, 6, 7, 8):
         rec = {4: _batched, 5: _propagation, 6: _commutator,
-               7: _clifford}[args.workload](pl, torch, args)
+               7: _clifford, 8: _lex}[args.workload](pl, torch, args)
         print(json.dumps(rec), flush=True)
         return
     A, B = _inputs(args.workload)

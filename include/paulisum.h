@@ -205,6 +205,19 @@ typedef struct {
 pauli_status_t pauli_apply_clifford(paulisum_t s, int32_t n_gates, const pauli_gate_t* gates,
                                     paulisum_t* out, void* stream);
 
+/* pauli_sort_lex: the terms of s in lexicographic order of their packed
+ * words (Section III-H: the canonical sum is sorted on a key formed from the
+ * bit-packed words of each string).  Terms are compared on the tuple
+ * (X[W-1], ..., X[0], Z[W-1], ..., Z[0]) of their words, each compared as an
+ * unsigned 64-bit integer (for n <= 32 the order of the integer x 2^32 + z).
+ * pauli_merge orders its output by fingerprint instead; this call gives a
+ * merged sum the string order.  Terms with equal strings keep
+ * their input order; phases, coefficients and fingerprints travel with their
+ * strings.  s is not changed; *out is a new sum of |s| terms that the caller
+ * destroys.  Errors: INVALID for NULL arguments, CAPACITY beyond 2^32 terms,
+ * OOM. */
+pauli_status_t pauli_sort_lex(paulisum_t s, paulisum_t* out, void* stream);
+
 /* pauli_outer_product_batched: nb independent fused products
  * out[t] = merge(a[t] * b[t]) with one set of merge options; the pairs may
  * differ in qubit count and term counts but a[t], b[t] must agree with each
@@ -276,7 +289,8 @@ typedef enum {
   PAULI_STAGE_WRITE = 4,         /* output of the merged terms (fused: the expand kernel) */
   PAULI_STAGE_LONG = 5,          /* fused: long segments, drop compaction */
   PAULI_STAGE_CLIFFORD = 6,      /* Clifford gate application */
-  PAULI_STAGE_COUNT = 7
+  PAULI_STAGE_LEX = 7,           /* lexicographic order (pauli_sort_lex) */
+  PAULI_STAGE_COUNT = 8
 } pauli_stage_t;
 pauli_status_t pauli_profile_enable(int32_t on);
 pauli_status_t pauli_profile_read(int32_t stage, double* total_ms, int64_t* launches,

@@ -29,9 +29,9 @@ EXPORTS = (
     "paulisum_info", "paulisum_export", "pauli_outer_product", "pauli_merge",
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
-    "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford",
+    "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford", "pauli_sort_lex",
 )
-STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford")
+STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford", "lex")
 
 
 class PauliLibraryMissing(RuntimeError):
@@ -97,6 +97,8 @@ def lib():
                                              ctypes.POINTER(_vp), _vp]
     L.pauli_apply_clifford.restype = st
     L.pauli_apply_clifford.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.POINTER(_vp), _vp]
+    L.pauli_sort_lex.restype = st
+    L.pauli_sort_lex.argtypes = [_vp, ctypes.POINTER(_vp), _vp]
     L.pauli_commutator.restype = st
     L.pauli_commutator.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
     L.pauli_outer_product_batched.restype = st
@@ -308,6 +310,15 @@ def apply_clifford(s: PauliSum, gates, stream=None) -> PauliSum:
     out = _vp()
     _check(lib().pauli_apply_clifford(s.handle, int(len(gates)), g.ctypes.data if len(gates) else None,
                                       ctypes.byref(out), _stream(stream)))
+    return PauliSum(out)
+
+
+def sort_lex(s: PauliSum, stream=None) -> PauliSum:
+    """The terms of s in lexicographic order of their packed words
+    (pauli_sort_lex): X[W-1] .. X[0] then Z[W-1] .. Z[0], each an unsigned
+    64-bit integer; equal strings keep their order."""
+    out = _vp()
+    _check(lib().pauli_sort_lex(s.handle, ctypes.byref(out), _stream(stream)))
     return PauliSum(out)
 
 

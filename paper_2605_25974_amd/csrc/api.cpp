@@ -502,6 +502,16 @@ pauli_status_t pauli_apply_clifford(paulisum_t s, int32_t n_gates, const pauli_g
   });
 }
 
+pauli_status_t pauli_sort_lex(paulisum_t s, paulisum_t* out, void* stream) {
+  return guarded([&] {
+    if (!s || !out) fail(PAULI_ERR_INVALID, "s and out must not be NULL");
+    use_device(s);
+    hipStream_t st = as_stream(stream);
+    s->last_stream = st;
+    *out = sort_lex(s, st);
+  });
+}
+
 pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
                                            const pauli_merge_opts_t* opts,
                                            const pauli_tune_t* tune, paulisum_t* out,

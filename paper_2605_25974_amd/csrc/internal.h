@@ -124,9 +124,11 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
 size_t radix_workspace_bytes(int64_t n);
 // Stable LSD radix sort of (key, val) by key bits [0, key_bits).  The sorted
 // result ends up in (keys, vals) or (keys_alt, vals_alt): returns true if in
-// the alternate pair.
+// the alternate pair.  An 8-bit digit with no bit set in vary is taken to be
+// the same for every key and is not sorted on.
 bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                      int64_t n, int key_bits, void* work, hipStream_t s);
+                      int64_t n, int key_bits, void* work, hipStream_t s,
+                      uint64_t vary = ~0ull);
 
 // k_merge.hip
 struct MergeArgs {
@@ -160,6 +162,10 @@ paulisum* commutator_products(const paulisum* a, const paulisum* b, hipStream_t 
 // (validated by the caller).
 paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n_gates,
                          hipStream_t st);
+
+// k_lex.hip: the terms of s in lexicographic order of their packed words
+// (X[W-1], ..., X[0], Z[W-1], ..., Z[0]); equal strings keep their order.
+paulisum* sort_lex(const paulisum* s, hipStream_t st);
 
 // k_rotate.hip: one rotation step (product or conjugation semantics),
 // followed by the merge o.  px, pz: host words of the rotation string.

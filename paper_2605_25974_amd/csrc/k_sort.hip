@@ -236,7 +236,7 @@ size_t radix_workspace_bytes(int64_t n) {
 }
 
 bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                      int64_t n, int key_bits, void* work, hipStream_t s) {
+                      int64_t n, int key_bits, void* work, hipStream_t s, uint64_t vary) {
   if (n <= 1 || key_bits <= 0) return false;
   int64_t ntiles = (n + kRsTile - 1) / kRsTile;
   uint32_t* counts = static_cast<uint32_t*>(work);
@@ -244,6 +244,7 @@ bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32
   void* scan_work = static_cast<char*>(work) + cbytes;
   bool alt = false;
   for (int shift = 0; shift < key_bits; shift += 8) {
+    if (((vary >> shift) & 0xFFull) == 0) continue;  // the same digit in every key
     const uint64_t* kin = alt ? keys_alt : keys;
     const uint32_t* vin = alt ? vals_alt : vals;
     uint64_t* kout = alt ? keys : keys_alt;
