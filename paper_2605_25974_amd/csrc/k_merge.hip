@@ -433,55 +433,132 @@ paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   }
 }
 
+// Stream compaction of the kept terms in two passes over tiles of kTileC
+// terms: the first counts each tile's kept terms, an exclusive scan of the
+// counts gives each tile its first output position, and the second pass
+// finds the same flags again and copies the kept terms.  Wave w of a block
+// owns the tile positions [w*64*kRoundsC, (w+1)*64*kRoundsC) in rounds of 64
+// and ranks its kept terms by ballots.  Only the phase bytes (and, for a
+// drop, the coefficients) are read twice.
+constexpr int kCompact = 256;
+constexpr int kRoundsC = 16;
+constexpr int kTileC = kCompact * kRoundsC;
+
 template <typename T>
-__global__ void k_keep_flags(const cplx<T>* __restrict__ c, const uint8_t* __restrict__ ph,
-                             int64_t m, double drop2, int marked, uint32_t* __restrict__ keep) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-       t += (int64_t)gridDim.x * blockDim.x)
-    keep[t] = !(marked && ph[t] != 0) && (drop2 < 0.0 || keep_value(c[t], drop2)) ? 1u : 0u;
+__device__ __forceinline__ bool keep_term(const cplx<T>* __restrict__ c,
+                                          const uint8_t* __restrict__ ph, int64_t t, double drop2,
+                                          int marked) {
+  return !(marked && ph[t] != 0) && (drop2 < 0.0 || keep_value(c[t], drop2));
+}
+
+// Kept terms of the wave's part of tile blockIdx.x.
+template <typename T>
+__device__ __forceinline__ uint32_t wave_kept(const cplx<T>* __restrict__ c,
+                                              const uint8_t* __restrict__ ph, int64_t m,
+                                              double drop2, int marked, int64_t w0, int lane) {
+  uint32_t n = 0;
+#pragma unroll 4
+  for (int r = 0; r < kRoundsC; ++r) {
+    const int64_t t = w0 + r * 64 + lane;
+    n += static_cast<uint32_t>(__popcll(__ballot(t < m && keep_term(c, ph, t, drop2, marked))));
+  }
+  return n;
 }
 
 template <typename T>
-__global__ void k_gather_kept(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
-                              const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
-                              const uint64_t* __restrict__ fp, int W, int64_t m, int64_t ld,
-                              const uint32_t* __restrict__ keep, const uint32_t* __restrict__ idx,
-                              uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
-                              uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc,
-                              uint64_t* __restrict__ Ofp, int64_t ldo) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    if (!keep[t]) continue;
-    const int64_t o = idx[t];
-    for (int w = 0; w < W; ++w) {
-      OX[w * ldo + o] = X[w * ld + t];
-      OZ[w * ldo + o] = Z[w * ld + t];
-    }
-    Oph[o] = ph[t];
-    Oc[o] = c[t];
-    Ofp[o] = fp[t];
+__global__ void __launch_bounds__(kCompact)
+k_keep_count(const cplx<T>* __restrict__ c, const uint8_t* __restrict__ ph, int64_t m,
+             double drop2, int marked, uint32_t* __restrict__ bcount) {
+  __shared__ uint32_t sw[kCompact / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t w0 = blockIdx.x * static_cast<int64_t>(kTileC) + wave * (64 * kRoundsC);
+  const uint32_t n = wave_kept(c, ph, m, drop2, marked, w0, lane);
+  if (lane == 0) sw[wave] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kCompact / 64; ++w) tot += sw[w];
+    bcount[blockIdx.x] = tot;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCompact)
+k_compact(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
+          const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
+          const uint64_t* __restrict__ fp, int W, int64_t m, int64_t ld, double drop2, int marked,
+          const uint32_t* __restrict__ boff, uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
+          uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp,
+          int64_t ldo) {
+  __shared__ uint32_t sw[kCompact / 64];
+  __shared__ uint16_t s_pos[kTileC];  // tile positions of the kept terms, in order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kTileC);
+  const int64_t w0 = base + wave * (64 * kRoundsC);
+  const uint32_t n = wave_kept(c, ph, m, drop2, marked, w0, lane);
+  if (lane == 0) sw[wave] = n;
+  __syncthreads();
+  uint32_t o = 0, total = 0;
+  for (int w = 0; w < kCompact / 64; ++w) {
+    if (w < wave) o += sw[w];
+    total += sw[w];
+  }
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < kRoundsC; ++r) {
+    const int64_t t = w0 + r * 64 + lane;
+    const bool k = t < m && keep_term(c, ph, t, drop2, marked);
+    const uint64_t bal = __ballot(k);
+    if (k) s_pos[o + __popcll(bal & lt)] = static_cast<uint16_t>(t - base);
+    o += static_cast<uint32_t>(__popcll(bal));
+  }
+  __syncthreads();
+  // every thread copies kept terms j, j + kCompact, ...: consecutive output
+  // positions, and the loads of different terms in flight together
+  const int64_t d0 = boff[blockIdx.x];
+  for (uint32_t j = threadIdx.x; j < total; j += kCompact) {
+    const int64_t t = base + s_pos[j], d = d0 + j;
+    uint64_t xv[kMaxWords], zv[kMaxWords];
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w)
+      if (w < W) {
+        xv[w] = X[w * ld + t];
+        zv[w] = Z[w * ld + t];
+      }
+    const uint8_t p = ph[t];
+    const cplx<T> v = c[t];
+    const uint64_t f = fp[t];
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w)
+      if (w < W) {
+        OX[w * ldo + d] = xv[w];
+        OZ[w * ldo + d] = zv[w];
+      }
+    Oph[d] = p;
+    Oc[d] = v;
+    Ofp[d] = f;
   }
 }
 
 template <typename T>
 paulisum* drop_t(const paulisum* a, double drop_abs, bool marked, hipStream_t s) {
   const int64_t m = a->m;
-  DBuf keep((m + 1) * 4, s), idx((m + 1) * 4, s), tot(4, s);
-  DBuf work(scan_workspace_bytes(m), s);
-  const unsigned g = grid_for(m);
-  hipLaunchKernelGGL(k_keep_flags<T>, dim3(g), dim3(kBlock), 0, s,
-                     static_cast<const cplx<T>*>(a->coef), a->ph, m,
-                     drop_abs >= 0.0 ? drop_abs * drop_abs : -1.0, marked ? 1 : 0,
-                     keep.as<uint32_t>());
-  scan_exclusive_u32(keep.as<uint32_t>(), idx.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, s);
+  const int64_t nb = (m + kTileC - 1) / kTileC;
+  const double drop2 = drop_abs >= 0.0 ? drop_abs * drop_abs : -1.0;
+  DBuf cnt((nb + 1) * 4, s), off((nb + 1) * 4, s), tot(4, s);
+  DBuf work(scan_workspace_bytes(nb), s);
+  const auto c = static_cast<const cplx<T>*>(a->coef);
+  hipLaunchKernelGGL(k_keep_count<T>, dim3(static_cast<unsigned>(nb)), dim3(kCompact), 0, s, c,
+                     a->ph, m, drop2, marked ? 1 : 0, cnt.as<uint32_t>());
+  scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), nb, tot.as<uint32_t>(), work.p, s);
   uint32_t kept = 0;
   PAULI_HIP(hipMemcpyAsync(&kept, tot.p, 4, hipMemcpyDeviceToHost, s));
   PAULI_HIP(hipStreamSynchronize(s));
   paulisum* out = new_sum(a->n, kept, kept, a->dtype, s);
   if (kept > 0)
-    hipLaunchKernelGGL(k_gather_kept<T>, dim3(g), dim3(kBlock), 0, s, a->X, a->Z, a->ph,
-                       static_cast<const cplx<T>*>(a->coef), a->fp, a->W, m, a->ld,
-                       keep.as<uint32_t>(), idx.as<uint32_t>(), out->X, out->Z, out->ph,
+    hipLaunchKernelGGL(k_compact<T>, dim3(static_cast<unsigned>(nb)), dim3(kCompact), 0, s, a->X,
+                       a->Z, a->ph, c, a->fp, a->W, m, a->ld, drop2, marked ? 1 : 0,
+                       off.as<uint32_t>(), out->X, out->Z, out->ph,
                        static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
   PAULI_HIP(hipGetLastError());
   return out;
