@@ -77,13 +77,26 @@ k_lex_permute(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m;
        r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx[r];
-    for (int w = 0; w < W; ++w) {
-      OX[w * ldo + r] = X[w * ld + i];
-      OZ[w * ldo + r] = Z[w * ld + i];
-    }
-    Oph[r] = ph[i];
-    Oc[r] = c[i];
-    Ofp[r] = fp[i];
+    // every load of the term is issued before the first store
+    uint64_t xv[kMaxWords], zv[kMaxWords];
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w)
+      if (w < W) {
+        xv[w] = X[w * ld + i];
+        zv[w] = Z[w * ld + i];
+      }
+    const uint8_t p = ph[i];
+    const cplx<T> v = c[i];
+    const uint64_t f = fp[i];
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w)
+      if (w < W) {
+        OX[w * ldo + r] = xv[w];
+        OZ[w * ldo + r] = zv[w];
+      }
+    Oph[r] = p;
+    Oc[r] = v;
+    Ofp[r] = f;
   }
 }
 
