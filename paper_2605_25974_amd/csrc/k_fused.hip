@@ -803,57 +803,74 @@ __device__ void bucket_segments(uint32_t b, uint32_t lo, uint32_t n, SortSmem& S
   if (threadIdx.x == 0) out.nseg[b] = total;
 }
 
-// Buckets that fit in LDS.  One block per compute unit takes the buckets
-// blockIdx.x, blockIdx.x + gridDim.x, ...  COUNT (the counting sort): once
-// a bucket is scattered into bins, the block loads the records of its next
-// bucket, so that the loads overlap the rest of the work.  A bucket over
-// kCap records, or one the counting sort gives up on, is queued for
-// k_heavy_sort.
-template <bool COUNT>
+// Buckets that fit in LDS, counting sort.  One block per compute unit
+// takes the buckets blockIdx.x, blockIdx.x + gridDim.x, ...; once a bucket
+// is scattered into bins, the block loads the records of its next bucket,
+// so that the loads overlap the rest of the work.  A bucket over kCap
+// records is queued for k_heavy_sort, one with a bin of more than kMaxBin
+// records (many equal keys) for k_bucket_radix.
 __global__ void __launch_bounds__(kSortNT)
-k_bucket_sort(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
-              uint32_t nbk, SortField f, SegOut out, uint32_t* __restrict__ heavy,
-              uint32_t* __restrict__ nheavy) {
+k_bucket_count(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
+               uint32_t nbk, SortField f, SegOut out, uint32_t* __restrict__ heavy,
+               uint32_t* __restrict__ nheavy, uint32_t* __restrict__ redo,
+               uint32_t* __restrict__ nredo) {
   __shared__ SortSmem S;
   uint64_t k[kSortRounds];
   uint32_t v[kSortRounds];
   uint32_t b = blockIdx.x, lo = 0, n = 0;
-  if (COUNT && b < nbk) {
+  if (b < nbk) {
     lo = boff[b];
     n = boff[b + 1] - lo;
     load_bucket(keys, out.vals, lo, n, k, v);
   }
   for (; b < nbk; b += gridDim.x) {
-    if (!COUNT) {
-      lo = boff[b];
-      n = boff[b + 1] - lo;
-      load_bucket(keys, out.vals, lo, n, k, v);
+    const bool fits = n <= static_cast<uint32_t>(kCap);
+    const bool ok = fits && count_scatter(n, f.lo14, k, v, S);
+    // every load of this bucket has been used: the wait is free, and it
+    // keeps the compiler from waiting for the next bucket's loads when it
+    // reuses their registers
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    const uint32_t b2 = b + gridDim.x;
+    uint32_t lo2 = 0, n2 = 0;
+    if (b2 < nbk) {
+      lo2 = boff[b2];
+      n2 = boff[b2 + 1] - lo2;
     }
-    bool ok = n <= static_cast<uint32_t>(kCap);
-    if (COUNT) {
-      if (ok) ok = count_scatter(n, f.lo14, k, v, S);
-      // every load of this bucket has been used: the wait is free, and it
-      // keeps the compiler from waiting for the next bucket's loads when it
-      // reuses their registers
-      __builtin_amdgcn_s_waitcnt(kWaitVm0);
-      const uint32_t b2 = b + gridDim.x;
-      uint32_t lo2 = 0, n2 = 0;
-      if (b2 < nbk) {
-        lo2 = boff[b2];
-        n2 = boff[b2 + 1] - lo2;
-      }
-      load_bucket(keys, out.vals, lo2, n2, k, v);
-      if (ok) {
-        count_order(n, f.lo14, S);
-        bucket_segments<true>(b, lo, n, S, out);
-      }
-      lo = lo2;
-      n = n2;
-    } else if (ok) {
-      radix_bucket(n, k, v, f, S);
-      bucket_segments<false>(b, lo, n, S, out);
+    load_bucket(keys, out.vals, lo2, n2, k, v);
+    if (ok) {
+      count_order(n, f.lo14, S);
+      bucket_segments<true>(b, lo, n, S, out);
+    } else if (threadIdx.x == 0) {
+      if (fits) redo[atomicAdd(nredo, 1u)] = b;
+      else heavy[atomicAdd(nheavy, 1u)] = b;
     }
-    if (!ok && threadIdx.x == 0) heavy[atomicAdd(nheavy, 1u)] = b;
+    lo = lo2;
+    n = n2;
+  }
+}
+
+// Buckets that fit in LDS, radix sort: the buckets list[0, *nlist), or every
+// bucket when list is null.  A bucket over kCap records is queued for
+// k_heavy_sort.
+__global__ void __launch_bounds__(kSortNT)
+k_bucket_radix(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
+               uint32_t nbk, const uint32_t* __restrict__ list,
+               const uint32_t* __restrict__ nlist, SortField f, SegOut out,
+               uint32_t* __restrict__ heavy, uint32_t* __restrict__ nheavy) {
+  __shared__ SortSmem S;
+  uint64_t k[kSortRounds];
+  uint32_t v[kSortRounds];
+  const uint32_t L = list ? *nlist : nbk;
+  for (uint32_t x = blockIdx.x; x < L; x += gridDim.x) {
+    const uint32_t b = list ? list[x] : x;
+    const uint32_t lo = boff[b], n = boff[b + 1] - lo;
+    if (n > static_cast<uint32_t>(kCap)) {
+      if (threadIdx.x == 0) heavy[atomicAdd(nheavy, 1u)] = b;
+      continue;
+    }
+    load_bucket(keys, out.vals, lo, n, k, v);
+    radix_bucket(n, k, v, f, S);
+    bucket_segments<false>(b, lo, n, S, out);
   }
 }
 
@@ -1072,7 +1089,8 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   DBuf keys(P * 8ull, s), vals(P * 4ull, s), keys2(P * 8ull, s), vals2(P * 4ull, s);
   DBuf Tt(static_cast<size_t>(nc) * nc * 4, s), S(nc * 4ull, s), soff(nc * 4ull + 4, s);
   DBuf boff((nbk + 1) * 4ull, s), ctr(64, s);
-  uint32_t* ctr32 = ctr.as<uint32_t>();  // [0] heavy count [1] long count [2] err [3] total
+  // [0] heavy count [1] long count [2] err [3] total [4] expand work items [6] radix redo count
+  uint32_t* ctr32 = ctr.as<uint32_t>();
   uint64_t* K = keys.as<uint64_t>();
   uint32_t* V = vals.as<uint32_t>();
   uint64_t* K2 = keys2.as<uint64_t>();
@@ -1128,18 +1146,25 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   }
 
   DBuf segidx(P * 4ull, s), nseg(nbk * 4ull + 4, s), segoff(nbk * 4ull + 4, s);
-  DBuf heavy(nbk * 4ull, s), long_list(static_cast<size_t>(P / kLong + 2) * 8, s);
+  DBuf heavy(nbk * 4ull, s), redo(nbk * 4ull, s);
+  DBuf long_list(static_cast<size_t>(P / kLong + 2) * 8, s);
   SegOut so{V, segidx.as<uint32_t>(), nseg.as<uint32_t>(), long_list.as<uint32_t>(), ctr32 + 1};
   {
     StageScope sc(PAULI_STAGE_SEGMENT, s, Peff * 20.0);
     // one block per compute unit (the LDS of a block fills most of one)
     const uint32_t gsort = nbk < static_cast<uint32_t>(device_cus()) ? nbk : device_cus();
-    if (sf.lo14 >= 0)
-      hipLaunchKernelGGL(k_bucket_sort<true>, dim3(gsort), dim3(kSortNT), 0, s, K,
-                         boff.as<uint32_t>(), nbk, sf, so, heavy.as<uint32_t>(), ctr32);
-    else
-      hipLaunchKernelGGL(k_bucket_sort<false>, dim3(gsort), dim3(kSortNT), 0, s, K,
-                         boff.as<uint32_t>(), nbk, sf, so, heavy.as<uint32_t>(), ctr32);
+    if (sf.lo14 >= 0) {
+      // the buckets the counting sort gives up on take the radix sort
+      hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
+                         nbk, sf, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(), ctr32 + 6);
+      // (usually none: a few blocks)
+      hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, K,
+                         boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, so,
+                         heavy.as<uint32_t>(), ctr32);
+    } else {
+      hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
+                         nbk, nullptr, nullptr, sf, so, heavy.as<uint32_t>(), ctr32);
+    }
     hipLaunchKernelGGL(k_heavy_sort, dim3(64), dim3(kSortNT), 0, s, K, K2, V2, boff.as<uint32_t>(),
                        rem, heavy.as<uint32_t>(), ctr32, so);
     PAULI_HIP(hipGetLastError());
