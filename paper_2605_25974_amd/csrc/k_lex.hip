@@ -65,38 +65,64 @@ __global__ void k_lex_gather(const uint64_t* __restrict__ w, const uint32_t* __r
     keys[r] = w[idx[r]];
 }
 
-// Output term r is input term idx[r].
+// The terms as rows of RW = 2W + 4 words: X[0..W), Z[0..W), the
+// coefficient (two words, FP32 pairs packed in the first), the fingerprint
+// and the phase byte, so that the final gather in sorted order reads whole
+// lines instead of one 8-byte word per array.
 template <typename T>
 __global__ void __launch_bounds__(kLexBlock)
-k_lex_permute(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
-              const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
-              const uint64_t* __restrict__ fp, int W, int64_t ld,
-              const uint32_t* __restrict__ idx, int64_t m, uint64_t* __restrict__ OX,
-              uint64_t* __restrict__ OZ, uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc,
-              uint64_t* __restrict__ Ofp, int64_t ldo) {
+k_lex_rows(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
+           const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
+           const uint64_t* __restrict__ fp, int W, int64_t ld, int64_t m,
+           uint64_t* __restrict__ R) {
+  const int RW = 2 * W + 4;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t* row = R + t * RW;
+    for (int w = 0; w < W; ++w) {
+      row[w] = X[w * ld + t];
+      row[W + w] = Z[w * ld + t];
+    }
+    const cplx<T> v = c[t];
+    uint64_t c0 = 0, c1 = 0;
+    static_assert(sizeof(cplx<T>) <= 16, "coefficient fits two words");
+    __builtin_memcpy(&c0, &v, sizeof(cplx<T>) < 8 ? sizeof(cplx<T>) : 8);
+    if (sizeof(cplx<T>) > 8) __builtin_memcpy(&c1, reinterpret_cast<const char*>(&v) + 8, 8);
+    row[2 * W] = c0;
+    row[2 * W + 1] = c1;
+    row[2 * W + 2] = fp[t];
+    row[2 * W + 3] = ph[t];
+  }
+}
+
+// Output term r is row idx[r].
+template <typename T>
+__global__ void __launch_bounds__(kLexBlock)
+k_lex_permute(const uint64_t* __restrict__ R, int W, const uint32_t* __restrict__ idx,
+              int64_t m, uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
+              uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp,
+              int64_t ldo) {
+  const int RW = 2 * W + 4;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m;
        r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx[r];
-    // every load of the term is issued before the first store
-    uint64_t xv[kMaxWords], zv[kMaxWords];
-#pragma unroll
-    for (int w = 0; w < kMaxWords; ++w)
-      if (w < W) {
-        xv[w] = X[w * ld + i];
-        zv[w] = Z[w * ld + i];
-      }
-    const uint8_t p = ph[i];
-    const cplx<T> v = c[i];
-    const uint64_t f = fp[i];
-#pragma unroll
-    for (int w = 0; w < kMaxWords; ++w)
-      if (w < W) {
-        OX[w * ldo + r] = xv[w];
-        OZ[w * ldo + r] = zv[w];
-      }
-    Oph[r] = p;
-    Oc[r] = v;
-    Ofp[r] = f;
+    const uint64_t* row = R + static_cast<int64_t>(idx[r]) * RW;
+    // the string words in 16-byte pieces (rows start on 16-byte boundaries)
+    const ulonglong2* row2 = reinterpret_cast<const ulonglong2*>(row);
+    for (int p = 0; p < W; ++p) {
+      const ulonglong2 v = row2[p];
+      const int w0 = 2 * p, w1 = 2 * p + 1;
+      if (w0 < W) OX[w0 * ldo + r] = v.x;
+      else OZ[(w0 - W) * ldo + r] = v.x;
+      if (w1 < W) OX[w1 * ldo + r] = v.y;
+      else OZ[(w1 - W) * ldo + r] = v.y;
+    }
+    const uint64_t c0 = row[2 * W], c1 = row[2 * W + 1];
+    cplx<T> cv;
+    __builtin_memcpy(&cv, &c0, sizeof(cplx<T>) < 8 ? sizeof(cplx<T>) : 8);
+    if (sizeof(cplx<T>) > 8) __builtin_memcpy(reinterpret_cast<char*>(&cv) + 8, &c1, 8);
+    Oc[r] = cv;
+    Ofp[r] = row[2 * W + 2];
+    Oph[r] = static_cast<uint8_t>(row[2 * W + 3]);
   }
 }
 
@@ -109,9 +135,14 @@ unsigned lex_grid(int64_t m) {
 
 template <typename T>
 void lex_permute_t(const paulisum* s, const uint32_t* idx, paulisum* o, hipStream_t st) {
-  hipLaunchKernelGGL((k_lex_permute<T>), dim3(lex_grid(s->m)), dim3(kLexBlock), 0, st, s->X,
-                     s->Z, s->ph, static_cast<const cplx<T>*>(s->coef), s->fp, s->W, s->ld, idx,
-                     s->m, o->X, o->Z, o->ph, static_cast<cplx<T>*>(o->coef), o->fp, o->ld);
+  const int RW = 2 * s->W + 4;
+  DBuf rows(static_cast<size_t>(s->m) * RW * 8, st);
+  hipLaunchKernelGGL((k_lex_rows<T>), dim3(lex_grid(s->m)), dim3(kLexBlock), 0, st, s->X, s->Z,
+                     s->ph, static_cast<const cplx<T>*>(s->coef), s->fp, s->W, s->ld, s->m,
+                     rows.as<uint64_t>());
+  hipLaunchKernelGGL((k_lex_permute<T>), dim3(lex_grid(s->m)), dim3(kLexBlock), 0, st,
+                     rows.as<uint64_t>(), s->W, idx, s->m, o->X, o->Z, o->ph,
+                     static_cast<cplx<T>*>(o->coef), o->fp, o->ld);
   PAULI_HIP(hipGetLastError());
 }
 
