@@ -127,6 +127,7 @@ k_clifford(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
     uint64_t f = fp[t];
     uint32_t flips = 0;
     // every thread reads the same gate: uniform (scalar) loads
+#pragma unroll 4
     for (int i = 0; i < ngates; ++i) flips += apply_gate<WT>(s, gates[i], f);
 #pragma unroll
     for (int w = 0; w < WT; ++w)
