@@ -1165,8 +1165,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
       hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
                          nbk, nullptr, nullptr, sf, so, heavy.as<uint32_t>(), ctr32);
     }
-    hipLaunchKernelGGL(k_heavy_sort, dim3(64), dim3(kSortNT), 0, s, K, K2, V2, boff.as<uint32_t>(),
-                       rem, heavy.as<uint32_t>(), ctr32, so);
+    // one block per compute unit: a workload of many equal strings can make
+    // most buckets heavy
+    hipLaunchKernelGGL(k_heavy_sort, dim3(gsort), dim3(kSortNT), 0, s, K, K2, V2,
+                       boff.as<uint32_t>(), rem, heavy.as<uint32_t>(), ctr32, so);
     PAULI_HIP(hipGetLastError());
     DBuf w(scan_workspace_bytes(nbk), s);
     scan_exclusive_u32(nseg.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
