@@ -167,6 +167,24 @@ paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n
 // (X[W-1], ..., X[0], Z[W-1], ..., Z[0]); equal strings keep their order.
 paulisum* sort_lex(const paulisum* s, hipStream_t st);
 
+// A rotation string P of a propagation step, passed to kernels by value.
+struct RotString {
+  uint64_t x[kMaxWordsHost];
+  uint64_t z[kMaxWordsHost];
+  uint64_t fp;
+  int W;
+  int y;  // |X & Z| of P
+};
+
+// Sort-and-combine of the conjugated sum of s under R = cos(theta) I
+// - i sin(theta) P without storing it: record 2t is term t of s (times
+// cos(theta) where it anticommutes with P, cnt[t] == 2), record 2t + 1 the
+// new term -i sin(theta) P Q_t.  keys / vals: the N records in key order
+// (equal keys adjacent), used as scratch.
+paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
+                        const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
+                        const MergeArgs& o, hipStream_t st);
+
 // k_rotate.hip: one rotation step (product or conjugation semantics),
 // followed by the merge o.  px, pz: host words of the rotation string.
 paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,

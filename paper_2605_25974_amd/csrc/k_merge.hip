@@ -17,6 +17,7 @@
 //
 // The same pipeline serves a materialised sum (term source) and the fused
 // outer product (pair source, no product is ever stored).
+#include <cmath>
 #include <memory>
 #include <type_traits>
 
@@ -570,6 +571,61 @@ paulisum* drop_terms(const paulisum* a, double drop_abs, hipStream_t s, bool mar
   if (a->m == 0) return new_sum(a->n, 0, 0, a->dtype, s);
   if (a->dtype == PAULI_C128) return drop_t<double>(a, drop_abs, marked, s);
   return drop_t<float>(a, drop_abs, marked, s);
+}
+
+namespace {
+
+template <int WT, typename T>
+paulisum* merge_rotated_t(const paulisum* a, const RotString& P, double theta,
+                          const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
+                          const MergeArgs& o, hipStream_t s) {
+  RotSrc<WT, T> src{};
+  src.X = a->X;
+  src.Z = a->Z;
+  src.ph = a->ph;
+  src.c = static_cast<const cplx<T>*>(a->coef);
+  src.f = a->fp;
+  src.cnt = cnt;
+  src.ld = a->ld;
+  src.nw = a->W;
+  src.py = P.y;
+  src.pfp = P.fp;
+  src.co = static_cast<T>(std::cos(theta));
+  src.si = static_cast<T>(std::sin(theta));
+  for (int q = 0; q < WT; ++q) {
+    src.px[q] = q < a->W ? P.x[q] : 0ull;
+    src.pz[q] = q < a->W ? P.z[q] : 0ull;
+  }
+  return o.mode == PAULI_MERGE_COMPENSATED
+             ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s, true)
+             : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s, true);
+}
+
+template <typename T>
+paulisum* merge_rotated_w(const paulisum* a, const RotString& P, double theta,
+                          const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
+                          const MergeArgs& o, hipStream_t s) {
+  switch (a->W) {  // the source reads exactly WT words when WT <= 8
+    case 1: return merge_rotated_t<1, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 2: return merge_rotated_t<2, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 3: return merge_rotated_t<3, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 4: return merge_rotated_t<4, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 5: return merge_rotated_t<5, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 6: return merge_rotated_t<6, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 7: return merge_rotated_t<7, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 8: return merge_rotated_t<8, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    default: return merge_rotated_t<kMaxWords, T>(a, P, theta, cnt, keys, vals, N, o, s);
+  }
+}
+
+}  // namespace
+
+paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
+                        const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
+                        const MergeArgs& o, hipStream_t st) {
+  if (N == 0) return new_sum(s->n, 0, 0, o.mode == PAULI_MERGE_COMPENSATED ? PAULI_C64 : s->dtype, st);
+  if (s->dtype == PAULI_C128) return merge_rotated_w<double>(s, P, theta, cnt, keys, vals, N, o, st);
+  return merge_rotated_w<float>(s, P, theta, cnt, keys, vals, N, o, st);
 }
 
 paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals,

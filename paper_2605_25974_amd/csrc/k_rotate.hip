@@ -27,15 +27,6 @@ inline unsigned grid_for(int64_t n) {
   return static_cast<unsigned>(g);
 }
 
-// The rotation string, passed by value.
-struct RotString {
-  uint64_t x[kMaxWords];
-  uint64_t z[kMaxWords];
-  uint64_t fp;
-  int W;
-  int y;  // |X & Z| of P
-};
-
 // cnt[t] = 1 + (term t anticommutes with P): the parity of the symplectic
 // product (Section III-F), sum over words of |X_t & Z_P| + |Z_t & X_P|.
 __global__ void k_rot_count(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
@@ -88,19 +79,21 @@ __global__ void k_rot_write(const uint64_t* __restrict__ X, const uint64_t* __re
 // Records of the conjugated sum when the input sum is in key order: the
 // kept strings (every input term, in input order, so already sorted) and
 // the new strings P Q of the anticommuting terms (compacted, to be sorted).
-__global__ void k_rot_records(const uint64_t* __restrict__ mfp, const uint32_t* __restrict__ cnt,
-                              const uint32_t* __restrict__ off, int64_t m, int kshift,
-                              uint64_t* __restrict__ kk, uint32_t* __restrict__ kv,
+// Record ids address the conjugated sum without storing it: 2t is input
+// term t, 2t + 1 its new term.
+__global__ void k_rot_records(const uint64_t* __restrict__ fp, const uint32_t* __restrict__ cnt,
+                              const uint32_t* __restrict__ off, int64_t m, uint64_t pfp,
+                              int kshift, uint64_t* __restrict__ kk, uint32_t* __restrict__ kv,
                               uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t o = off[t];
-    kk[t] = mfp[o] >> kshift;
-    kv[t] = o;
+    const uint64_t f = fp[t];
+    kk[t] = f >> kshift;
+    kv[t] = static_cast<uint32_t>(2 * t);
     if (cnt[t] == 2) {
-      const uint32_t j = o - static_cast<uint32_t>(t);  // anticommuting terms before t
-      nk[j] = mfp[o + 1] >> kshift;
-      nv[j] = o + 1;
+      const uint32_t j = off[t] - static_cast<uint32_t>(t);  // anticommuting terms before t
+      nk[j] = (f ^ pfp) >> kshift;
+      nv[j] = static_cast<uint32_t>(2 * t + 1);
     }
   }
 }
@@ -206,60 +199,64 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
   const int64_t m = s->m;
   DBuf cnt((m + 1) * 4, st), off((m + 1) * 4, st), tot(4, st), work(scan_workspace_bytes(m), st);
   const unsigned g = grid_for(m);
-  paulisum* mat = nullptr;
+  uint32_t M2 = 0;
   {
     StageScope sc(PAULI_STAGE_PREP, st, m * (16.0 * s->W + 8));
     hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, m, P,
                        cnt.as<uint32_t>());
     scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, st);
-    uint32_t M2 = 0;
     PAULI_HIP(hipMemcpyAsync(&M2, tot.p, 4, hipMemcpyDeviceToHost, st));
     PAULI_HIP(hipStreamSynchronize(st));
-    mat = new_sum(s->n, M2, M2, s->dtype, st);
-    hipLaunchKernelGGL(k_rot_write<T>, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ph,
-                       static_cast<const cplx<T>*>(s->coef), s->fp, s->ld, m, P,
-                       static_cast<T>(std::cos(theta)), static_cast<T>(std::sin(theta)),
-                       cnt.as<uint32_t>(), off.as<uint32_t>(), mat->X, mat->Z, mat->ph,
-                       static_cast<cplx<T>*>(mat->coef), mat->fp, mat->ld);
-    PAULI_HIP(hipGetLastError());
   }
+  if (sorted_input && M2 <= 0x7FFFFFFFu && m <= 0x7FFFFFFFll) {
+    // the kept strings are in key order already: sort only the new ones,
+    // merge the two lists, and combine straight from the input terms (the
+    // conjugated sum is never stored)
+    const int64_t na = m, nb = static_cast<int64_t>(M2) - m;
+    const int kshift = 64 - o.key_bits;
+    DBuf keys(M2 * 8ull, st), vals(M2 * 4ull, st), kk(m * 8, st), kv(m * 4, st);
+    DBuf nk(nb * 8 + 8, st), nv(nb * 4 + 4, st), nk2(nb * 8 + 8, st), nv2(nb * 4 + 4, st);
+    {
+      StageScope sc(PAULI_STAGE_SORT, st, m * 24.0 + nb * 12.0 * 2 + M2 * 36.0);
+      hipLaunchKernelGGL(k_rot_records, dim3(g), dim3(kBlock), 0, st, s->fp, cnt.as<uint32_t>(),
+                         off.as<uint32_t>(), m, P.fp, kshift, kk.as<uint64_t>(),
+                         kv.as<uint32_t>(), nk.as<uint64_t>(), nv.as<uint32_t>());
+      PAULI_HIP(hipGetLastError());
+      uint64_t* bk = nk.as<uint64_t>();
+      uint32_t* bv = nv.as<uint32_t>();
+      if (nb > 1) {
+        DBuf rwork(radix_workspace_bytes(nb), st);
+        if (radix_sort_pairs(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), nb, o.key_bits,
+                             rwork.p, st)) {
+          bk = nk2.as<uint64_t>();
+          bv = nv2.as<uint32_t>();
+        }
+      }
+      int64_t blocks = (static_cast<int64_t>(M2) + kMergeOut - 1) / kMergeOut;
+      if (blocks > 65536) blocks = 65536;
+      if (blocks < 1) blocks = 1;
+      hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
+                         kk.as<uint64_t>(), kv.as<uint32_t>(), na, bk, bv, nb,
+                         keys.as<uint64_t>(), vals.as<uint32_t>());
+      PAULI_HIP(hipGetLastError());
+    }
+    return merge_rotated(s, P, theta, cnt.as<uint32_t>(), keys.as<uint64_t>(),
+                         vals.as<uint32_t>(), M2, o, st);
+  }
+  // input in any order: store the conjugated sum and merge it
+  paulisum* mat = new_sum(s->n, M2, M2, s->dtype, st);
   paulisum* r = nullptr;
   try {
-    if (!sorted_input) {
-      r = merge_generic(mat, nullptr, o, st);
-    } else {
-      // the kept strings are in key order already: sort only the new ones
-      // and merge the two lists instead of sorting every record
-      const int64_t M2 = mat->m, na = m, nb = M2 - m;
-      const int kshift = 64 - o.key_bits;
-      DBuf keys(M2 * 8, st), vals(M2 * 4, st), kk(m * 8, st), kv(m * 4, st);
-      DBuf nk(nb * 8 + 8, st), nv(nb * 4 + 4, st), nk2(nb * 8 + 8, st), nv2(nb * 4 + 4, st);
-      {
-        StageScope sc(PAULI_STAGE_SORT, st, m * 24.0 + nb * 12.0 * 2 + M2 * 36.0);
-        hipLaunchKernelGGL(k_rot_records, dim3(g), dim3(kBlock), 0, st, mat->fp,
-                           cnt.as<uint32_t>(), off.as<uint32_t>(), m, kshift, kk.as<uint64_t>(),
-                           kv.as<uint32_t>(), nk.as<uint64_t>(), nv.as<uint32_t>());
-        PAULI_HIP(hipGetLastError());
-        uint64_t* bk = nk.as<uint64_t>();
-        uint32_t* bv = nv.as<uint32_t>();
-        if (nb > 1) {
-          DBuf rwork(radix_workspace_bytes(nb), st);
-          if (radix_sort_pairs(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), nb, o.key_bits,
-                               rwork.p, st)) {
-            bk = nk2.as<uint64_t>();
-            bv = nv2.as<uint32_t>();
-          }
-        }
-        int64_t blocks = (M2 + kMergeOut - 1) / kMergeOut;
-        if (blocks > 65536) blocks = 65536;
-        if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
-                           kk.as<uint64_t>(), kv.as<uint32_t>(), na, bk, bv, nb,
-                           keys.as<uint64_t>(), vals.as<uint32_t>());
-        PAULI_HIP(hipGetLastError());
-      }
-      r = merge_sorted_records(mat, keys.as<uint64_t>(), vals.as<uint32_t>(), o, st);
+    {
+      StageScope sc(PAULI_STAGE_PREP, st, m * (16.0 * s->W + 25) + M2 * (16.0 * s->W + 25));
+      hipLaunchKernelGGL(k_rot_write<T>, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ph,
+                         static_cast<const cplx<T>*>(s->coef), s->fp, s->ld, m, P,
+                         static_cast<T>(std::cos(theta)), static_cast<T>(std::sin(theta)),
+                         cnt.as<uint32_t>(), off.as<uint32_t>(), mat->X, mat->Z, mat->ph,
+                         static_cast<cplx<T>*>(mat->coef), mat->fp, mat->ld);
+      PAULI_HIP(hipGetLastError());
     }
+    r = merge_generic(mat, nullptr, o, st);
   } catch (...) {
     free_sum(mat);
     throw;

@@ -99,6 +99,65 @@ struct TermSrc {
   __device__ __forceinline__ uint64_t fp(uint32_t id) const { return f[id]; }
 };
 
+// The conjugated sum of a rotation step (Section III-B, eq. (5)), not
+// stored: record 2t is input term t, its coefficient times cos(theta) when
+// Q_t anticommutes with P (cnt[t] == 2); record 2t + 1 is the new term
+// -i sin(theta) P Q_t of an anticommuting Q_t, with the phase of the product
+// P Q_t (Section III-A) and the fingerprint fp(P) ^ fp(Q_t).  The values are
+// formed in T and then converted, as a stored copy of them would be.
+template <int WT, typename T>
+struct RotSrc {
+  const uint64_t* X;
+  const uint64_t* Z;
+  const uint8_t* ph;
+  const cplx<T>* c;
+  const uint64_t* f;
+  const uint32_t* cnt;
+  int64_t ld;
+  int nw;
+  int py;
+  uint64_t pfp;
+  T co, si;
+  uint64_t px[WT], pz[WT];
+
+  __device__ __forceinline__ void string(uint32_t id, uint64_t* w) const {
+    const uint32_t t = id >> 1;
+    const uint64_t nm = (id & 1u) ? ~0ull : 0ull;
+#pragma unroll
+    for (int q = 0; q < WT; ++q) {
+      if (WT > 8 && q >= nw) break;
+      w[q] = X[q * ld + t] ^ (px[q] & nm);
+      w[nw + q] = Z[q * ld + t] ^ (pz[q] & nm);
+    }
+  }
+  template <typename TV = T>
+  __device__ __forceinline__ cplx<TV> term(uint32_t id, uint64_t* w) const {
+    const uint32_t t = id >> 1;
+    const cplx<T> v = c[t];
+    if ((id & 1u) == 0) {
+      string(id, w);
+      const cplx<T> u = cnt[t] == 2 ? cplx<T>{v.re * co, v.im * co} : v;
+      return rot_ik(ph[t], cplx<TV>{static_cast<TV>(u.re), static_cast<TV>(u.im)});
+    }
+    int k = py;
+#pragma unroll
+    for (int q = 0; q < WT; ++q) {
+      if (WT > 8 && q >= nw) break;
+      const uint64_t xq = X[q * ld + t], zq = Z[q * ld + t];
+      const uint64_t x3 = px[q] ^ xq, z3 = pz[q] ^ zq;
+      k += popc64(xq & zq) + 2 * popc64(pz[q] & xq) - popc64(x3 & z3);
+      w[q] = x3;
+      w[nw + q] = z3;
+    }
+    // -i sin(theta) i^k P Q: the factor -i = i^3 joins the phase exponent
+    const cplx<T> u{v.re * si, v.im * si};
+    return rot_ik((ph[t] + k + 3) & 3, cplx<TV>{static_cast<TV>(u.re), static_cast<TV>(u.im)});
+  }
+  __device__ __forceinline__ uint64_t fp(uint32_t id) const {
+    return f[id >> 1] ^ ((id & 1u) ? pfp : 0ull);
+  }
+};
+
 template <int WT>
 __device__ __forceinline__ bool words_equal(const uint64_t* a, const uint64_t* b, int nw) {
   uint64_t d = 0;
