@@ -18,12 +18,13 @@
 //              straight into their buckets (each record written once).  For
 //              a sum times itself only the tiles hA <= hB are generated and
 //              each record stands for an unordered pair.
-//  3 sort      per bucket, in LDS: stable radix sort on the 16 key bits below
-//              the bucket bits, runs tied on those bits finished by insertion
-//              sort on the full key; writes the sorted pair ids and each
-//              record's segment index (equal keys = one segment).  Buckets
-//              too large for LDS are sorted on all remaining key bits by
-//              one block in global memory.
+//  3 sort      per bucket, in LDS: counting sort on the 14 key bits below
+//              the bucket bits, then each bin in (key, pair id) order; writes
+//              the sorted pair ids and each record's segment index (equal
+//              keys = one segment).  A bucket with a bin of many equal keys
+//              takes a stable LDS radix sort on 16 bits with ties finished on
+//              the full key; a bucket too large for LDS is sorted on all
+//              remaining key bits by one block in global memory.
 //  4 scan      segment counts -> output offsets.
 //  5 expand    per record: a group of G lanes loads the record's two operand
 //              rows with one 16-byte load per lane (one cache line per row),
