@@ -290,7 +290,10 @@ typedef enum {
   PAULI_STAGE_LONG = 5,          /* fused: long segments, drop compaction */
   PAULI_STAGE_CLIFFORD = 6,      /* Clifford gate application */
   PAULI_STAGE_LEX = 7,           /* lexicographic order (pauli_sort_lex) */
-  PAULI_STAGE_COUNT = 8
+  PAULI_STAGE_FILTER = 8,        /* commutator: search for anticommuting pairs; its
+                                    algorithmic figure counts 32-bit integer
+                                    operations (8W + 2 per pair), not bytes */
+  PAULI_STAGE_COUNT = 9
 } pauli_stage_t;
 pauli_status_t pauli_profile_enable(int32_t on);
 pauli_status_t pauli_profile_read(int32_t stage, double* total_ms, int64_t* launches,

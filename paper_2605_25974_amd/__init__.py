@@ -31,7 +31,8 @@ EXPORTS = (
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
     "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford", "pauli_sort_lex",
 )
-STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford", "lex")
+STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford", "lex",
+          "filter")
 
 
 class PauliLibraryMissing(RuntimeError):

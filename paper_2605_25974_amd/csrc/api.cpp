@@ -150,6 +150,11 @@ void use_device(const paulisum* s) {
   if (cur != s->device) PAULI_HIP(hipSetDevice(s->device));
 }
 
+// Above this fraction of anticommuting pairs the commutator takes the fused
+// product path (the filtered path merges its products through the general
+// pipeline, whose cost grows with their number).
+constexpr double kCommFilterFrac = 0.125;
+
 void check_pair(paulisum_t a, paulisum_t b) {
   check_sum(a, "a");
   check_sum(b, "b");
@@ -458,6 +463,13 @@ pauli_status_t pauli_commutator(paulisum_t a, paulisum_t b, const pauli_merge_op
     a->last_stream = b->last_stream = s;
     paulisum* r = nullptr;
     if (a->m > 0 && b->m > 0) {
+      // few anticommuting pairs (physical Hamiltonians): find them first and
+      // merge only their products; many: the fused product with a kept flag
+      r = commutator_filtered(a, b, m, kCommFilterFrac, s);
+      if (r) {
+        *out = r;
+        return;
+      }
       MergeArgs mc = m;
       mc.comm = 1;
       r = fused_bucket(a, b, mc, s);

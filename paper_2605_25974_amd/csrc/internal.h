@@ -154,6 +154,13 @@ paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals
 // kernel marks the strings of a commutator that no anticommuting pair gave).
 paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st, bool marked = false);
 
+// k_merge.hip: the commutator [a, b] = sum over anticommuting pairs of
+// 2 a_i b_j, the pairs found by a tiled parity test before any sorting and
+// only they merged.  Returns nullptr (nothing allocated) when more than
+// max_frac of the pairs anticommute.  Requires |a| |b| < 2^32.
+paulisum* commutator_filtered(const paulisum* a, const paulisum* b, const MergeArgs& o,
+                              double max_frac, hipStream_t s);
+
 // k_basic.hip: the unmerged products 2 a_i b_j of the anticommuting pairs
 // of a and b (the terms of [a, b] before merging), in pair order.
 paulisum* commutator_products(const paulisum* a, const paulisum* b, hipStream_t s);

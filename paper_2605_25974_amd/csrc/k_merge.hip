@@ -620,6 +620,160 @@ paulisum* merge_rotated_w(const paulisum* a, const RotString& P, double theta,
 
 }  // namespace
 
+namespace {
+
+// Anticommuting pairs of a commutator, found before any sorting
+// (Section III-F: two strings anticommute when their symplectic product is
+// odd).  Tile (ti, tj) holds the left terms i = 64 ti + lane, whose words a
+// lane keeps in registers, and the right terms j = 64 tj + r, r < 64, whose
+// rows the block stages in LDS; wave w tests j = 64 tj + 16 w + c, c < 16.
+// Each wave writes the pair ids p = j * ma + i it finds, in (j, i) order,
+// into its own 1024 slots, and their number into wcount.
+constexpr int kCommTile = 64;
+constexpr int kCommSlots = kCommTile * kCommTile / 4;
+
+template <int WT>
+__global__ void __launch_bounds__(256)
+k_comm_tiles(const uint64_t* __restrict__ ra, const uint64_t* __restrict__ rb, int nw,
+             uint32_t ma, uint32_t mb, uint32_t nti, uint32_t* __restrict__ slots,
+             uint32_t* __restrict__ wcount) {
+  __shared__ uint64_t sb[kCommTile][2 * WT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t ti = blockIdx.x % nti, tj = blockIdx.x / nti;
+  const int rw = 2 * nw;
+  for (int k = threadIdx.x; k < kCommTile * rw; k += blockDim.x) {
+    const int r = k / rw, q = k - r * rw;
+    const uint32_t j = tj * kCommTile + r;
+    sb[r][q] = j < mb ? rb[static_cast<size_t>(j) * rw + q] : 0ull;
+  }
+  const uint32_t i = ti * kCommTile + lane;
+  const bool vi = i < ma;
+  uint64_t xa[WT], za[WT];
+#pragma unroll
+  for (int q = 0; q < WT; ++q) {
+    const bool ld = vi && (WT <= 8 || q < nw);
+    xa[q] = ld ? ra[static_cast<size_t>(i) * rw + q] : 0ull;
+    za[q] = ld ? ra[static_cast<size_t>(i) * rw + nw + q] : 0ull;
+  }
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t* out = slots + (static_cast<size_t>(blockIdx.x) * 4 + wave) * kCommSlots;
+  uint32_t n = 0;
+#pragma unroll 1
+  for (int c = 0; c < kCommTile / 4; ++c) {
+    const int r = wave * (kCommTile / 4) + c;
+    const uint32_t j = tj * kCommTile + r;
+    if (j >= mb) break;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < WT; ++q)
+      if (WT <= 8 || q < nw) acc ^= (xa[q] & sb[r][nw + q]) ^ (za[q] & sb[r][q]);
+    const bool anti = vi && (popc64(acc) & 1);
+    const uint64_t bal = __ballot(anti);
+    if (anti) out[n + __popcll(bal & lt)] = j * ma + i;
+    n += static_cast<uint32_t>(__popcll(bal));
+  }
+  if (lane == 0) wcount[blockIdx.x * 4 + wave] = n;
+}
+
+// Records (key, pair id) of the anticommuting pairs, in tile and wave order:
+// one wave per slot group copies its ids to their compacted positions.
+__global__ void __launch_bounds__(64)
+k_comm_records(const uint32_t* __restrict__ slots, const uint32_t* __restrict__ wcount,
+               const uint32_t* __restrict__ woff, const uint64_t* __restrict__ fa,
+               const uint64_t* __restrict__ fb, uint32_t ma, int kshift,
+               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const uint32_t g = blockIdx.x, n = wcount[g], o = woff[g];
+  const uint32_t* src = slots + static_cast<size_t>(g) * kCommSlots;
+  for (uint32_t k = threadIdx.x; k < n; k += 64) {
+    const uint32_t p = src[k];
+    const uint32_t j = p / ma, i = p - j * ma;
+    keys[o + k] = (fa[i] ^ fb[j]) >> kshift;
+    vals[o + k] = p;
+  }
+}
+
+template <int WT, typename T>
+paulisum* commutator_filtered_t(const paulisum* a, const paulisum* b, const MergeArgs& o,
+                                double max_frac, hipStream_t s) {
+  const int W = a->W;
+  const uint32_t ma = static_cast<uint32_t>(a->m), mb = static_cast<uint32_t>(b->m);
+  const uint32_t nti = (ma + kCommTile - 1) / kCommTile, ntj = (mb + kCommTile - 1) / kCommTile;
+  const int64_t ntiles = static_cast<int64_t>(nti) * ntj, ngroups = ntiles * 4;
+  DBuf ra(a->m * 2 * W * sizeof(uint64_t), s), ea(a->m, s);
+  DBuf rb(b->m * 2 * W * sizeof(uint64_t), s), eb(b->m, s);
+  DBuf slots(static_cast<size_t>(ngroups) * kCommSlots * 4, s);
+  DBuf wcount(ngroups * 4 + 4, s), woff(ngroups * 4 + 4, s), tot(4, s);
+  DBuf work(scan_workspace_bytes(ngroups), s);
+  uint32_t K = 0;
+  {
+    StageScope sc(PAULI_STAGE_PREP, s, (a->m + b->m) * (16.0 * W) * 2);
+    launch_prep_side(a, ra.as<uint64_t>(), ea.as<uint8_t>(), s);
+    launch_prep_side(b, rb.as<uint64_t>(), eb.as<uint8_t>(), s);
+  }
+  {
+    // per pair: an AND, an AND and two XORs on W word pairs (8W 32-bit
+    // operations) and a 64-bit popcount (2)
+    StageScope sc(PAULI_STAGE_FILTER, s, static_cast<double>(ma) * mb * (8.0 * W + 2.0));
+    hipLaunchKernelGGL((k_comm_tiles<WT>), dim3(static_cast<unsigned>(ntiles)), dim3(256), 0, s,
+                       ra.as<uint64_t>(), rb.as<uint64_t>(), W, ma, mb, nti,
+                       slots.as<uint32_t>(), wcount.as<uint32_t>());
+    PAULI_HIP(hipGetLastError());
+  }
+  {
+    StageScope sc(PAULI_STAGE_PREP, s, ngroups * 8.0);
+    scan_exclusive_u32(wcount.as<uint32_t>(), woff.as<uint32_t>(), ngroups, tot.as<uint32_t>(),
+                       work.p, s);
+    PAULI_HIP(hipMemcpyAsync(&K, tot.p, 4, hipMemcpyDeviceToHost, s));
+    PAULI_HIP(hipStreamSynchronize(s));
+  }
+  if (static_cast<double>(K) > max_frac * static_cast<double>(a->m) * static_cast<double>(b->m))
+    return nullptr;
+  if (K == 0)
+    return new_sum(a->n, 0, 0, o.mode == PAULI_MERGE_COMPENSATED ? PAULI_C64 : a->dtype, s);
+  DBuf keys(K * 8ull, s), vals(K * 4ull, s);
+  {
+    StageScope sc(PAULI_STAGE_PREP, s, K * 16.0);
+    hipLaunchKernelGGL(k_comm_records, dim3(static_cast<unsigned>(ngroups)), dim3(64), 0, s,
+                       slots.as<uint32_t>(), wcount.as<uint32_t>(), woff.as<uint32_t>(), a->fp,
+                       b->fp, ma, 64 - o.key_bits, keys.as<uint64_t>(), vals.as<uint32_t>());
+    PAULI_HIP(hipGetLastError());
+  }
+  slots.reset();
+  PairSrc<WT, T> src{ra.as<uint64_t>(), ea.as<uint8_t>(), static_cast<const cplx<T>*>(a->coef),
+                     a->fp, rb.as<uint64_t>(), eb.as<uint8_t>(),
+                     static_cast<const cplx<T>*>(b->coef), b->fp, ma, W, 1};
+  return o.mode == PAULI_MERGE_COMPENSATED
+             ? run_pipeline<WT, T, kComp>(src, a->n, K, a->dtype, keys.as<uint64_t>(),
+                                          vals.as<uint32_t>(), o, s)
+             : run_pipeline<WT, T, kPlain>(src, a->n, K, a->dtype, keys.as<uint64_t>(),
+                                           vals.as<uint32_t>(), o, s);
+}
+
+template <typename T>
+paulisum* commutator_filtered_w(const paulisum* a, const paulisum* b, const MergeArgs& o,
+                                double max_frac, hipStream_t s) {
+  switch (a->W) {  // the pair source reads exactly WT words when WT <= 8
+    case 1: return commutator_filtered_t<1, T>(a, b, o, max_frac, s);
+    case 2: return commutator_filtered_t<2, T>(a, b, o, max_frac, s);
+    case 3: return commutator_filtered_t<3, T>(a, b, o, max_frac, s);
+    case 4: return commutator_filtered_t<4, T>(a, b, o, max_frac, s);
+    case 5: return commutator_filtered_t<5, T>(a, b, o, max_frac, s);
+    case 6: return commutator_filtered_t<6, T>(a, b, o, max_frac, s);
+    case 7: return commutator_filtered_t<7, T>(a, b, o, max_frac, s);
+    case 8: return commutator_filtered_t<8, T>(a, b, o, max_frac, s);
+    default: return commutator_filtered_t<kMaxWords, T>(a, b, o, max_frac, s);
+  }
+}
+
+}  // namespace
+
+paulisum* commutator_filtered(const paulisum* a, const paulisum* b, const MergeArgs& o,
+                              double max_frac, hipStream_t s) {
+  if (a->dtype == PAULI_C128) return commutator_filtered_w<double>(a, b, o, max_frac, s);
+  return commutator_filtered_w<float>(a, b, o, max_frac, s);
+}
+
 paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
                         const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
                         const MergeArgs& o, hipStream_t st) {

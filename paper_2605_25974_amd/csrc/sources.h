@@ -20,6 +20,7 @@ struct PairSrc {
   const uint64_t* fb;
   uint32_t ma;
   int nw;
+  int doubled = 0;  // 1: the value is 2 a_i b_j (a commutator's anticommuting pair)
 
   __device__ __forceinline__ void split(uint32_t id, uint32_t& i, uint32_t& j) const {
     j = id / ma;
@@ -55,8 +56,9 @@ struct PairSrc {
       w[nw + q] = z;
     }
     const cplx<T> a = ca[i], b = cb[j];
-    return rot_ik(acc, cmul(cplx<TV>{static_cast<TV>(a.re), static_cast<TV>(a.im)},
-                            cplx<TV>{static_cast<TV>(b.re), static_cast<TV>(b.im)}));
+    const cplx<TV> v = rot_ik(acc, cmul(cplx<TV>{static_cast<TV>(a.re), static_cast<TV>(a.im)},
+                                        cplx<TV>{static_cast<TV>(b.re), static_cast<TV>(b.im)}));
+    return doubled ? cplx<TV>{v.re + v.re, v.im + v.im} : v;
   }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const {
     uint32_t i, j;
