@@ -129,6 +129,19 @@ size_t radix_workspace_bytes(int64_t n);
 bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                       int64_t n, int key_bits, void* work, hipStream_t s,
                       uint64_t vary = ~0ull);
+// Stable passes on the 8-bit digits at the given shifts, in order (a key's
+// digit is (key >> shift) & 255).  Same result convention.
+bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                   int64_t n, const int* shifts, int nshifts, void* work, hipStream_t s);
+
+// k_fused.hip: (key, val) records of a key_bits-bit key put in key order by
+// a partition on the top key bits and an LDS sort per bucket, for uniformly
+// spread keys (fingerprints).  Equal keys end up ordered by val in buckets
+// the LDS counting sort takes, in input order elsewhere (both deterministic;
+// the same order when the vals ascend in input order).  Small inputs take
+// radix_sort_pairs.  Same result convention as radix_sort_pairs.
+bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                           uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s);
 
 // k_merge.hip
 struct MergeArgs {

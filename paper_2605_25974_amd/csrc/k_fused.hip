@@ -720,6 +720,9 @@ struct SegOut {
   uint32_t* nseg;    // [bucket] segment count
   uint32_t* long_list;  // (bucket, first record) of segments longer than kLong
   uint32_t* nlong;
+  // sort only (no segments): the sorted keys are written over the bucket's
+  // keys here, the ids over vals, and the other fields are not used
+  uint64_t* keys_out = nullptr;
 };
 
 // Loads the (key, id) records of a bucket of n <= kCap records starting at
@@ -756,6 +759,19 @@ __device__ void bucket_segments(uint32_t b, uint32_t lo, uint32_t n, SortSmem& S
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t span = sort_span(n);
   const int rounds = static_cast<int>(span / 64);
+  if (out.keys_out) {
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      if (q < n) {
+        const uint32_t at = PERM ? S.perm[q] : q;
+        out.keys_out[lo + q] = S.key[at];
+        out.vals[lo + q] = S.id[at];
+      }
+    }
+    return;
+  }
   // segment heads (a key differing from the one before), counted per wave
   uint64_t hb[kSortRounds];
   uint32_t hc = 0;
@@ -811,7 +827,7 @@ __device__ void bucket_segments(uint32_t b, uint32_t lo, uint32_t n, SortSmem& S
 // records is queued for k_heavy_sort, one with a bin of more than kMaxBin
 // records (many equal keys) for k_bucket_radix.
 __global__ void __launch_bounds__(kSortNT)
-k_bucket_count(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
+k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
                uint32_t nbk, SortField f, SegOut out, uint32_t* __restrict__ heavy,
                uint32_t* __restrict__ nheavy, uint32_t* __restrict__ redo,
                uint32_t* __restrict__ nredo) {
@@ -854,7 +870,7 @@ k_bucket_count(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ b
 // bucket when list is null.  A bucket over kCap records is queued for
 // k_heavy_sort.
 __global__ void __launch_bounds__(kSortNT)
-k_bucket_radix(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ boff,
+k_bucket_radix(const uint64_t* keys, const uint32_t* __restrict__ boff,
                uint32_t nbk, const uint32_t* __restrict__ list,
                const uint32_t* __restrict__ nlist, SortField f, SegOut out,
                uint32_t* __restrict__ heavy, uint32_t* __restrict__ nheavy) {
@@ -957,6 +973,7 @@ k_heavy_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ tkeys,
       }
       __syncthreads();
     }
+    if (out.keys_out) continue;  // sort only
     const uint64_t* K = keys + lo;
     uint32_t run = 0;
     for (uint32_t base = 0; base < n; base += kSortNT) {
@@ -1244,6 +1261,85 @@ int fused_default_bucket_bits(int64_t p, int key_bits) {
   if (d > kMaxBits) d = kMaxBits;
   if (d > key_bits) d = key_bits;
   return d;
+}
+
+namespace {
+
+// boff[b] = first record whose key has top bits >= b (keys in bucket order),
+// boff[nbk] = n.
+__global__ void k_bucket_bounds(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                uint32_t nbk, uint32_t* __restrict__ boff) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cur = r < n ? static_cast<int64_t>(keys[r] >> shift) : nbk;
+    const int64_t prev = r > 0 ? static_cast<int64_t>(keys[r - 1] >> shift) : -1;
+    for (int64_t b = prev + 1; b <= cur; ++b) boff[b] = static_cast<uint32_t>(r);
+  }
+}
+
+}  // namespace
+
+bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                           uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s) {
+  // small sorts: the radix passes (the bucket pipeline's fixed costs dominate)
+  if (n < (int64_t(1) << 16) || key_bits < 24 || n > 0xFFFFFFFFll) {
+    DBuf w(radix_workspace_bytes(n), s);
+    return radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, key_bits, w.p, s);
+  }
+  const int d = fused_default_bucket_bits(n, key_bits);
+  if (d == 0) {
+    DBuf w(radix_workspace_bytes(n), s);
+    return radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, key_bits, w.p, s);
+  }
+  const uint32_t nbk = 1u << d;
+  bool alt = false;
+  {  // partition on the top d bits: stable passes on 8-bit digits
+    int shifts[2];
+    int ns = 0;
+    shifts[ns++] = key_bits - d;
+    if (d > 8) shifts[ns++] = key_bits - d + 8;
+    DBuf w(radix_workspace_bytes(n), s);
+    alt = radix_sort_at(keys, vals, keys_alt, vals_alt, n, shifts, ns, w.p, s);
+  }
+  uint64_t* K = alt ? keys_alt : keys;
+  uint32_t* V = alt ? vals_alt : vals;
+  uint64_t* K2 = alt ? keys : keys_alt;
+  uint32_t* V2 = alt ? vals : vals_alt;
+  DBuf boff((nbk + 1) * 4ull, s), ctr(64, s), heavy(nbk * 4ull, s), redo(nbk * 4ull, s);
+  uint32_t* ctr32 = ctr.as<uint32_t>();  // [0] heavy count [6] radix redo count
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr32, 16u, 0u);
+  hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for(n + 1)), dim3(kB), 0, s, K, n, key_bits - d,
+                     nbk, boff.as<uint32_t>());
+  PAULI_HIP(hipGetLastError());
+  const int rem = key_bits - d;
+  SortField sf;
+  sf.lo14 = rem >= kBinBits ? rem - kBinBits : -1;
+  if (rem >= 16) {
+    sf.lo16 = rem - 16;
+    sf.passes = 2;
+    sf.fmask = 0xFFFFull;
+  } else {
+    sf.lo16 = 0;
+    sf.passes = (rem + 7) / 8;
+    sf.fmask = rem ? ((1ull << rem) - 1) : 0ull;
+  }
+  SegOut so{V, nullptr, nullptr, nullptr, nullptr, K};
+  StageScope sc(PAULI_STAGE_SORT, s, n * 24.0);
+  const uint32_t gsort = nbk < device_cus() ? nbk : device_cus();
+  if (sf.lo14 >= 0) {
+    hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
+                       nbk, sf, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(), ctr32 + 6);
+    hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, K,
+                       boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, so,
+                       heavy.as<uint32_t>(), ctr32);
+  } else {
+    hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
+                       nbk, nullptr, nullptr, sf, so, heavy.as<uint32_t>(), ctr32);
+  }
+  hipLaunchKernelGGL(k_heavy_sort, dim3(gsort), dim3(kSortNT), 0, s, K, K2, V2,
+                     boff.as<uint32_t>(), rem, heavy.as<uint32_t>(), ctr32, so);
+  PAULI_HIP(hipGetLastError());
+  return alt;
 }
 
 paulisum* fused_bucket(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {

@@ -279,9 +279,8 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, uint6
   if (!presorted) {
     keys_alt = DBuf(N * sizeof(uint64_t), s);
     vals_alt = DBuf(N * sizeof(uint32_t), s);
-    DBuf rwork(radix_workspace_bytes(N), s);
-    if (radix_sort_pairs(keys, vals, keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(), N,
-                         o.key_bits, rwork.p, s)) {
+    if (sort_records_bucketed(keys, vals, keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(), N,
+                              o.key_bits, s)) {
       keys = keys_alt.as<uint64_t>();
       vals = vals_alt.as<uint32_t>();
     }

@@ -224,13 +224,10 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
       PAULI_HIP(hipGetLastError());
       uint64_t* bk = nk.as<uint64_t>();
       uint32_t* bv = nv.as<uint32_t>();
-      if (nb > 1) {
-        DBuf rwork(radix_workspace_bytes(nb), st);
-        if (radix_sort_pairs(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), nb, o.key_bits,
-                             rwork.p, st)) {
-          bk = nk2.as<uint64_t>();
-          bv = nv2.as<uint32_t>();
-        }
+      if (nb > 1 && sort_records_bucketed(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), nb,
+                                          o.key_bits, st)) {
+        bk = nk2.as<uint64_t>();
+        bv = nv2.as<uint32_t>();
       }
       int64_t blocks = (static_cast<int64_t>(M2) + kMergeOut - 1) / kMergeOut;
       if (blocks > 65536) blocks = 65536;

@@ -235,16 +235,16 @@ size_t radix_workspace_bytes(int64_t n) {
   return counts + scan_workspace_bytes(256 * ntiles);
 }
 
-bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                      int64_t n, int key_bits, void* work, hipStream_t s, uint64_t vary) {
-  if (n <= 1 || key_bits <= 0) return false;
+bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                   int64_t n, const int* shifts, int nshifts, void* work, hipStream_t s) {
+  if (n <= 1) return false;
   int64_t ntiles = (n + kRsTile - 1) / kRsTile;
   uint32_t* counts = static_cast<uint32_t*>(work);
   size_t cbytes = (static_cast<size_t>(256 * ntiles + 1) * sizeof(uint32_t) + 255) & ~size_t(255);
   void* scan_work = static_cast<char*>(work) + cbytes;
   bool alt = false;
-  for (int shift = 0; shift < key_bits; shift += 8) {
-    if (((vary >> shift) & 0xFFull) == 0) continue;  // the same digit in every key
+  for (int k = 0; k < nshifts; ++k) {
+    const int shift = shifts[k];
     const uint64_t* kin = alt ? keys_alt : keys;
     const uint32_t* vin = alt ? vals_alt : vals;
     uint64_t* kout = alt ? keys : keys_alt;
@@ -262,6 +262,16 @@ bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32
     alt = !alt;
   }
   return alt;
+}
+
+bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                      int64_t n, int key_bits, void* work, hipStream_t s, uint64_t vary) {
+  if (n <= 1 || key_bits <= 0) return false;
+  int shifts[8];
+  int ns = 0;
+  for (int shift = 0; shift < key_bits; shift += 8)
+    if (((vary >> shift) & 0xFFull) != 0) shifts[ns++] = shift;  // else the same digit in every key
+  return radix_sort_at(keys, vals, keys_alt, vals_alt, n, shifts, ns, work, s);
 }
 
 }  // namespace pauli
