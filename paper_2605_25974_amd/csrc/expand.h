@@ -14,7 +14,8 @@ namespace pauli {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kLong = 32;  // segments longer than this are reduced by a block
+constexpr int kLong = 32;      // segments longer than this are reduced by a block
+constexpr int kLongB = 1024;  // threads of that block (many records in flight)
 constexpr int kBS = 32;    // terms per aligned store block of the expand kernel
 constexpr int kParts = 4;  // work items per bucket of the expand kernel
 
@@ -572,15 +573,16 @@ __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, i
 }
 
 // Segments longer than kLong: one block per segment; group g adds records
-// g, g + NG, ... in order, then the NG partial sums are added in group order.
+// g, g + NG, ... in order, then the NG partial sums are added in a fixed
+// pairwise tree.
 // In the compensated form a cancelled segment is summed again the same way
 // in FP64.
 template <int G, int WT, typename T, int MODE>
-__global__ void __launch_bounds__(kB)
+__global__ void __launch_bounds__(kLongB)
 k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ long_list,
               const uint32_t* __restrict__ nlong) {
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
-  constexpr int NG = kB / G;
+  constexpr int NG = kLongB / G;
   __shared__ Acc<MODE, TV> s_acc[NG];
   __shared__ double s_re[NG], s_im[NG];
   __shared__ uint32_t s_end;
@@ -619,10 +621,13 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
     if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
     if (gl == 0) s_acc[g] = acc;
     __syncthreads();
-    // every thread forms the same total, so the branch below is uniform
-    Acc<MODE, TV> tot;
-    tot.zero();
-    for (int h = 0; h < NG; ++h) tot.add(s_acc[h]);
+    // the NG partial sums in a fixed pairwise tree
+    for (int h = NG / 2; h > 0; h >>= 1) {
+      if (gl == 0 && g < h) s_acc[g].add(s_acc[g + h]);
+      __syncthreads();
+    }
+    // every thread reads the same total, so the branch below is uniform
+    const Acc<MODE, TV> tot = s_acc[0];
     TV vr = tot.value_re(), vi = tot.value_im();
     if (MODE == kComp && tot.cancels(E.tau)) {
       double re = 0.0, im = 0.0;
@@ -636,13 +641,15 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
         s_im[g] = im;
       }
       __syncthreads();
-      double tr = 0.0, ti = 0.0;
-      for (int h = 0; h < NG; ++h) {
-        tr = tr + s_re[h];
-        ti = ti + s_im[h];
+      for (int h = NG / 2; h > 0; h >>= 1) {
+        if (gl == 0 && g < h) {
+          s_re[g] = s_re[g] + s_re[g + h];
+          s_im[g] = s_im[g] + s_im[g + h];
+        }
+        __syncthreads();
       }
-      vr = static_cast<TV>(tr);
-      vi = static_cast<TV>(ti);
+      vr = static_cast<TV>(s_re[0]);
+      vi = static_cast<TV>(s_im[0]);
     }
     if (threadIdx.x < G)
       write_out<G, TV, TV>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, vr, vi,

@@ -1225,8 +1225,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   }
   {
     StageScope sc(PAULI_STAGE_LONG, s, 0.0);
-    hipLaunchKernelGGL((k_expand_long<G, WT, T, MODE>), dim3(256), dim3(kB), 0, s, E, op,
-                       long_list.as<uint32_t>(), ctr32 + 1);
+    const uint32_t nlong = host[1];  // the segment stage listed them all
+    if (nlong > 0)
+      hipLaunchKernelGGL((k_expand_long<G, WT, T, MODE>), dim3(nlong < 256u ? nlong : 256u),
+                         dim3(kLongB), 0, s, E, op, long_list.as<uint32_t>(), ctr32 + 1);
     PAULI_HIP(hipGetLastError());
   }
   PAULI_HIP(hipMemcpyAsync(host, ctr32, sizeof(host), hipMemcpyDeviceToHost, s));
