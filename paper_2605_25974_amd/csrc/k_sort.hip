@@ -117,25 +117,28 @@ k_rs_count(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __
   counts[threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Stable scatter of one tile.  Records are visited in rounds of 256
-// consecutive positions; inside a round each wave finds the lanes holding the
-// same digit with eight ballots, so the rank of a record among equal digits
-// is (earlier rounds) + (earlier waves of this round) + (earlier lanes of its
-// wave): exactly its order in the input.  Records are first placed in LDS
-// grouped by digit, then written out in LDS order so that each digit's run
-// is stored contiguously.
+// Stable scatter of one tile.  Each wave takes a contiguous quarter of the
+// tile and visits it in rounds of 64 consecutive records; in a round the
+// lanes holding the same digit are found with eight ballots, and the rank of
+// a record among the equal digits of its wave is (the wave's count of that
+// digit so far) + (earlier lanes of the round).  The wave counts are kept in
+// LDS, read by all peers before the first peer adds the round's number (LDS
+// operations of one wave take effect in program order).  One scan over the
+// digits then gives each wave's offset per digit, the wave order being the
+// input order, so the place of a record in the tile is its input order among
+// equal digits.  Records are placed in LDS grouped by digit, then written
+// out in LDS order so that each digit's run is stored contiguously.
 __global__ void __launch_bounds__(kRsBlock)
 k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
              uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
              const uint32_t* __restrict__ offsets, int64_t ntiles) {
   __shared__ uint64_t s_k[kRsTile];
   __shared__ uint32_t s_v[kRsTile];
-  __shared__ uint32_t s_hist[256], s_start[256], s_run[256], s_goff[256];
-  __shared__ uint32_t s_wc[kRsWaves][256];
+  __shared__ uint32_t s_start[256], s_goff[256];
+  __shared__ uint32_t s_wc[kRsWaves][256];  // wave counts, then wave offsets
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t base = blockIdx.x * (int64_t)kRsTile;
-  s_hist[tid] = 0;
-  s_run[tid] = 0;
+  const int64_t wbase = base + static_cast<int64_t>(wave) * (kRsItems * 64);
 #pragma unroll
   for (int w = 0; w < kRsWaves; ++w) s_wc[w][tid] = 0;
   s_goff[tid] = offsets[tid * ntiles + blockIdx.x];
@@ -143,59 +146,58 @@ k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
 
   uint64_t k[kRsItems];
   uint32_t v[kRsItems];
-  int d[kRsItems];
+  uint32_t rk[kRsItems];
 #pragma unroll
   for (int r = 0; r < kRsItems; ++r) {
-    int64_t i = base + r * kRsBlock + tid;
-    if (i < n) {
-      k[r] = kin[i];
-      v[r] = vin[i];
-      d[r] = static_cast<int>((k[r] >> shift) & 255);
-      atomicAdd(&s_hist[d[r]], 1u);
-    } else {
-      k[r] = 0;
-      v[r] = 0;
-      d[r] = -1;
-    }
+    const int64_t i = wbase + r * 64 + lane;
+    k[r] = i < n ? kin[i] : 0ull;
+    v[r] = i < n ? vin[i] : 0u;
   }
-  __syncthreads();
-  {
-    uint32_t h = s_hist[tid];
-    uint32_t ex = block_exclusive_scan<uint32_t>(h, nullptr);
-    s_start[tid] = ex;
-  }
-  __syncthreads();
-
   const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
   for (int r = 0; r < kRsItems; ++r) {
-    const bool valid = d[r] >= 0;
+    const bool valid = wbase + r * 64 + lane < n;
+    const int d = static_cast<int>((k[r] >> shift) & 255);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool bit = valid && ((d[r] >> b) & 1);
+      const bool bit = (d >> b) & 1;
       const uint64_t bm = __ballot(bit);
       peers &= bit ? bm : ~bm;
     }
-    const int rank = __popcll(peers & lt);
-    if (valid && rank == 0) s_wc[wave][d[r]] = static_cast<uint32_t>(__popcll(peers));
-    __syncthreads();
-    if (valid) {
-      uint32_t off = s_start[d[r]] + s_run[d[r]];
-      for (int w = 0; w < wave; ++w) off += s_wc[w][d[r]];
-      off += rank;
+    const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
+    const uint32_t before = valid ? s_wc[wave][d] : 0u;
+    if (valid && rank == 0) s_wc[wave][d] = before + static_cast<uint32_t>(__popcll(peers));
+    rk[r] = before + rank;
+  }
+  __syncthreads();
+  {  // thread tid is digit tid: the tile's start of the digit and each wave's offset
+    uint32_t c[kRsWaves];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kRsWaves; ++w) {
+      c[w] = s_wc[w][tid];
+      tot += c[w];
+    }
+    uint32_t run = block_exclusive_scan<uint32_t>(tot, nullptr);
+    s_start[tid] = run;
+#pragma unroll
+    for (int w = 0; w < kRsWaves; ++w) {
+      s_wc[w][tid] = run;
+      run += c[w];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    if (wbase + r * 64 + lane < n) {
+      const int d = static_cast<int>((k[r] >> shift) & 255);
+      const uint32_t off = s_wc[wave][d] + rk[r];
       s_k[off] = k[r];
       s_v[off] = v[r];
     }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int w = 0; w < kRsWaves; ++w) {
-      add += s_wc[w][tid];
-      s_wc[w][tid] = 0;
-    }
-    s_run[tid] += add;
-    __syncthreads();
   }
+  __syncthreads();
 
   const int64_t cnt = (n - base) < kRsTile ? (n - base) : kRsTile;
   for (int e = tid; e < cnt; e += kRsBlock) {

@@ -117,3 +117,31 @@ def test_lex_propagation_state_full_size():
     d = synth.workload5_state()
     g = pl.sort_lex(pl.PauliSum.from_dict(d)).export()
     _exact(g, _ref(d))
+
+
+@pytest.mark.parametrize("n,where", [(200, "x"), (100, "z"), (40, "x"), (300, "x2")])
+def test_lex_runs_of_equal_top_words(n, where):
+    """Strings whose most significant varying word takes a handful of values,
+    so that the words below decide the order inside long runs: the runs are
+    ordered on their lower words (with repeats of whole strings among them).
+    "x2": the two top X words both take few values."""
+    rng = synth.rng_for(975, n)
+    W = (n + 63) // 64
+    m = 20000
+    d = synth.random_sum(rng, n, m, distinct_strings=False)
+    top_bits = n - 64 * (W - 1)
+    few = np.array([0, 1, 3, 1 << (top_bits - 1)], np.uint64)
+    if where == "z":
+        d["x"][:] = 0
+        d["z"][:, W - 1] = rng.choice(few, size=m)
+    else:
+        d["x"][:, W - 1] = rng.choice(few, size=m)
+        if where == "x2":
+            d["x"][:, W - 2] = rng.choice(np.array([7, 1 << 63], np.uint64), size=m)
+    k = m // 5
+    src, dst = rng.integers(0, m, size=k), rng.integers(0, m, size=k)
+    d["x"][dst] = d["x"][src]
+    d["z"][dst] = d["z"][src]
+    g = pl.sort_lex(pl.PauliSum.from_dict(d)).export()
+    _exact(g, _ref(d))
+    _assert_nondecreasing(g["x"], g["z"])
