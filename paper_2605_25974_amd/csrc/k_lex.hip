@@ -7,16 +7,22 @@
 //
 // One pass over the sum first finds, per word, the bits that differ between
 // terms; a word that is the same for every term is skipped, and so is an
-// 8-bit digit that is.  The term positions are then radix-sorted (stable) on
-// the most significant varying word alone.  Terms whose value of that word is
-// unique are in their final place.  The others (runs of equal values) are
-// listed and put in order by a stable LSD over their varying words, least
-// significant first and ending with the top word again, which regroups the
-// runs in the order they had; they go back to the positions they came from.
-// For distinct random strings of more than 64 bits the runs are the repeats
-// of a string, and the whole order costs the passes of one word.  The rows
-// are then gathered once in the final order, through LDS tiles that keep both
-// the reads and the writes on whole lines.
+// 8-bit digit that is.  Two ways to order the positions, both stable LSD
+// radix sorts of 64-bit keys:
+//  * strings with few bit transitions (sparse letters, Z ranges: the
+//    Jordan-Wigner shape) sort on a few keys that code the places of their
+//    transitions (k_lex_trans_keys), when those take fewer sorts than the
+//    varying words;
+//  * otherwise the positions are sorted on the most significant varying word
+//    alone.  Terms whose value of that word is unique are then in their final
+//    place; the others (runs of equal values) are listed and put in order by
+//    a stable LSD over their varying words, least significant first and
+//    ending with the top word again, which regroups the runs in the order
+//    they had, and go back to the positions they came from.  For distinct
+//    random strings of more than 64 bits the runs are the repeats of a
+//    string, and the order costs the passes of one word.
+// The rows are then gathered once in the final order, through LDS tiles that
+// keep both the reads and the writes on whole lines.
 #include "common.h"
 #include "internal.h"
 
@@ -25,6 +31,11 @@ namespace pauli {
 namespace {
 
 constexpr int kLexBlock = 256;
+constexpr int kLexMaxKeys = 16;  // transition keys at most
+
+__global__ void k_fill_u32_lex(uint32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
 
 __global__ void k_lex_iota(uint32_t* __restrict__ idx, int64_t m) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m;
@@ -103,6 +114,105 @@ __global__ void k_lex_put(const uint32_t* __restrict__ pos, const uint32_t* __re
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ms;
        j += (int64_t)gridDim.x * blockDim.x)
     idx[pos[j]] = sub[j];
+}
+
+// The varying word positions, most significant first (p < W: Z[p], else
+// X[p - W]).
+struct LexWords {
+  int n;
+  int pos[2 * kMaxWords];
+};
+
+__device__ __forceinline__ const uint64_t* lex_word(const uint64_t* X, const uint64_t* Z, int W,
+                                                    int64_t ld, int p) {
+  return p < W ? Z + p * ld : X + (p - W) * ld;
+}
+
+// Transition code of a string.  Read the varying words as one bit string,
+// most significant bit first, with a 0 above the first bit; G is a bit's
+// place (0 at the top, L = 64 x the number of words).  A string is fixed by
+// the places of its transitions (bits that differ from the bit above), and
+// two strings compare as the tuples c_1, c_2, ... with c_j = L - G_j for odd
+// j (a 0 -> 1 transition: earlier means larger) and c_j = G_j for even j
+// (1 -> 0: earlier means smaller), a missing transition taking 0 (odd j) or
+// L (even j): at the first bit where two strings differ the same number of
+// transitions lie above, and exactly one of the two has its next transition
+// there.  Strings with few transitions (sparse letters, ranges of Z) thus
+// sort on a few 64-bit keys of S codes of b bits each instead of on all their
+// words.
+__device__ __forceinline__ uint64_t lex_transitions(uint64_t w, uint64_t prev) {
+  return w ^ ((w >> 1) | (prev << 63));
+}
+
+// The largest number of transitions over the terms.
+__global__ void __launch_bounds__(kLexBlock)
+k_lex_trans_max(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z, int W, int64_t ld,
+                int64_t m, LexWords vw, unsigned* __restrict__ tmax) {
+  unsigned mx = 0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t prev = 0;
+    unsigned c = 0;
+    for (int i = 0; i < vw.n; ++i) {
+      const uint64_t w = lex_word(X, Z, W, ld, vw.pos[i])[t];
+      c += static_cast<unsigned>(__popcll(lex_transitions(w, prev)));
+      prev = w & 1ull;
+    }
+    mx = c > mx ? c : mx;
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned o = __shfl_xor(mx, d, 64);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(tmax, mx);
+}
+
+// The K keys of every term (key k of term t at KS[k m + t]): the codes c_1,
+// c_2, ... in order, S to a key, the first in the key's top bits.  The next
+// word is loaded before the transitions of the current one are coded.
+__global__ void __launch_bounds__(kLexBlock)
+k_lex_trans_keys(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z, int W,
+                 int64_t ld, int64_t m, LexWords vw, int b, int S, int K,
+                 uint64_t* __restrict__ KS) {
+  const uint32_t L = 64u * static_cast<uint32_t>(vw.n);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t prev = 0, key = 0;
+    int j = 0, s = 0, k = 0;  // codes so far, codes in the current key, keys written
+    uint64_t w = lex_word(X, Z, W, ld, vw.pos[0])[t];
+    for (int i = 0; i < vw.n; ++i) {
+      const uint64_t wn = i + 1 < vw.n ? lex_word(X, Z, W, ld, vw.pos[i + 1])[t] : 0ull;
+      uint64_t tb = lex_transitions(w, prev);
+      prev = w & 1ull;
+      while (tb != 0ull) {
+        const int bit = 63 - __clzll(static_cast<long long>(tb));
+        tb &= ~(1ull << bit);
+        const uint32_t G = 64u * static_cast<uint32_t>(i) + static_cast<uint32_t>(63 - bit);
+        const uint32_t c = (j & 1) ? G : L - G;
+        key |= static_cast<uint64_t>(c) << (b * (S - 1 - s));
+        ++j;
+        if (++s == S) {
+          if (k < K) KS[k * m + t] = key;
+          ++k;
+          key = 0;
+          s = 0;
+        }
+      }
+      w = wn;
+    }
+    while (k < K) {  // missing transitions
+      const uint32_t c = (j & 1) ? L : 0u;
+      key |= static_cast<uint64_t>(c) << (b * (S - 1 - s));
+      ++j;
+      if (++s == S) {
+        KS[k * m + t] = key;
+        ++k;
+        key = 0;
+        s = 0;
+      }
+    }
+  }
 }
 
 // The terms as rows of RW = 2W + 4 words: X[0..W), Z[0..W), the
@@ -223,23 +333,46 @@ void lex_permute_t(const paulisum* s, const uint32_t* idx, paulisum* o, hipStrea
   PAULI_HIP(hipGetLastError());
 }
 
-// Stable LSD of the positions vals[0..n) on the varying words at positions
-// [0, top] (least significant first).  Returns the buffer holding the result.
-uint32_t* lex_lsd(const paulisum* s, const std::vector<uint64_t>& bits, int top, uint32_t* vals,
-                  uint32_t* spare, int64_t n, uint64_t* keys, uint64_t* keys_alt, void* work,
-                  hipStream_t st) {
-  for (int p = 0; p <= top; ++p) {
-    const uint64_t vary = bits[2 * p] ^ bits[2 * p + 1];
-    if (vary == 0) continue;
-    const uint64_t* w = p < s->W ? s->Z + p * s->ld : s->X + (p - s->W) * s->ld;
-    hipLaunchKernelGGL(k_lex_gather, dim3(lex_grid(n)), dim3(kLexBlock), 0, st, w, vals, n, keys);
+// A key column of the stable LSD: col[t] for term t; digits with no bit in
+// vary are skipped.
+struct LexCol {
+  const uint64_t* col;
+  uint64_t vary;
+};
+
+// Stable LSD of the terms vals[0..n) on the columns, least significant
+// first.  Returns the buffer holding the result.
+uint32_t* lex_lsd(const std::vector<LexCol>& cols, uint32_t* vals, uint32_t* spare, int64_t n,
+                  uint64_t* keys, uint64_t* keys_alt, void* work, hipStream_t st) {
+  for (const LexCol& c : cols) {
+    if (c.vary == 0) continue;
+    hipLaunchKernelGGL(k_lex_gather, dim3(lex_grid(n)), dim3(kLexBlock), 0, st, c.col, vals, n,
+                       keys);
     PAULI_HIP(hipGetLastError());
-    if (radix_sort_pairs(keys, vals, keys_alt, spare, n, 64, work, st, vary)) {
+    if (radix_sort_pairs(keys, vals, keys_alt, spare, n, 64, work, st, c.vary)) {
       std::swap(vals, spare);
       std::swap(keys, keys_alt);
     }
   }
   return vals;
+}
+
+// Number of transition keys that hold every term's codes, or 0 when they
+// would take as many sorts as the varying words (or more than kLexMaxKeys).
+int lex_transition_keys(const paulisum* s, const LexWords& vw, int b, int S, hipStream_t st) {
+  if (vw.n < 2) return 0;
+  DBuf tm(256, st);
+  hipLaunchKernelGGL(k_fill_u32_lex, dim3(1), dim3(64), 0, st, tm.as<uint32_t>(), 1);
+  int64_t g = (s->m + kLexBlock - 1) / kLexBlock;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_lex_trans_max, dim3(static_cast<unsigned>(g)), dim3(kLexBlock), 0, st,
+                     s->X, s->Z, s->W, s->ld, s->m, vw, tm.as<unsigned>());
+  PAULI_HIP(hipGetLastError());
+  uint32_t tmax = 0;
+  PAULI_HIP(hipMemcpyAsync(&tmax, tm.p, 4, hipMemcpyDeviceToHost, st));
+  PAULI_HIP(hipStreamSynchronize(st));
+  const int K = static_cast<int>((tmax + S - 1) / S);
+  return K >= 1 && K < vw.n && K <= kLexMaxKeys ? K : 0;
 }
 
 }  // namespace
@@ -268,15 +401,36 @@ paulisum* sort_lex(const paulisum* s, hipStream_t st) {
     std::vector<uint64_t> bits(static_cast<size_t>(npos) * 2);
     PAULI_HIP(hipMemcpyAsync(bits.data(), acc.p, bits.size() * 8, hipMemcpyDeviceToHost, st));
     PAULI_HIP(hipStreamSynchronize(st));
-    int top = -1;  // the most significant varying word position
-    for (int p = npos - 1; p >= 0 && top < 0; --p)
-      if (bits[2 * p] != bits[2 * p + 1]) top = p;
+    LexWords vw{};  // the varying word positions, most significant first
+    for (int p = npos - 1; p >= 0; --p)
+      if (bits[2 * p] != bits[2 * p + 1]) vw.pos[vw.n++] = p;
+    const int top = vw.n ? vw.pos[0] : -1;
 
     DBuf i0(m * 4ull, st), i1(m * 4ull, st), k0(m * 8ull, st), k1(m * 8ull, st);
     DBuf work(radix_workspace_bytes(m), st);
     uint32_t* cur = i0.as<uint32_t>();
     hipLaunchKernelGGL(k_lex_iota, dim3(lex_grid(m)), dim3(kLexBlock), 0, st, cur, m);
-    if (top >= 0) {
+    const uint32_t L = 64u * static_cast<uint32_t>(vw.n);
+    const int b = L ? 64 - __builtin_clzll(static_cast<unsigned long long>(L)) : 1;
+    const int S = 64 / b;
+    const int K = lex_transition_keys(s, vw, b, S, st);
+    if (K > 0) {
+      // few transitions: the K transition keys of all terms, least
+      // significant first; the first sort takes its key column in place
+      DBuf tk(static_cast<size_t>(K) * m * 8, st);
+      hipLaunchKernelGGL(k_lex_trans_keys, dim3(lex_grid(m)), dim3(kLexBlock), 0, st, s->X, s->Z,
+                         W, s->ld, m, vw, b, S, K, tk.as<uint64_t>());
+      PAULI_HIP(hipGetLastError());
+      const uint64_t used = S * b == 64 ? ~0ull : (1ull << (S * b)) - 1;
+      uint64_t* last = tk.as<uint64_t>() + static_cast<int64_t>(K - 1) * m;
+      if (radix_sort_pairs(last, cur, k0.as<uint64_t>(), i1.as<uint32_t>(), m, 64, work.p, st,
+                           used))
+        cur = i1.as<uint32_t>();
+      std::vector<LexCol> cols;
+      for (int k = K - 2; k >= 0; --k) cols.push_back({tk.as<uint64_t>() + k * m, used});
+      cur = lex_lsd(cols, cur, cur == i0.as<uint32_t>() ? i1.as<uint32_t>() : i0.as<uint32_t>(),
+                    m, k0.as<uint64_t>(), k1.as<uint64_t>(), work.p, st);
+    } else if (top >= 0) {
       // the top varying word alone
       const uint64_t vary = bits[2 * top] ^ bits[2 * top + 1];
       const uint64_t* w = top < W ? s->Z + top * s->ld : s->X + (top - W) * s->ld;
@@ -289,9 +443,7 @@ paulisum* sort_lex(const paulisum* s, hipStream_t st) {
         cur = i1.as<uint32_t>();
         keys = keys_alt;
       }
-      bool lower = false;  // a varying word below the top one
-      for (int p = 0; p < top; ++p) lower |= bits[2 * p] != bits[2 * p + 1];
-      if (lower) {
+      if (vw.n > 1) {
         // the runs of equal top words, ordered on all their varying words
         DBuf off(m * 4ull, st), tot(256, st), sw(scan_workspace_bytes(m), st);
         hipLaunchKernelGGL(k_lex_tied, dim3(lex_grid(m)), dim3(kLexBlock), 0, st, keys, m,
@@ -307,7 +459,12 @@ paulisum* sort_lex(const paulisum* s, hipStream_t st) {
                              off.as<uint32_t>(), tot.as<uint32_t>(), cur, m, pos.as<uint32_t>(),
                              sa.as<uint32_t>());
           PAULI_HIP(hipGetLastError());
-          uint32_t* su = lex_lsd(s, bits, top, sa.as<uint32_t>(), sb.as<uint32_t>(), ms,
+          std::vector<LexCol> cols;
+          for (int p = 0; p <= top; ++p) {
+            const uint64_t* wp = p < W ? s->Z + p * s->ld : s->X + (p - W) * s->ld;
+            cols.push_back({wp, bits[2 * p] ^ bits[2 * p + 1]});
+          }
+          uint32_t* su = lex_lsd(cols, sa.as<uint32_t>(), sb.as<uint32_t>(), ms,
                                  k0.as<uint64_t>(), k1.as<uint64_t>(), work.p, st);
           hipLaunchKernelGGL(k_lex_put, dim3(lex_grid(ms)), dim3(kLexBlock), 0, st,
                              pos.as<uint32_t>(), su, static_cast<int64_t>(ms), cur);

@@ -145,3 +145,54 @@ def test_lex_runs_of_equal_top_words(n, where):
     g = pl.sort_lex(pl.PauliSum.from_dict(d)).export()
     _exact(g, _ref(d))
     _assert_nondecreasing(g["x"], g["z"])
+
+
+def _ranges(rng, n, m):
+    """Z on one random range of qubits (sometimes reaching qubit 0 or the
+    last qubit), X on at most two qubits."""
+    W = (n + 63) // 64
+    bits_z = np.zeros((m, n), bool)
+    bits_x = np.zeros((m, n), bool)
+    a = rng.integers(0, n, size=m)
+    b = rng.integers(0, n + 1, size=m)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    lo[rng.random(m) < 0.2] = 0
+    hi[rng.random(m) < 0.2] = n
+    q = np.arange(n)
+    bits_z[:] = (q[None, :] >= lo[:, None]) & (q[None, :] < hi[:, None])
+    for _ in range(2):
+        sel = rng.random(m) < 0.5
+        bits_x[np.nonzero(sel)[0], rng.integers(0, n, size=int(sel.sum()))] = True
+    pack = lambda B: np.packbits(np.pad(B, ((0, 0), (0, 64 * W - n))).reshape(m, W, 64)[:, :, ::-1],
+                                 axis=2, bitorder="big").view(">u8").reshape(m, W).astype(np.uint64)
+    return pack(bits_x), pack(bits_z)
+
+
+@pytest.mark.parametrize("n,kind", [(70, "jw"), (130, "jw"), (500, "jw"), (200, "sparse"),
+                                    (300, "ranges"), (64, "ranges"), (1000, "ranges")])
+def test_lex_strings_with_few_transitions(n, kind):
+    """Strings with few bit transitions, which are put in order on their
+    transition codes: Jordan-Wigner-shaped strings, strings of weight <= 3,
+    and Z ranges with X on a qubit or two.  Full comparison with the oracle's
+    stable order (repeats of whole strings included), in complex128 and in
+    complex64."""
+    rng = synth.rng_for(976, n)
+    m = 20000
+    if kind == "jw":
+        x, z = synth.jordan_wigner(rng, n, m)
+    elif kind == "sparse":
+        d = synth.random_sum(rng, n, m, wmax=3, distinct_strings=False)
+        x, z = d["x"], d["z"]
+    else:
+        x, z = _ranges(rng, n, m)
+    k = m // 10
+    src, dst = rng.integers(0, m, size=k), rng.integers(0, m, size=k)
+    x[dst] = x[src]
+    z[dst] = z[src]
+    c = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    d = synth.make_sum(n, x, z, c, rng.integers(0, 4, size=m).astype(np.uint8))
+    g = pl.sort_lex(pl.PauliSum.from_dict(d)).export()
+    _exact(g, _ref(d))
+    _assert_nondecreasing(g["x"], g["z"])
+    d["coef"] = d["coef"].astype(np.complex64)
+    _exact(pl.sort_lex(pl.PauliSum.from_dict(d)).export(), _ref(d))
