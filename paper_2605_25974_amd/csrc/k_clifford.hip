@@ -17,94 +17,63 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// A gate as two lookup tables over the four letter bits it reads,
+// idx = x0 | z0 << 1 | x1 << 2 | z1 << 3 (qubit q0's letter, then q1's;
+// a one-qubit gate has q1 = q0 and leaves bits 2 and 3 as they are): the
+// new bits are 4-bit entry idx of the 64-bit table (tlo holds entries 0-7,
+// thi 8-15), and bit idx of ftab says whether the string's sign flips.
+// Every gate is then the same branch-free update, done on 32-bit halves of
+// the packed words: qubit q is bit q % 32 of half-word q / 32.
 struct DevGate {
-  int kind, q0, q1, pad;
-  uint64_t col[4];  // fingerprint columns of x_q0, z_q0, x_q1, z_q1
+  int w0, b0, w1, b1;  // half-word and bit of q0 and of q1
+  uint32_t tlo, thi, ftab, pad;
+  uint32_t col[8];  // fingerprint columns of x_q0, z_q0, x_q1, z_q1 as (low, high) halves
 };
 
-// The words of the term a thread works on, in LDS: x[w][threadIdx.x].
-// A gate's word index is the same for every thread, so the accesses of a
-// wave are consecutive (no bank conflicts) and registers are never indexed
-// dynamically.
+// The half-words of the term a thread works on, in LDS: x[h][threadIdx.x].
+// A gate's half-word index is the same for every thread, so the accesses of
+// a wave are consecutive (no bank conflicts) and registers are never
+// indexed dynamically.
 template <int WT>
 struct Words {
-  uint64_t x[WT][kBlock];
-  uint64_t z[WT][kBlock];
+  uint32_t x[2 * WT][kBlock];
+  uint32_t z[2 * WT][kBlock];
 };
 
-// One gate's conjugation on the letters of its qubits (letters by Table I:
-// (x, z) = (1, 0) X, (0, 1) Z, (1, 1) Y).  Returns 1 when the string's sign
-// flips.  The rules are the images of X, Z (and Y = i X Z) under U . U^dag:
-//   H:   X <-> Z, Y -> -Y            S:   X -> Y, Y -> -X, Z -> Z
-//   S^dag: X -> -Y, Y -> X           X, Y, Z: sign flips on anticommuting letters
-//   CX(c,t): X_c -> X_c X_t, Z_t -> Z_c Z_t (X_t, Z_c unchanged)
-//   CZ(a,b): X_a -> X_a Z_b, X_b -> Z_a X_b (Z unchanged)
-//   SWAP: the two letters exchange places
-// Each word the gate touches is read once from LDS and written once.
+// One gate on a term: each half-word the gate touches is read once from LDS
+// and written once; the fingerprint halves take the columns of the bits
+// that change.  Returns 1 when the string's sign flips.
 template <int WT>
-__device__ __forceinline__ uint32_t apply_gate(Words<WT>& s, const DevGate& g, uint64_t& fp) {
+__device__ __forceinline__ uint32_t apply_gate(Words<WT>& s, const DevGate& g, uint32_t& flo,
+                                               uint32_t& fhi) {
   const int t = threadIdx.x;
-  const bool two = g.kind >= PAULI_GATE_CX;
-  const int w0 = g.q0 >> 6, b0 = g.q0 & 63, w1 = g.q1 >> 6, b1 = g.q1 & 63;
-  uint64_t xw0 = s.x[w0][t], zw0 = s.z[w0][t];
-  uint64_t xw1 = xw0, zw1 = zw0;
-  if (two && w1 != w0) {
-    xw1 = s.x[w1][t];
-    zw1 = s.z[w1][t];
+  const int w0 = g.w0, b0 = g.b0, w1 = g.w1, b1 = g.b1;
+  const uint32_t xa = s.x[w0][t], za = s.z[w0][t];
+  uint32_t xb = xa, zb = za;
+  if (w1 != w0) {
+    xb = s.x[w1][t];
+    zb = s.z[w1][t];
   }
-  const uint32_t x0 = static_cast<uint32_t>(xw0 >> b0) & 1u, z0 = static_cast<uint32_t>(zw0 >> b0) & 1u;
-  const uint32_t x1 = static_cast<uint32_t>(xw1 >> b1) & 1u, z1 = static_cast<uint32_t>(zw1 >> b1) & 1u;
-  uint32_t nx0 = x0, nz0 = z0, nx1 = x1, nz1 = z1, flip = 0;
-  switch (g.kind) {
-    case PAULI_GATE_H:
-      nx0 = z0; nz0 = x0; flip = x0 & z0;
-      break;
-    case PAULI_GATE_S:
-      nz0 = z0 ^ x0; flip = x0 & z0;
-      break;
-    case PAULI_GATE_SDG:
-      nz0 = z0 ^ x0; flip = x0 & (z0 ^ 1u);
-      break;
-    case PAULI_GATE_X:
-      flip = z0;
-      break;
-    case PAULI_GATE_Y:
-      flip = x0 ^ z0;
-      break;
-    case PAULI_GATE_Z:
-      flip = x0;
-      break;
-    case PAULI_GATE_CX:
-      nx1 = x1 ^ x0; nz0 = z0 ^ z1; flip = x0 & z1 & (x1 ^ z0 ^ 1u);
-      break;
-    case PAULI_GATE_CZ:
-      nz0 = z0 ^ x1; nz1 = z1 ^ x0; flip = x0 & x1 & (z0 ^ z1);
-      break;
-    default:  // PAULI_GATE_SWAP
-      nx0 = x1; nz0 = z1; nx1 = x0; nz1 = z0;
-      break;
-  }
-  // bit changes as XOR masks, then fingerprint columns of the changed bits
-  const uint64_t dx0 = static_cast<uint64_t>(nx0 ^ x0) << b0, dz0 = static_cast<uint64_t>(nz0 ^ z0) << b0;
-  const uint64_t dx1 = static_cast<uint64_t>(nx1 ^ x1) << b1, dz1 = static_cast<uint64_t>(nz1 ^ z1) << b1;
-  if (dx0) fp ^= g.col[0];
-  if (dz0) fp ^= g.col[1];
-  if (two) {
-    if (dx1) fp ^= g.col[2];
-    if (dz1) fp ^= g.col[3];
-  }
-  if (two && w1 == w0) {
-    s.x[w0][t] = xw0 ^ dx0 ^ dx1;
-    s.z[w0][t] = zw0 ^ dz0 ^ dz1;
+  const uint32_t idx = ((xa >> b0) & 1u) | (((za >> b0) & 1u) << 1) | (((xb >> b1) & 1u) << 2) |
+                       (((zb >> b1) & 1u) << 3);
+  const uint32_t tw = idx < 8u ? g.tlo : g.thi;
+  const uint32_t d = ((tw >> (4u * (idx & 7u))) & 15u) ^ idx;  // changed bits
+  const uint32_t m0 = 0u - (d & 1u), m1 = 0u - ((d >> 1) & 1u);
+  const uint32_t m2 = 0u - ((d >> 2) & 1u), m3 = 0u - (d >> 3);
+  flo ^= (g.col[0] & m0) ^ (g.col[2] & m1) ^ (g.col[4] & m2) ^ (g.col[6] & m3);
+  fhi ^= (g.col[1] & m0) ^ (g.col[3] & m1) ^ (g.col[5] & m2) ^ (g.col[7] & m3);
+  const uint32_t dx0 = (d & 1u) << b0, dz0 = ((d >> 1) & 1u) << b0;
+  const uint32_t dx1 = ((d >> 2) & 1u) << b1, dz1 = (d >> 3) << b1;
+  if (w1 == w0) {
+    s.x[w0][t] = xa ^ dx0 ^ dx1;
+    s.z[w0][t] = za ^ dz0 ^ dz1;
   } else {
-    s.x[w0][t] = xw0 ^ dx0;
-    s.z[w0][t] = zw0 ^ dz0;
-    if (two) {
-      s.x[w1][t] = xw1 ^ dx1;
-      s.z[w1][t] = zw1 ^ dz1;
-    }
+    s.x[w0][t] = xa ^ dx0;
+    s.z[w0][t] = za ^ dz0;
+    s.x[w1][t] = xb ^ dx1;
+    s.z[w1][t] = zb ^ dz1;
   }
-  return flip;
+  return (g.ftab >> idx) & 1u;
 }
 
 template <int WT, typename T>
@@ -121,23 +90,35 @@ k_clifford(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
        t += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int w = 0; w < WT; ++w) {
-      s.x[w][tid] = w < nw ? X[w * ld + t] : 0ull;
-      s.z[w][tid] = w < nw ? Z[w * ld + t] : 0ull;
+      const uint64_t xv = w < nw ? X[w * ld + t] : 0ull;
+      const uint64_t zv = w < nw ? Z[w * ld + t] : 0ull;
+      s.x[2 * w][tid] = static_cast<uint32_t>(xv);
+      s.x[2 * w + 1][tid] = static_cast<uint32_t>(xv >> 32);
+      s.z[2 * w][tid] = static_cast<uint32_t>(zv);
+      s.z[2 * w + 1][tid] = static_cast<uint32_t>(zv >> 32);
     }
-    uint64_t f = fp[t];
+    const uint64_t f0 = fp[t];
+    uint32_t flo = static_cast<uint32_t>(f0), fhi = static_cast<uint32_t>(f0 >> 32);
     uint32_t flips = 0;
-    // every thread reads the same gate: uniform (scalar) loads
-#pragma unroll 4
-    for (int i = 0; i < ngates; ++i) flips += apply_gate<WT>(s, gates[i], f);
+    // every thread reads the same gate: uniform (scalar) loads, the next
+    // gate's issued before the current one is applied
+    if (ngates > 0) {
+      DevGate g = gates[0];
+      for (int i = 0; i < ngates; ++i) {
+        const DevGate nx = gates[i + 1 < ngates ? i + 1 : i];
+        flips += apply_gate<WT>(s, g, flo, fhi);
+        g = nx;
+      }
+    }
 #pragma unroll
     for (int w = 0; w < WT; ++w)
       if (w < nw) {
-        OX[w * ldo + t] = s.x[w][tid];
-        OZ[w * ldo + t] = s.z[w][tid];
+        OX[w * ldo + t] = s.x[2 * w][tid] | (static_cast<uint64_t>(s.x[2 * w + 1][tid]) << 32);
+        OZ[w * ldo + t] = s.z[2 * w][tid] | (static_cast<uint64_t>(s.z[2 * w + 1][tid]) << 32);
       }
     Oph[t] = static_cast<uint8_t>((ph[t] + 2 * flips) & 3);
     Oc[t] = c[t];
-    Ofp[t] = f;
+    Ofp[t] = flo | (static_cast<uint64_t>(fhi) << 32);
   }
 }
 
@@ -164,6 +145,55 @@ void clifford_t(const paulisum* s, const DevGate* dg, int ngates, paulisum* o, h
   PAULI_HIP(hipGetLastError());
 }
 
+// The tables of a gate kind.  The rules are the images of X, Z (and
+// Y = i X Z) under U . U^dag, letters by Table I ((x, z) = (1, 0) X,
+// (0, 1) Z, (1, 1) Y):
+//   H:   X <-> Z, Y -> -Y            S:   X -> Y, Y -> -X, Z -> Z
+//   S^dag: X -> -Y, Y -> X           X, Y, Z: sign flips on anticommuting letters
+//   CX(c,t): X_c -> X_c X_t, Z_t -> Z_c Z_t (X_t, Z_c unchanged)
+//   CZ(a,b): X_a -> X_a Z_b, X_b -> Z_a X_b (Z unchanged)
+//   SWAP: the two letters exchange places
+void gate_tables(int kind, uint64_t* tab, uint32_t* ftab) {
+  *tab = 0;
+  *ftab = 0;
+  for (uint32_t idx = 0; idx < 16; ++idx) {
+    const uint32_t x0 = idx & 1u, z0 = (idx >> 1) & 1u, x1 = (idx >> 2) & 1u, z1 = (idx >> 3) & 1u;
+    uint32_t nx0 = x0, nz0 = z0, nx1 = x1, nz1 = z1, flip = 0;
+    switch (kind) {
+      case PAULI_GATE_H:
+        nx0 = z0; nz0 = x0; flip = x0 & z0;
+        break;
+      case PAULI_GATE_S:
+        nz0 = z0 ^ x0; flip = x0 & z0;
+        break;
+      case PAULI_GATE_SDG:
+        nz0 = z0 ^ x0; flip = x0 & (z0 ^ 1u);
+        break;
+      case PAULI_GATE_X:
+        flip = z0;
+        break;
+      case PAULI_GATE_Y:
+        flip = x0 ^ z0;
+        break;
+      case PAULI_GATE_Z:
+        flip = x0;
+        break;
+      case PAULI_GATE_CX:
+        nx1 = x1 ^ x0; nz0 = z0 ^ z1; flip = x0 & z1 & (x1 ^ z0 ^ 1u);
+        break;
+      case PAULI_GATE_CZ:
+        nz0 = z0 ^ x1; nz1 = z1 ^ x0; flip = x0 & x1 & (z0 ^ z1);
+        break;
+      default:  // PAULI_GATE_SWAP
+        nx0 = x1; nz0 = z1; nx1 = x0; nz1 = z0;
+        break;
+    }
+    const uint64_t out = nx0 | (nz0 << 1) | (nx1 << 2) | (nz1 << 3);
+    *tab |= out << (4 * idx);
+    *ftab |= flip << idx;
+  }
+}
+
 }  // namespace
 
 paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n_gates,
@@ -172,14 +202,22 @@ paulisum* apply_clifford(const paulisum* s, const pauli_gate_t* gates, int32_t n
   for (int32_t i = 0; i < n_gates; ++i) {
     const pauli_gate_t& g = gates[i];
     DevGate& d = dg[static_cast<size_t>(i)];
-    d.kind = g.kind;
-    d.q0 = g.q0;
-    d.q1 = g.kind >= PAULI_GATE_CX ? g.q1 : g.q0;
+    const int q0 = g.q0, q1 = g.kind >= PAULI_GATE_CX ? g.q1 : g.q0;
+    d.w0 = q0 >> 5;
+    d.b0 = q0 & 31;
+    d.w1 = q1 >> 5;
+    d.b1 = q1 & 31;
+    uint64_t tab = 0;
+    gate_tables(g.kind, &tab, &d.ftab);
+    d.tlo = static_cast<uint32_t>(tab);
+    d.thi = static_cast<uint32_t>(tab >> 32);
     d.pad = 0;
-    d.col[0] = fp_column(2 * d.q0);
-    d.col[1] = fp_column(2 * d.q0 + 1);
-    d.col[2] = fp_column(2 * d.q1);
-    d.col[3] = fp_column(2 * d.q1 + 1);
+    const uint64_t cols[4] = {fp_column(2 * q0), fp_column(2 * q0 + 1), fp_column(2 * q1),
+                              fp_column(2 * q1 + 1)};
+    for (int k = 0; k < 4; ++k) {
+      d.col[2 * k] = static_cast<uint32_t>(cols[k]);
+      d.col[2 * k + 1] = static_cast<uint32_t>(cols[k] >> 32);
+    }
   }
   paulisum* o = new_sum(s->n, s->m, s->m, s->dtype, st);
   if (s->m == 0) return o;
