@@ -71,15 +71,13 @@ k_heads(Src src, const uint64_t* __restrict__ keys, const uint32_t* __restrict__
         uint32_t* __restrict__ head, cplx<TV>* __restrict__ v, uint32_t* __restrict__ dirty,
         int second_pass) {
   if (second_pass && *dirty == 0) return;
-  uint64_t w[2 * WT], pw[2 * WT];
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
        r += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t id = vals[r];
-    v[r] = src.template term<TV>(id, w);
+    v[r] = src.template value<TV>(id);
     uint32_t h = 1;
-    if (r > 0 && keys[r] == keys[r - 1]) {
-      src.string(vals[r - 1], pw);
-      if (words_equal<WT>(w, pw, src.nw))
+    if (r > 0 && keys[r] == keys[r - 1]) {  // the strings only where the keys are equal
+      if (same_string<WT>(src, id, vals[r - 1]))
         h = 0;
       else if (!second_pass)
         atomicOr(dirty, 1u);
@@ -153,8 +151,7 @@ __device__ __forceinline__ bool keep_value(cplx<T> c, double drop2) {
 // FP64 value of record r (the re-merge of a cancelled segment).
 template <int WT, typename Src>
 __device__ __forceinline__ cplx<double> value64(const Src& src, uint32_t id) {
-  uint64_t w[2 * WT];
-  return src.template term<double>(id, w);
+  return src.template value<double>(id);
 }
 
 // Short segments: one thread adds its records in order.  In the compensated
@@ -591,9 +588,11 @@ paulisum* merge_rotated_t(const paulisum* a, const RotString& P, double theta,
   src.pfp = P.fp;
   src.co = static_cast<T>(std::cos(theta));
   src.si = static_cast<T>(std::sin(theta));
+  src.smask = 0;
   for (int q = 0; q < WT; ++q) {
     src.px[q] = q < a->W ? P.x[q] : 0ull;
     src.pz[q] = q < a->W ? P.z[q] : 0ull;
+    if (src.px[q] | src.pz[q]) src.smask |= 1u << q;
   }
   return o.mode == PAULI_MERGE_COMPENSATED
              ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s, true)

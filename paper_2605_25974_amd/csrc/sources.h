@@ -60,11 +60,19 @@ struct PairSrc {
                                         cplx<TV>{static_cast<TV>(b.re), static_cast<TV>(b.im)}));
     return doubled ? cplx<TV>{v.re + v.re, v.im + v.im} : v;
   }
+  // The value alone (the phase needs the words of both operands).
+  template <typename TV = T>
+  __device__ __forceinline__ cplx<TV> value(uint32_t id) const {
+    uint64_t w[2 * WT];
+    return term<TV>(id, w);
+  }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const {
     uint32_t i, j;
     split(id, i, j);
     return fa[i] ^ fb[j];
   }
+  __device__ __forceinline__ uint64_t xword(uint32_t id, int q) const { return word(id, q); }
+  __device__ __forceinline__ uint64_t zword(uint32_t id, int q) const { return word(id, nw + q); }
   // Word t of the product string (X words first, then Z words).
   __device__ __forceinline__ uint64_t word(uint32_t id, int t) const {
     uint32_t i, j;
@@ -98,6 +106,13 @@ struct TermSrc {
     const cplx<T> v = c[id];
     return rot_ik(ph[id], cplx<TV>{static_cast<TV>(v.re), static_cast<TV>(v.im)});
   }
+  template <typename TV = T>
+  __device__ __forceinline__ cplx<TV> value(uint32_t id) const {
+    const cplx<T> v = c[id];
+    return rot_ik(ph[id], cplx<TV>{static_cast<TV>(v.re), static_cast<TV>(v.im)});
+  }
+  __device__ __forceinline__ uint64_t xword(uint32_t id, int q) const { return X[q * ld + id]; }
+  __device__ __forceinline__ uint64_t zword(uint32_t id, int q) const { return Z[q * ld + id]; }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const { return f[id]; }
 };
 
@@ -120,6 +135,7 @@ struct RotSrc {
   int py;
   uint64_t pfp;
   T co, si;
+  uint32_t smask;  // bit q: P has a letter in word q
   uint64_t px[WT], pz[WT];
 
   __device__ __forceinline__ void string(uint32_t id, uint64_t* w) const {
@@ -132,12 +148,13 @@ struct RotSrc {
       w[nw + q] = Z[q * ld + t] ^ (pz[q] & nm);
     }
   }
+  // The value alone: a word where P has no letter adds nothing to the phase
+  // of P Q_t (its two popcounts cancel), so only P's words are read.
   template <typename TV = T>
-  __device__ __forceinline__ cplx<TV> term(uint32_t id, uint64_t* w) const {
+  __device__ __forceinline__ cplx<TV> value(uint32_t id) const {
     const uint32_t t = id >> 1;
     const cplx<T> v = c[t];
     if ((id & 1u) == 0) {
-      string(id, w);
       const cplx<T> u = cnt[t] == 2 ? cplx<T>{v.re * co, v.im * co} : v;
       return rot_ik(ph[t], cplx<TV>{static_cast<TV>(u.re), static_cast<TV>(u.im)});
     }
@@ -145,15 +162,19 @@ struct RotSrc {
 #pragma unroll
     for (int q = 0; q < WT; ++q) {
       if (WT > 8 && q >= nw) break;
+      if (((smask >> q) & 1u) == 0) continue;
       const uint64_t xq = X[q * ld + t], zq = Z[q * ld + t];
       const uint64_t x3 = px[q] ^ xq, z3 = pz[q] ^ zq;
       k += popc64(xq & zq) + 2 * popc64(pz[q] & xq) - popc64(x3 & z3);
-      w[q] = x3;
-      w[nw + q] = z3;
     }
-    // -i sin(theta) i^k P Q: the factor -i = i^3 joins the phase exponent
     const cplx<T> u{v.re * si, v.im * si};
     return rot_ik((ph[t] + k + 3) & 3, cplx<TV>{static_cast<TV>(u.re), static_cast<TV>(u.im)});
+  }
+  __device__ __forceinline__ uint64_t xword(uint32_t id, int q) const {
+    return X[q * ld + (id >> 1)] ^ ((id & 1u) ? px[q] : 0ull);
+  }
+  __device__ __forceinline__ uint64_t zword(uint32_t id, int q) const {
+    return Z[q * ld + (id >> 1)] ^ ((id & 1u) ? pz[q] : 0ull);
   }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const {
     return f[id >> 1] ^ ((id & 1u) ? pfp : 0ull);
@@ -167,6 +188,18 @@ __device__ __forceinline__ bool words_equal(const uint64_t* a, const uint64_t* b
   for (int q = 0; q < 2 * WT; ++q) {
     if (WT > 8 && q >= 2 * nw) break;
     d |= a[q] ^ b[q];
+  }
+  return d == 0;
+}
+
+// Whether records a and b have the same string, one word pair at a time.
+template <int WT, typename Src>
+__device__ __forceinline__ bool same_string(const Src& src, uint32_t a, uint32_t b) {
+  uint64_t d = 0;
+#pragma unroll 2
+  for (int q = 0; q < WT; ++q) {
+    if (WT > 8 && q >= src.nw) break;
+    d |= (src.xword(a, q) ^ src.xword(b, q)) | (src.zword(a, q) ^ src.zword(b, q));
   }
   return d == 0;
 }
