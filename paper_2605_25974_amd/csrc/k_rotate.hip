@@ -34,7 +34,10 @@ __global__ void k_rot_count(const uint64_t* __restrict__ X, const uint64_t* __re
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x) {
     int s = 0;
-    for (int w = 0; w < P.W; ++w) s += popc64((X[w * ld + t] & P.z[w]) ^ (Z[w * ld + t] & P.x[w]));
+    for (int w = 0; w < P.W; ++w) {
+      if ((P.x[w] | P.z[w]) == 0) continue;  // no letter of P in this word: nothing to read
+      s += popc64((X[w * ld + t] & P.z[w]) ^ (Z[w * ld + t] & P.x[w]));
+    }
     cnt[t] = 1u + static_cast<uint32_t>(s & 1);
   }
 }
