@@ -129,3 +129,41 @@ def test_conjugation_steps_without_anticommuting_terms():
                      rotate_mode=pl.ROTATE_CONJUGATE).export()
     ref = O.merge(_osum(S))
     parity.assert_merged_fp64(g, ref)
+
+
+def _letter(n, W, q, letter):
+    """(x, z) words of one letter (1 X, 2 Y, 3 Z) on qubit q."""
+    x = np.zeros(W, np.uint64)
+    z = np.zeros(W, np.uint64)
+    b = np.uint64(1) << np.uint64(q % 64)
+    if letter in (1, 2):
+        x[q // 64] |= b
+    if letter in (2, 3):
+        z[q // 64] |= b
+    return x, z
+
+
+@pytest.mark.parametrize("n", [100, 1000])
+def test_conjugation_generators_in_few_words(n):
+    """Generators whose letters sit in one word, in the first and last
+    words, and in the last (partial) word: the steps read only the words
+    where the generator has letters (anticommutation count and the phase of
+    the new terms) and must still match the oracle, with 2 and 16 words."""
+    W = (n + 63) // 64
+    S = synth.random_sum(synth.rng_for(733, n), n, 1500, wmax=min(n, 300), distinct_strings=False)
+    gens = [[(1, 1), (5, 2), (9, 3)],                       # one word (the first)
+            [(2, 2), (n - 1, 1)],                           # first and last qubit
+            [(n - 3, 3), (n - 2, 2), (n - 1, 1)],           # the last word only
+            [(64 * (W // 2) + 7, 2), (3, 3), (n - 5, 1)]]   # three words
+    x = np.zeros((len(gens), W), np.uint64)
+    z = np.zeros((len(gens), W), np.uint64)
+    for s, g in enumerate(gens):
+        for q, letter in g:
+            gx, gz = _letter(n, W, q, letter)
+            x[s] |= gx
+            z[s] |= gz
+    th = np.array([0.4, 1.3, 2.2, 0.8])
+    g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, rotate_mode=pl.ROTATE_CONJUGATE).export()
+    ref = O.propagate(_osum(S), x, z, th, mode=O.CONJUGATE)
+    parity.assert_merged_fp64(g, ref)
+    parity.assert_sorted_by_key(g)
