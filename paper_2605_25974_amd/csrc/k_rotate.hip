@@ -195,18 +195,33 @@ RotString rot_string(int n, const uint64_t* px, const uint64_t* pz) {
   return P;
 }
 
+// Every term gives two records: (cos theta) Q_t and (-i sin theta) P Q_t.
+__global__ void k_rot_all(int64_t m, uint32_t* __restrict__ cnt) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
+       t += (int64_t)gridDim.x * blockDim.x)
+    cnt[t] = 2u;
+}
+
+// One rotation step on the records 2t (Q_t, times cos theta where cnt[t] is
+// 2) and 2t + 1 (-i sin theta P Q_t, where cnt[t] is 2).  The conjugation
+// P-rotation keeps the terms that commute with P as they are (cnt[t] = 1);
+// the literal product (cos theta I - i sin theta P) Q_t gives both records
+// for every term (all_new).
 // sorted_input: s is in key order (a merge's output with the same key bits).
 template <typename T>
 paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const MergeArgs& o,
-                      bool sorted_input, hipStream_t st) {
+                      bool sorted_input, bool all_new, hipStream_t st) {
   const int64_t m = s->m;
   DBuf cnt((m + 1) * 4, st), off((m + 1) * 4, st), tot(4, st), work(scan_workspace_bytes(m), st);
   const unsigned g = grid_for(m);
   uint32_t M2 = 0;
   {
     StageScope sc(PAULI_STAGE_PREP, st, m * (16.0 * s->W + 8));
-    hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, m, P,
-                       cnt.as<uint32_t>());
+    if (all_new)
+      hipLaunchKernelGGL(k_rot_all, dim3(g), dim3(kBlock), 0, st, m, cnt.as<uint32_t>());
+    else
+      hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, m, P,
+                         cnt.as<uint32_t>());
     scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, st);
     PAULI_HIP(hipMemcpyAsync(&M2, tot.p, 4, hipMemcpyDeviceToHost, st));
     PAULI_HIP(hipStreamSynchronize(st));
@@ -304,8 +319,15 @@ paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz,
   const RotString P = rot_string(s->n, px, pz);
   if (mode == PAULI_ROTATE_CONJUGATE) {
     if (s->m == 0) return merge_generic(s, nullptr, o, st);
-    return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, sorted_input, st)
-                                  : conjugate_t<float>(s, P, theta, o, sorted_input, st);
+    return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, sorted_input, false, st)
+                                  : conjugate_t<float>(s, P, theta, o, sorted_input, false, st);
+  }
+  if (sorted_input && s->m > 0) {
+    // the product with cos(theta) I - i sin(theta) P: the products I Q_t are
+    // the input strings, already in key order, so only the m strings P Q_t
+    // are sorted and the two lists merged, as in a conjugation step
+    return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, true, true, st)
+                                  : conjugate_t<float>(s, P, theta, o, true, true, st);
   }
   paulisum* R = rotation_sum(s, P, theta, st);
   paulisum* r = nullptr;
