@@ -111,15 +111,26 @@ struct Acc<kPlain, TV> {
 
 template <>
 struct Acc<kComp, float> {
+  // mass = sum of |term|; after begin() it is formed only when a second term
+  // comes (lazy), since a one-term segment cannot cancel for tau <= 1
   float sr, er, si, ei, mass;
-  __device__ __forceinline__ void zero() { sr = er = si = ei = mass = 0.0f; }
+  bool lazy;
+  __device__ __forceinline__ void zero() {
+    sr = er = si = ei = mass = 0.0f;
+    lazy = false;
+  }
   __device__ __forceinline__ void begin(float r, float i) {
     sr = r;
     si = i;
     er = ei = 0.0f;
-    mass = hypotf(r, i);
+    lazy = true;  // mass would be hypotf(r, i)
   }
+  __device__ __forceinline__ float mass_now() const { return lazy ? hypotf(sr, si) : mass; }
   __device__ __forceinline__ void add(float r, float i) {
+    if (lazy) {
+      mass = hypotf(sr, si);  // sr, si still hold the first term
+      lazy = false;
+    }
     float s, e;
     two_sum(sr, r, s, e);
     sr = s;
@@ -131,6 +142,7 @@ struct Acc<kComp, float> {
   }
   // adds another partial sum (its rounding errors included)
   __device__ __forceinline__ void add(const Acc& o) {
+    const float m0 = mass_now(), m1 = o.mass_now();
     float s, e;
     two_sum(sr, o.sr, s, e);
     sr = s;
@@ -138,13 +150,16 @@ struct Acc<kComp, float> {
     two_sum(si, o.si, s, e);
     si = s;
     ei = ei + (o.ei + e);
-    mass = mass + o.mass;
+    mass = m0 + m1;
+    lazy = false;
   }
   __device__ __forceinline__ float value_re() const { return sr + er; }
   __device__ __forceinline__ float value_im() const { return si + ei; }
   __device__ __forceinline__ bool cancels(double tau) const {
+    // one term: |v| < tau |v| only for tau > 1
+    if (lazy && !(tau > 1.0)) return false;
     return static_cast<double>(hypotf(value_re(), value_im())) <
-           tau * static_cast<double>(mass);
+           tau * static_cast<double>(mass_now());
   }
 };
 
