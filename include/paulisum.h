@@ -237,8 +237,11 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
  * memory) and the angle theta[t] (host memory); R_t = cos(theta_t) I
  * - i sin(theta_t) P_t.
  *   PAULI_ROTATE_PRODUCT:   S <- merge(R_t * S), every term multiplied on
- *                           the left (the fused outer product with the 2-term
- *                           sum R_t).
+ *                           the left by the 2-term sum R_t (a fused outer
+ *                           product on the first step; on a state already in
+ *                           key order, the products I Q keep that order and
+ *                           only the products P_t Q are sorted before the
+ *                           merge).
  *   PAULI_ROTATE_CONJUGATE: terms commuting with P_t are kept; each
  *                           anticommuting term Q becomes
  *                           cos(theta_t) Q - i sin(theta_t) P_t Q; then merge.
