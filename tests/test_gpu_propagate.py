@@ -167,3 +167,18 @@ def test_conjugation_generators_in_few_words(n):
     ref = O.propagate(_osum(S), x, z, th, mode=O.CONJUGATE)
     parity.assert_merged_fp64(g, ref)
     parity.assert_sorted_by_key(g)
+
+
+def test_product_steps_compensated():
+    """The literal product in the precision form (the steps after the first
+    go through the merge path in FP32 with compensated sums) against the
+    FP64 oracle."""
+    S = _state(2000)
+    th, x, z = _rots(4)
+    g = pl.propagate(pl.PauliSum.from_dict(S), x, z, th, rotate_mode=pl.ROTATE_PRODUCT,
+                     mode=pl.COMPENSATED, drop_abs=1e-10).export()
+    ref = O.propagate(_osum(S), x, z, th, mode=O.PRODUCT, drop_abs=1e-10)
+    assert g["coef"].dtype == np.complex64
+    err = parity.max_rel_err_after_drop(g, ref)
+    print("4 product steps, compensated: max rel err %.3e" % err)
+    assert err <= 1e-5
