@@ -213,6 +213,43 @@ void add_value(Acc& acc, int k, double re, double im) {
   acc.mass += std::hypot(re, im);
 }
 
+// Truncation, Section III-B: is the modulus of re + i im strictly below t?
+// Decided exactly: |c| < t  <=>  re^2 + im^2 < t^2.  Let a >= b be |re|, |im|.
+// If a >= t the answer is no.  Otherwise multiply a, b and t by 2^-e with
+// e = ilogb(t) (exact for every value that matters below), so that t lies in
+// [1, 2).  If a < 2^-52, a^2 + b^2 < 2^-103 < t^2.  If b < 2^-52 the answer
+// is yes too: t and a < t are doubles, so t^2 - a^2 = (t - a)(t + a) >=
+// 2^-52 a > b a >= b^2.  In every remaining case the three squares are
+// above 2^-104, TwoProduct splits each into two doubles exactly, and the
+// exact sum of the six pieces is accumulated in an expansion; its largest
+// component carries the sign.
+bool below_threshold(double re, double im, double t) {
+  if (!(t > 0.0)) return false;
+  double a = std::fabs(re), b = std::fabs(im);
+  if (b > a) std::swap(a, b);
+  if (!(a < t)) return false;
+  const int e = std::ilogb(t);
+  a = std::ldexp(a, -e);
+  b = std::ldexp(b, -e);
+  t = std::ldexp(t, -e);
+  const double small = std::ldexp(1.0, -52);
+  if (a < small || b < small) return true;
+  Expansion d;
+  double p, q;
+  two_prod(a, a, p, q);
+  exp_add(d, p);
+  exp_add(d, q);
+  two_prod(b, b, p, q);
+  exp_add(d, p);
+  exp_add(d, q);
+  two_prod(t, t, p, q);
+  exp_add(d, -p);
+  exp_add(d, -q);
+  for (size_t k = d.p.size(); k > 0; --k)  // the largest nonzero component
+    if (d.p[k - 1] != 0.0) return d.p[k - 1] < 0.0;
+  return false;  // exactly |c| = t
+}
+
 struct Result {
   int n = 0;
   std::vector<std::string> keys;
@@ -226,7 +263,7 @@ Result* finish(int n, const std::map<std::string, Acc>& m, double drop_abs) {
   for (const auto& kv : m) {
     double re = exp_round(kv.second.re);
     double im = exp_round(kv.second.im);
-    if (drop_abs >= 0.0 && re * re + im * im < drop_abs * drop_abs) continue;
+    if (drop_abs >= 0.0 && below_threshold(re, im, drop_abs)) continue;
     r->keys.push_back(kv.first);
     r->coef.push_back(re);
     r->coef.push_back(im);
