@@ -163,6 +163,61 @@ struct Acc<kComp, float> {
   }
 };
 
+// -------------------------------------------------------------- truncation
+//
+// Section III-B removes a merged term whose modulus is strictly below the
+// threshold t.  below_threshold decides |re + i im| < t exactly, in integer
+// arithmetic on the significands (no square is rounded, so neither underflow
+// for tiny t nor rounding near |c| = t can flip the answer).  With
+// a = max(|re|, |im|) and b = min(|re|, |im|):
+//   a >= t            -> no;
+//   2a < t            -> yes (a^2 + b^2 <= 2 a^2 < t^2 / 2);
+//   otherwise t/2 <= a < t, so t and a are within one binade of each other:
+//   with t = T 2^E, a = A 2^E (common exponent E, T and A integers below
+//   2^54), |c| < t  <=>  b^2 < (T - A)(T + A) 2^(2E), and with b = B 2^F
+//   that is  B^2 2^(2F - 2E) < (T - A)(T + A),  where B^2 < 2^106 and the
+//   product is below 2^109: 128-bit integers hold both.  For
+//   X < D 2^k (k >= 0, D integer) the test is floor(X / 2^k) < D.
+__host__ __device__ __forceinline__ void dbl_split(double x, uint64_t& m, int& e) {
+  uint64_t u;
+  __builtin_memcpy(&u, &x, 8);
+  const int be = static_cast<int>((u >> 52) & 0x7FF);
+  m = u & ((uint64_t(1) << 52) - 1);
+  if (be == 0) {
+    e = -1074;  // subnormal or zero
+  } else {
+    m |= uint64_t(1) << 52;
+    e = be - 1075;
+  }
+}
+
+__host__ __device__ __forceinline__ bool below_threshold(double re, double im, double t) {
+  if (!(t > 0.0)) return false;
+  double a = re < 0.0 ? -re : re, b = im < 0.0 ? -im : im;
+  if (b > a) {
+    const double x = a;
+    a = b;
+    b = x;
+  }
+  if (!(a < t)) return false;           // also a NaN component: kept
+  if (t > 1.7976931348623157e308) return true;  // t = inf, a finite
+  if (a + a < t) return true;           // 2a is exact here (a < t / 2 <= max / 2)
+  uint64_t mt, ma, mb;
+  int et, ea, eb;
+  dbl_split(t, mt, et);
+  dbl_split(a, ma, ea);
+  const int e0 = et < ea ? et : ea;      // |et - ea| <= 1
+  const unsigned __int128 T = static_cast<unsigned __int128>(mt) << (et - e0);
+  const unsigned __int128 A = static_cast<unsigned __int128>(ma) << (ea - e0);
+  const unsigned __int128 D = (T - A) * (T + A);  // > 0 since a < t
+  if (b == 0.0) return true;
+  dbl_split(b, mb, eb);
+  const unsigned __int128 B2 = static_cast<unsigned __int128>(mb) * mb;
+  const int k = 2 * (e0 - eb);  // b^2 < D 2^(2 e0)  <=>  B^2 < D 2^k
+  if (k >= 0) return k >= 128 ? true : (B2 >> k) < D;
+  return (B2 << (-k)) < D;  // -k <= 4: b <= a
+}
+
 // ------------------------------------------------------------ phase rule
 //
 // Write each letter as L(x,z) = i^{xz} X^x Z^z (so L(1,1) = iXZ = Y, Table I

@@ -141,11 +141,12 @@ __global__ void k_count_kept(const uint32_t* __restrict__ keep, const uint32_t* 
   *nkept = U ? outidx[U - 1] + keep[U - 1] : 0u;
 }
 
+// drop < 0: every term is kept; otherwise the strict truncation |c| < drop
+// of Section III-B, decided exactly.
 template <typename T>
-__device__ __forceinline__ bool keep_value(cplx<T> c, double drop2) {
-  if (drop2 < 0.0) return true;
-  const double re = c.re, im = c.im;
-  return !(re * re + im * im < drop2);
+__device__ __forceinline__ bool keep_value(cplx<T> c, double drop) {
+  if (drop < 0.0) return true;
+  return !below_threshold(static_cast<double>(c.re), static_cast<double>(c.im), drop);
 }
 
 // FP64 value of record r (the re-merge of a cancelled segment).
@@ -161,7 +162,7 @@ __global__ void k_seg_reduce(Src src, const uint32_t* __restrict__ vals,
                              const cplx<TV>* __restrict__ v, const uint32_t* __restrict__ seg_start,
                              const uint32_t* __restrict__ nseg, cplx<TV>* __restrict__ coef,
                              uint32_t* __restrict__ keep, uint32_t* __restrict__ long_list,
-                             uint32_t* __restrict__ nlong, double drop2, double tau) {
+                             uint32_t* __restrict__ nlong, double drop, double tau) {
   const uint32_t U = *nseg;
   for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < U;
        u += (int64_t)gridDim.x * blockDim.x) {
@@ -184,7 +185,7 @@ __global__ void k_seg_reduce(Src src, const uint32_t* __restrict__ vals,
       c = cplx<TV>{static_cast<TV>(re), static_cast<TV>(im)};
     }
     coef[u] = c;
-    keep[u] = keep_value(c, drop2) ? 1u : 0u;
+    keep[u] = keep_value(c, drop) ? 1u : 0u;
   }
 }
 
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__(kBlock)
 k_seg_reduce_long(Src src, const uint32_t* __restrict__ vals, const cplx<TV>* __restrict__ v,
                   const uint32_t* __restrict__ seg_start, const uint32_t* __restrict__ long_list,
                   const uint32_t* __restrict__ nlong, cplx<TV>* __restrict__ coef,
-                  uint32_t* __restrict__ keep, double drop2, double tau) {
+                  uint32_t* __restrict__ keep, double drop, double tau) {
   __shared__ Acc<MODE, TV> s_acc[kBlock];
   __shared__ double s_re[kBlock], s_im[kBlock];
   const uint32_t L = *nlong;
@@ -231,7 +232,7 @@ k_seg_reduce_long(Src src, const uint32_t* __restrict__ vals, const cplx<TV>* __
     }
     if (threadIdx.x == 0) {
       coef[u] = c;
-      keep[u] = keep_value(c, drop2) ? 1u : 0u;
+      keep[u] = keep_value(c, drop) ? 1u : 0u;
     }
     __syncthreads();
   }
@@ -316,11 +317,11 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, uint6
   uint32_t* keep = segid;  // segid is dead after k_seg_starts
   DBuf long_buf(N * sizeof(uint32_t), s);
   uint32_t* long_list = long_buf.as<uint32_t>();
-  const double drop2 = o.drop_abs < 0.0 ? -1.0 : o.drop_abs * o.drop_abs;
+  const double drop = o.drop_abs < 0.0 ? -1.0 : o.drop_abs;  // threshold, not squared
   hipLaunchKernelGGL((k_seg_reduce<WT, TV, MODE, Src>), dim3(g), dim3(kBlock), 0, s, src, vals, v,
-                     seg_start, ctr + 1, coef, keep, long_list, ctr + 3, drop2, o.tau);
+                     seg_start, ctr + 1, coef, keep, long_list, ctr + 3, drop, o.tau);
   hipLaunchKernelGGL((k_seg_reduce_long<WT, TV, MODE, Src>), dim3(1024), dim3(kBlock), 0, s, src,
-                     vals, v, seg_start, long_list, ctr + 3, coef, keep, drop2, o.tau);
+                     vals, v, seg_start, long_list, ctr + 3, coef, keep, drop, o.tau);
   PAULI_HIP(hipGetLastError());
   sc_seg.reset();
   v_buf.reset();
@@ -443,21 +444,21 @@ constexpr int kTileC = kCompact * kRoundsC;
 
 template <typename T>
 __device__ __forceinline__ bool keep_term(const cplx<T>* __restrict__ c,
-                                          const uint8_t* __restrict__ ph, int64_t t, double drop2,
+                                          const uint8_t* __restrict__ ph, int64_t t, double drop,
                                           int marked) {
-  return !(marked && ph[t] != 0) && (drop2 < 0.0 || keep_value(c[t], drop2));
+  return !(marked && ph[t] != 0) && (drop < 0.0 || keep_value(c[t], drop));
 }
 
 // Kept terms of the wave's part of tile blockIdx.x.
 template <typename T>
 __device__ __forceinline__ uint32_t wave_kept(const cplx<T>* __restrict__ c,
                                               const uint8_t* __restrict__ ph, int64_t m,
-                                              double drop2, int marked, int64_t w0, int lane) {
+                                              double drop, int marked, int64_t w0, int lane) {
   uint32_t n = 0;
 #pragma unroll 4
   for (int r = 0; r < kRoundsC; ++r) {
     const int64_t t = w0 + r * 64 + lane;
-    n += static_cast<uint32_t>(__popcll(__ballot(t < m && keep_term(c, ph, t, drop2, marked))));
+    n += static_cast<uint32_t>(__popcll(__ballot(t < m && keep_term(c, ph, t, drop, marked))));
   }
   return n;
 }
@@ -465,11 +466,11 @@ __device__ __forceinline__ uint32_t wave_kept(const cplx<T>* __restrict__ c,
 template <typename T>
 __global__ void __launch_bounds__(kCompact)
 k_keep_count(const cplx<T>* __restrict__ c, const uint8_t* __restrict__ ph, int64_t m,
-             double drop2, int marked, uint32_t* __restrict__ bcount) {
+             double drop, int marked, uint32_t* __restrict__ bcount) {
   __shared__ uint32_t sw[kCompact / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t w0 = blockIdx.x * static_cast<int64_t>(kTileC) + wave * (64 * kRoundsC);
-  const uint32_t n = wave_kept(c, ph, m, drop2, marked, w0, lane);
+  const uint32_t n = wave_kept(c, ph, m, drop, marked, w0, lane);
   if (lane == 0) sw[wave] = n;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -484,7 +485,7 @@ template <typename T>
 __global__ void __launch_bounds__(kCompact)
 k_compact(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
           const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
-          const uint64_t* __restrict__ fp, int W, int64_t m, int64_t ld, double drop2, int marked,
+          const uint64_t* __restrict__ fp, int W, int64_t m, int64_t ld, double drop, int marked,
           const uint32_t* __restrict__ boff, uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
           uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp,
           int64_t ldo) {
@@ -493,7 +494,7 @@ k_compact(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t base = blockIdx.x * static_cast<int64_t>(kTileC);
   const int64_t w0 = base + wave * (64 * kRoundsC);
-  const uint32_t n = wave_kept(c, ph, m, drop2, marked, w0, lane);
+  const uint32_t n = wave_kept(c, ph, m, drop, marked, w0, lane);
   if (lane == 0) sw[wave] = n;
   __syncthreads();
   uint32_t o = 0, total = 0;
@@ -504,7 +505,7 @@ k_compact(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int r = 0; r < kRoundsC; ++r) {
     const int64_t t = w0 + r * 64 + lane;
-    const bool k = t < m && keep_term(c, ph, t, drop2, marked);
+    const bool k = t < m && keep_term(c, ph, t, drop, marked);
     const uint64_t bal = __ballot(k);
     if (k) s_pos[o + __popcll(bal & lt)] = static_cast<uint16_t>(t - base);
     o += static_cast<uint32_t>(__popcll(bal));
@@ -541,12 +542,12 @@ template <typename T>
 paulisum* drop_t(const paulisum* a, double drop_abs, bool marked, hipStream_t s) {
   const int64_t m = a->m;
   const int64_t nb = (m + kTileC - 1) / kTileC;
-  const double drop2 = drop_abs >= 0.0 ? drop_abs * drop_abs : -1.0;
+  const double drop = drop_abs >= 0.0 ? drop_abs : -1.0;  // threshold, not squared
   DBuf cnt((nb + 1) * 4, s), off((nb + 1) * 4, s), tot(4, s);
   DBuf work(scan_workspace_bytes(nb), s);
   const auto c = static_cast<const cplx<T>*>(a->coef);
   hipLaunchKernelGGL(k_keep_count<T>, dim3(static_cast<unsigned>(nb)), dim3(kCompact), 0, s, c,
-                     a->ph, m, drop2, marked ? 1 : 0, cnt.as<uint32_t>());
+                     a->ph, m, drop, marked ? 1 : 0, cnt.as<uint32_t>());
   scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), nb, tot.as<uint32_t>(), work.p, s);
   uint32_t kept = 0;
   PAULI_HIP(hipMemcpyAsync(&kept, tot.p, 4, hipMemcpyDeviceToHost, s));
@@ -554,7 +555,7 @@ paulisum* drop_t(const paulisum* a, double drop_abs, bool marked, hipStream_t s)
   paulisum* out = new_sum(a->n, kept, kept, a->dtype, s);
   if (kept > 0)
     hipLaunchKernelGGL(k_compact<T>, dim3(static_cast<unsigned>(nb)), dim3(kCompact), 0, s, a->X,
-                       a->Z, a->ph, c, a->fp, a->W, m, a->ld, drop2, marked ? 1 : 0,
+                       a->Z, a->ph, c, a->fp, a->W, m, a->ld, drop, marked ? 1 : 0,
                        off.as<uint32_t>(), out->X, out->Z, out->ph,
                        static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
   PAULI_HIP(hipGetLastError());

@@ -244,9 +244,34 @@ def test_zero_coefficients_kept_unless_dropped():
          "coef": np.array([1.5 + 0j, 1.5 + 0j])}
     g = pl.merge(_gsum(S)).export()
     assert g["x"].shape[0] == 1 and g["coef"][0] == 0
-    # the drop test is |c|^2 < t^2 in FP64 (as in the oracle), so t must be
-    # representable when squared
-    assert pl.merge(_gsum(S), drop_abs=1e-100).m == 0
+    # |c| < t is decided exactly: a zero sum lies below any positive
+    # threshold, also one whose square underflows
+    assert pl.merge(_gsum(S), drop_abs=1e-300).m == 0
+    assert pl.merge(_gsum(S), drop_abs=5e-324).m == 0
+    assert pl.merge(_gsum(S), drop_abs=0.0).m == 1
+
+
+def test_drop_is_exact():
+    """Section III-B truncation, |c| < t strictly, on exact ties, near ties,
+    subnormals and thresholds whose squares under- or overflow: the kept set
+    equals exact rational arithmetic and the oracle's."""
+    from tests.test_oracle_truncation import _cases, _exact_below
+    by_t = {}
+    for re, im, t in _cases():
+        by_t.setdefault(t, []).append((re, im))
+    ts = sorted(by_t)
+    ts = [t for k, t in enumerate(ts) if len(by_t[t]) > 1 or k % 12 == 0]
+    n = 40
+    for t in ts:
+        vals = by_t[t]
+        m = len(vals)
+        S = {"n": n, "x": np.arange(1, m + 1, dtype=np.uint64).reshape(m, 1),
+             "z": np.zeros((m, 1), np.uint64), "phase": np.zeros(m, np.uint8),
+             "coef": np.array([complex(re, im) for re, im in vals], np.complex128)}
+        got = {int(v) for v in pl.merge(_gsum(S), drop_abs=t).export()["x"][:, 0]}
+        ref = {int(v) for v in O.merge(_osum(S), drop_abs=t).x[:, 0]}
+        want = {u + 1 for u, (re, im) in enumerate(vals) if not _exact_below(re, im, t)}
+        assert got == want == ref, t
 
 
 def test_determinism():
