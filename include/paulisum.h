@@ -247,6 +247,10 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
  *                           cos(theta_t) Q - i sin(theta_t) P_t Q; then merge.
  * Every step ends with the merge of opts (mode, drop_abs, ...), so a
  * drop_abs >= 0 truncates after each step.  steps == 0 returns merge(s).
+ * In the compensated mode the state is carried between steps as
+ * float-float pairs (about 48 significant bits; products by TwoProduct,
+ * sums by TwoSum, cancelled segments re-merged in FP64 from the carried
+ * state), starting from merge(s), and only the output is rounded to C64.
  * s is not modified; *out is a new sum (C64 once a compensated step ran).
  * Each step synchronises the stream once per size it has to learn.
  * Errors: INVALID for a NULL argument, steps < 0, an unknown mode or a

@@ -79,7 +79,7 @@ void dfree(void* p, size_t bytes, hipStream_t s) {
   arena_free(p, s);
 }
 
-paulisum* new_sum(int n, int64_t m, int64_t ld, pauli_dtype_t dt, hipStream_t s) {
+paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s) {
   const int W = words_for(n);
   const size_t L = static_cast<size_t>(ld);
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -365,7 +365,7 @@ pauli_status_t paulisum_info(paulisum_t s, int32_t* n_qubits, int64_t* n_terms,
     check_sum(s, "s");
     if (n_qubits) *n_qubits = s->n;
     if (n_terms) *n_terms = s->m;
-    if (dtype) *dtype = s->dtype;
+    if (dtype) *dtype = static_cast<pauli_dtype_t>(s->dtype);
   });
 }
 
@@ -581,11 +581,25 @@ pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
     }
     paulisum* cur = s;
     try {
+      const bool ff = m.mode == PAULI_MERGE_COMPENSATED;
+      MergeArgs ms = m;
+      if (ff) {
+        // the precision form carries the state as float-float pairs from
+        // step to step; it starts as the merged input, in key order
+        MergeArgs m0 = m;
+        m0.mode = kModeFF;
+        m0.ff_out = 1;
+        m0.drop_abs = -1.0;
+        cur = merge_generic(s, nullptr, m0, st);
+        ms.mode = kModeFF;
+      }
       for (int32_t t = 0; t < steps; ++t) {
-        // after the first step the state is a merge's output, in key order
+        // after the first step (from the first, in the precision form) the
+        // state is a merge's output, in key order
+        ms.ff_out = t + 1 < steps ? 1 : 0;  // the last step writes C64
         paulisum* next = rotate_step(cur, p_x + static_cast<size_t>(t) * W,
-                                     p_z + static_cast<size_t>(t) * W, theta[t], rotate_mode, m,
-                                     t > 0, st);
+                                     p_z + static_cast<size_t>(t) * W, theta[t], rotate_mode, ms,
+                                     ff || t > 0, st);
         if (cur != s) free_sum(cur);
         cur = next;
       }

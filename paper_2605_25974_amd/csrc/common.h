@@ -163,6 +163,138 @@ struct Acc<kComp, float> {
   }
 };
 
+// ------------------------------------------------------------- float-float
+//
+// The state of a propagation loop in the precision form is carried from one
+// rotation step to the next as float-float pairs hi + lo (|lo| <= ulp(hi)/2,
+// Dekker 1971): a coefficient keeps about 48 significant bits while every
+// operation on it is an FP32 operation.  Rounding the state to FP32 after
+// each step would add about 2^-24 of relative error per step (eq. (5) is
+// applied 64 times in a row), which a float-float carry avoids.
+//   TwoProduct: a*b = p + e exactly, e = fma(a, b, -p) (Ogita, Rump and
+//               Oishi 2005).
+//   FastTwoSum: for |a| >= |b|, a + b = s + e exactly, e = b - (s - a).
+// kFF is the accumulation policy of a merge whose records carry
+// float-float values (kept as FP32 sum and FP32 error term, as in kComp,
+// with the low parts added to the error term).
+constexpr int kFF = 2;
+
+struct ff {
+  float hi, lo;
+};
+
+__host__ __device__ __forceinline__ ff operator-(ff a) { return {-a.hi, -a.lo}; }
+
+__device__ __forceinline__ ff fast_two_sum(float a, float b) {
+  const float s = a + b;
+  return {s, b - (s - a)};
+}
+
+// (a.hi + a.lo)(b.hi + b.lo) to float-float: the product of the high parts
+// exactly, the two cross terms in FP32, the product of the low parts
+// (below 2^-48 relative) left out.
+__device__ __forceinline__ ff ff_mul(ff a, ff b) {
+  const float p = a.hi * b.hi;
+  const float e = fmaf(a.hi, b.hi, -p);
+  const float c = a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p, e + c);
+}
+
+// Conversions between the coefficient types (double, float, float-float).
+template <typename TO>
+struct conv_to;
+template <>
+struct conv_to<double> {
+  __device__ __forceinline__ static double of(double x) { return x; }
+  __device__ __forceinline__ static double of(float x) { return static_cast<double>(x); }
+  __device__ __forceinline__ static double of(ff x) {
+    return static_cast<double>(x.hi) + static_cast<double>(x.lo);
+  }
+};
+template <>
+struct conv_to<float> {
+  __device__ __forceinline__ static float of(double x) { return static_cast<float>(x); }
+  __device__ __forceinline__ static float of(float x) { return x; }
+  __device__ __forceinline__ static float of(ff x) {
+    return static_cast<float>(static_cast<double>(x.hi) + static_cast<double>(x.lo));
+  }
+};
+template <>
+struct conv_to<ff> {
+  __device__ __forceinline__ static ff of(double x) {
+    const float h = static_cast<float>(x);
+    return {h, static_cast<float>(x - static_cast<double>(h))};
+  }
+  __device__ __forceinline__ static ff of(float x) { return {x, 0.0f}; }
+  __device__ __forceinline__ static ff of(ff x) { return x; }
+};
+template <typename TO, typename TI>
+__device__ __forceinline__ TO conv(TI x) {
+  return conv_to<TO>::of(x);
+}
+template <typename TO, typename TI>
+__device__ __forceinline__ cplx<TO> convc(cplx<TI> v) {
+  return {conv<TO>(v.re), conv<TO>(v.im)};
+}
+
+template <>
+struct Acc<kFF, ff> {
+  float sr, er, si, ei, mass;
+  bool lazy;  // as in Acc<kComp, float>: the mass is formed at the second term
+  __device__ __forceinline__ void zero() {
+    sr = er = si = ei = mass = 0.0f;
+    lazy = false;
+  }
+  __device__ __forceinline__ void begin(ff r, ff i) {
+    sr = r.hi;
+    er = r.lo;
+    si = i.hi;
+    ei = i.lo;
+    lazy = true;
+  }
+  __device__ __forceinline__ float mass_now() const { return lazy ? hypotf(sr, si) : mass; }
+  __device__ __forceinline__ void add(ff r, ff i) {
+    if (lazy) {
+      mass = hypotf(sr, si);
+      lazy = false;
+    }
+    float s, e;
+    two_sum(sr, r.hi, s, e);
+    sr = s;
+    er = er + (e + r.lo);
+    two_sum(si, i.hi, s, e);
+    si = s;
+    ei = ei + (e + i.lo);
+    mass = mass + hypotf(r.hi, i.hi);
+  }
+  __device__ __forceinline__ void add(const Acc& o) {
+    const float m0 = mass_now(), m1 = o.mass_now();
+    float s, e;
+    two_sum(sr, o.sr, s, e);
+    sr = s;
+    er = er + (o.er + e);
+    two_sum(si, o.si, s, e);
+    si = s;
+    ei = ei + (o.ei + e);
+    mass = m0 + m1;
+    lazy = false;
+  }
+  __device__ __forceinline__ ff value_re() const { return fast_two_sum_any(sr, er); }
+  __device__ __forceinline__ ff value_im() const { return fast_two_sum_any(si, ei); }
+  __device__ __forceinline__ bool cancels(double tau) const {
+    if (lazy && !(tau > 1.0)) return false;
+    return static_cast<double>(hypotf(sr + er, si + ei)) < tau * static_cast<double>(mass_now());
+  }
+
+ private:
+  // s + e renormalised; |e| may exceed |s| after cancellation, so TwoSum
+  __device__ __forceinline__ static ff fast_two_sum_any(float s, float e) {
+    float h, l;
+    two_sum(s, e, h, l);
+    return {h, l};
+  }
+};
+
 // -------------------------------------------------------------- truncation
 //
 // Section III-B removes a merged term whose modulus is strictly below the

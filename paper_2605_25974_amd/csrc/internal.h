@@ -18,7 +18,7 @@ struct paulisum {
   int32_t n = 0, W = 0;
   int64_t m = 0;   // number of terms
   int64_t ld = 0;  // column length (capacity) of every SoA array
-  pauli_dtype_t dtype = PAULI_C128;
+  int32_t dtype = PAULI_C128;  // pauli_dtype_t, or kDtypeFF inside a propagation loop
   int device = 0;
   void* block = nullptr;  // one allocation backing every array below
   size_t block_bytes = 0;
@@ -75,10 +75,14 @@ struct DBuf {
 };
 
 inline int words_for(int n) { return (n + 63) / 64; }
-inline size_t coef_bytes(pauli_dtype_t t) { return t == PAULI_C128 ? 16 : 8; }
+// Internal coefficient type of a propagation state in the precision form:
+// per term {re.hi, re.lo, im.hi, im.lo} as floats (float-float pairs).  It
+// never leaves the library: the last step of a loop writes C64.
+constexpr int32_t kDtypeFF = 2;
+inline size_t coef_bytes(int32_t t) { return t == PAULI_C64 ? 8 : 16; }
 
 // Allocates a container with capacity ld (>= m) on the current device.
-paulisum* new_sum(int n, int64_t m, int64_t ld, pauli_dtype_t dt, hipStream_t s);
+paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s);
 void free_sum(paulisum* p);
 
 // ---------------------------------------------------------------- profiling
@@ -144,8 +148,12 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                            uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s);
 
 // k_merge.hip
+// Internal merge mode: the precision form on float-float record values (a
+// propagation state carried between steps); the public modes are 0 and 1.
+constexpr int kModeFF = 2;
 struct MergeArgs {
   int mode = PAULI_MERGE_PLAIN;
+  int ff_out = 1;  // kModeFF: 1 writes a float-float sum, 0 a C64 sum
   double drop_abs = -1.0;
   double tau = 1e-3;
   int key_bits = 64;

@@ -146,7 +146,7 @@ __global__ void k_count_kept(const uint32_t* __restrict__ keep, const uint32_t* 
 template <typename T>
 __device__ __forceinline__ bool keep_value(cplx<T> c, double drop) {
   if (drop < 0.0) return true;
-  return !below_threshold(static_cast<double>(c.re), static_cast<double>(c.im), drop);
+  return !below_threshold(conv<double>(c.re), conv<double>(c.im), drop);
 }
 
 // FP64 value of record r (the re-merge of a cancelled segment).
@@ -182,7 +182,7 @@ __global__ void k_seg_reduce(Src src, const uint32_t* __restrict__ vals,
         re = re + x.re;
         im = im + x.im;
       }
-      c = cplx<TV>{static_cast<TV>(re), static_cast<TV>(im)};
+      c = cplx<TV>{conv<TV>(re), conv<TV>(im)};
     }
     coef[u] = c;
     keep[u] = keep_value(c, drop) ? 1u : 0u;
@@ -228,7 +228,7 @@ k_seg_reduce_long(Src src, const uint32_t* __restrict__ vals, const cplx<TV>* __
         tr = tr + s_re[h];
         ti = ti + s_im[h];
       }
-      c = cplx<TV>{static_cast<TV>(tr), static_cast<TV>(ti)};
+      c = cplx<TV>{conv<TV>(tr), conv<TV>(ti)};
     }
     if (threadIdx.x == 0) {
       coef[u] = c;
@@ -238,13 +238,13 @@ k_seg_reduce_long(Src src, const uint32_t* __restrict__ vals, const cplx<TV>* __
   }
 }
 
-template <int WT, typename T, typename Src>
+template <int WT, typename T, typename TO, typename Src>
 __global__ void __launch_bounds__(kBlock)
 k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ seg_start,
                const uint32_t* __restrict__ nseg, const uint32_t* __restrict__ keep,
                const uint32_t* __restrict__ outidx, const cplx<T>* __restrict__ coef,
                uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ, uint8_t* __restrict__ Oph,
-               cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp, int64_t ldo) {
+               cplx<TO>* __restrict__ Oc, uint64_t* __restrict__ Ofp, int64_t ldo) {
   const uint32_t U = *nseg;
   uint64_t w[2 * WT];
   for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < U;
@@ -260,7 +260,7 @@ k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __res
       OZ[q * ldo + o] = w[src.nw + q];
     }
     Oph[o] = 0;
-    Oc[o] = coef[u];
+    Oc[o] = convc<TO>(coef[u]);
     Ofp[o] = src.fp(id);
   }
 }
@@ -268,11 +268,15 @@ k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __res
 // -------------------------------------------------------------- pipeline
 
 // presorted: the records are already in key order (equal keys adjacent).
+// MODE kFF (record values in float-float) writes a float-float sum when
+// o.ff_out is set, else a C64 sum rounded from it.
 template <int WT, typename T, int MODE, typename Src>
-paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, uint64_t* keys,
+paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* keys,
                        uint32_t* vals, const MergeArgs& o, hipStream_t s, bool presorted = false) {
-  using TV = typename std::conditional<MODE == kComp, float, T>::type;
+  using TV = typename std::conditional<MODE == kComp, float,
+                                       typename std::conditional<MODE == kFF, ff, T>::type>::type;
   if (MODE == kComp) dt = PAULI_C64;
+  if (MODE == kFF) dt = o.ff_out ? kDtypeFF : PAULI_C64;
   DBuf keys_alt, vals_alt;
   if (!presorted) {
     keys_alt = DBuf(N * sizeof(uint64_t), s);
@@ -342,10 +346,15 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, pauli_dtype_t dt, uint6
 
   paulisum* out = new_sum(n, U, U, dt, s);
   if (U > 0) {
-    StageScope sc_w(PAULI_STAGE_WRITE, s, U * (16.0 * src.nw + sizeof(cplx<TV>) + 1 + 8));
-    hipLaunchKernelGGL((k_write_output<WT, TV, Src>), dim3(grid_for(nseg)), dim3(kBlock), 0, s, src,
-                       vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z, out->ph,
-                       static_cast<cplx<TV>*>(out->coef), out->fp, out->ld);
+    StageScope sc_w(PAULI_STAGE_WRITE, s, U * (16.0 * src.nw + coef_bytes(dt) + 1 + 8));
+    if (MODE == kFF && !o.ff_out)
+      hipLaunchKernelGGL((k_write_output<WT, TV, float, Src>), dim3(grid_for(nseg)), dim3(kBlock),
+                         0, s, src, vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z,
+                         out->ph, static_cast<cplx<float>*>(out->coef), out->fp, out->ld);
+    else
+      hipLaunchKernelGGL((k_write_output<WT, TV, TV, Src>), dim3(grid_for(nseg)), dim3(kBlock), 0,
+                         s, src, vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z,
+                         out->ph, static_cast<cplx<TV>*>(out->coef), out->fp, out->ld);
     PAULI_HIP(hipGetLastError());
   }
   return out;
@@ -362,6 +371,9 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                        keys.as<uint64_t>(), vals.as<uint32_t>());
     PAULI_HIP(hipGetLastError());
     TermSrc<WT, T> src{a->X, a->Z, a->ph, static_cast<const cplx<T>*>(a->coef), a->fp, a->ld, a->W};
+    if (o.mode == kModeFF)
+      return run_pipeline<WT, T, kFF>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
+                                       vals.as<uint32_t>(), o, s);
     return o.mode == PAULI_MERGE_COMPENSATED
                ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
                                             vals.as<uint32_t>(), o, s)
@@ -388,6 +400,34 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                                           vals.as<uint32_t>(), o, s)
              : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
                                            vals.as<uint32_t>(), o, s);
+}
+
+// merge(a) of a float-float state (the precision form's carried state).
+template <int WT>
+paulisum* merge_ff_t(const paulisum* a, const MergeArgs& o, hipStream_t s) {
+  const int64_t N = a->m;
+  DBuf keys(N * sizeof(uint64_t), s), vals(N * sizeof(uint32_t), s);
+  StageScope sc(PAULI_STAGE_PREP, s, N * 20.0);
+  hipLaunchKernelGGL(k_term_records, dim3(grid_for(N)), dim3(kBlock), 0, s, a->fp, N,
+                     64 - o.key_bits, keys.as<uint64_t>(), vals.as<uint32_t>());
+  PAULI_HIP(hipGetLastError());
+  TermSrc<WT, ff> src{a->X, a->Z, a->ph, static_cast<const cplx<ff>*>(a->coef), a->fp, a->ld, a->W};
+  return run_pipeline<WT, ff, kFF>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
+                                   vals.as<uint32_t>(), o, s);
+}
+
+paulisum* merge_ff(const paulisum* a, const MergeArgs& o, hipStream_t s) {
+  switch (a->W) {
+    case 1: return merge_ff_t<1>(a, o, s);
+    case 2: return merge_ff_t<2>(a, o, s);
+    case 3: return merge_ff_t<3>(a, o, s);
+    case 4: return merge_ff_t<4>(a, o, s);
+    case 5: return merge_ff_t<5>(a, o, s);
+    case 6: return merge_ff_t<6>(a, o, s);
+    case 7: return merge_ff_t<7>(a, o, s);
+    case 8: return merge_ff_t<8>(a, o, s);
+    default: return merge_ff_t<kMaxWords>(a, o, s);
+  }
 }
 
 // merge(a) from records (key, term index) of a that are already in key order.
@@ -587,17 +627,20 @@ paulisum* merge_rotated_t(const paulisum* a, const RotString& P, double theta,
   src.nw = a->W;
   src.py = P.y;
   src.pfp = P.fp;
-  src.co = static_cast<T>(std::cos(theta));
-  src.si = static_cast<T>(std::sin(theta));
   src.smask = 0;
   for (int q = 0; q < WT; ++q) {
     src.px[q] = q < a->W ? P.x[q] : 0ull;
     src.pz[q] = q < a->W ? P.z[q] : 0ull;
     if (src.px[q] | src.pz[q]) src.smask |= 1u << q;
   }
-  return o.mode == PAULI_MERGE_COMPENSATED
-             ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys, vals, o, s, true)
-             : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s, true);
+  src.co = RotScale::of(std::cos(theta));
+  src.si = RotScale::of(std::sin(theta));
+  // a float-float state (the precision form) merges in float-float; a
+  // stored FP64 or FP32 state in its own precision
+  if constexpr (std::is_same<T, ff>::value)
+    return run_pipeline<WT, T, kFF>(src, a->n, N, a->dtype, keys, vals, o, s, true);
+  else
+    return run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s, true);
 }
 
 template <typename T>
@@ -776,7 +819,14 @@ paulisum* commutator_filtered(const paulisum* a, const paulisum* b, const MergeA
 paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
                         const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
                         const MergeArgs& o, hipStream_t st) {
-  if (N == 0) return new_sum(s->n, 0, 0, o.mode == PAULI_MERGE_COMPENSATED ? PAULI_C64 : s->dtype, st);
+  if (s->dtype == kDtypeFF) {
+    if (o.mode != kModeFF) fail(PAULI_ERR_INVALID, "a float-float state needs its own merge mode");
+    if (N == 0) return new_sum(s->n, 0, 0, o.ff_out ? kDtypeFF : PAULI_C64, st);
+    return merge_rotated_w<ff>(s, P, theta, cnt, keys, vals, N, o, st);
+  }
+  if (o.mode != PAULI_MERGE_PLAIN)
+    fail(PAULI_ERR_INVALID, "a rotation step on a stored FP64/FP32 state merges in its precision");
+  if (N == 0) return new_sum(s->n, 0, 0, s->dtype, st);
   if (s->dtype == PAULI_C128) return merge_rotated_w<double>(s, P, theta, cnt, keys, vals, N, o, st);
   return merge_rotated_w<float>(s, P, theta, cnt, keys, vals, N, o, st);
 }
@@ -789,6 +839,13 @@ paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals
 }
 
 paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+  if (a->dtype == kDtypeFF) {
+    if (b != nullptr || o.mode != kModeFF)
+      fail(PAULI_ERR_INVALID, "a float-float state is only merged on its own");
+    return merge_ff(a, o, s);
+  }
+  if (o.mode == kModeFF && b != nullptr)
+    fail(PAULI_ERR_INVALID, "the float-float merge takes one stored sum");
   if (a->dtype == PAULI_C128) return merge_w<double>(a, b, o, s);
   return merge_w<float>(a, b, o, s);
 }

@@ -9,6 +9,7 @@
 //                     written by one streaming kernel, then merged.
 // Both end with the merge options' truncation.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -202,6 +203,11 @@ __global__ void k_rot_all(int64_t m, uint32_t* __restrict__ cnt) {
     cnt[t] = 2u;
 }
 
+template <typename T>
+paulisum* conjugate_stored(const paulisum* s, const RotString& P, double theta,
+                           const MergeArgs& o, uint32_t M2, const DBuf& cnt, const DBuf& off,
+                           unsigned g, hipStream_t st);
+
 // One rotation step on the records 2t (Q_t, times cos theta where cnt[t] is
 // 2) and 2t + 1 (-i sin theta P Q_t, where cnt[t] is 2).  The conjugation
 // P-rotation keeps the terms that commute with P as they are (cnt[t] = 1);
@@ -259,6 +265,18 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
                          vals.as<uint32_t>(), M2, o, st);
   }
   // input in any order: store the conjugated sum and merge it
+  if constexpr (std::is_same<T, ff>::value) {
+    fail(PAULI_ERR_OVERFLOW, "a float-float state step needs the sorted path (< 2^31 records)");
+  } else {
+    return conjugate_stored<T>(s, P, theta, o, M2, cnt, off, g, st);
+  }
+}
+
+template <typename T>
+paulisum* conjugate_stored(const paulisum* s, const RotString& P, double theta,
+                           const MergeArgs& o, uint32_t M2, const DBuf& cnt, const DBuf& off,
+                           unsigned g, hipStream_t st) {
+  const int64_t m = s->m;
   paulisum* mat = new_sum(s->n, M2, M2, s->dtype, st);
   paulisum* r = nullptr;
   try {
@@ -317,12 +335,17 @@ paulisum* rotation_sum(const paulisum* s, const RotString& P, double theta, hipS
 paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
                       int mode, const MergeArgs& o, bool sorted_input, hipStream_t st) {
   const RotString P = rot_string(s->n, px, pz);
+  if (s->m == 0) return merge_generic(s, nullptr, o, st);  // an empty sum stays empty
+  if (s->dtype == kDtypeFF) {
+    // the precision form's float-float state, in key order
+    if (!sorted_input) fail(PAULI_ERR_INVALID, "a float-float state must be in key order");
+    return conjugate_t<ff>(s, P, theta, o, true, mode == PAULI_ROTATE_PRODUCT, st);
+  }
   if (mode == PAULI_ROTATE_CONJUGATE) {
-    if (s->m == 0) return merge_generic(s, nullptr, o, st);
     return s->dtype == PAULI_C128 ? conjugate_t<double>(s, P, theta, o, sorted_input, false, st)
                                   : conjugate_t<float>(s, P, theta, o, sorted_input, false, st);
   }
-  if (sorted_input && s->m > 0) {
+  if (sorted_input) {
     // the product with cos(theta) I - i sin(theta) P: the products I Q_t are
     // the input strings, already in key order, so only the m strings P Q_t
     // are sorted and the two lists merged, as in a conjugation step
@@ -332,7 +355,7 @@ paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz,
   paulisum* R = rotation_sum(s, P, theta, st);
   paulisum* r = nullptr;
   try {
-    if (s->m > 0) r = fused_bucket(R, s, o, st);
+    r = fused_bucket(R, s, o, st);
     if (!r) r = merge_generic(R, s, o, st);
   } catch (...) {
     free_sum(R);

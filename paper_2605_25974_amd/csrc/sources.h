@@ -2,6 +2,8 @@
 // its packed string, its value i^k * c and its fingerprint.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace pauli {
@@ -103,25 +105,58 @@ struct TermSrc {
   template <typename TV = T>
   __device__ __forceinline__ cplx<TV> term(uint32_t id, uint64_t* w) const {
     string(id, w);
-    const cplx<T> v = c[id];
-    return rot_ik(ph[id], cplx<TV>{static_cast<TV>(v.re), static_cast<TV>(v.im)});
+    return rot_ik(ph[id], convc<TV>(c[id]));
   }
   template <typename TV = T>
   __device__ __forceinline__ cplx<TV> value(uint32_t id) const {
-    const cplx<T> v = c[id];
-    return rot_ik(ph[id], cplx<TV>{static_cast<TV>(v.re), static_cast<TV>(v.im)});
+    return rot_ik(ph[id], convc<TV>(c[id]));
   }
   __device__ __forceinline__ uint64_t xword(uint32_t id, int q) const { return X[q * ld + id]; }
   __device__ __forceinline__ uint64_t zword(uint32_t id, int q) const { return Z[q * ld + id]; }
   __device__ __forceinline__ uint64_t fp(uint32_t id) const { return f[id]; }
 };
 
+// A real factor (cos theta or sin theta) in every precision a rotation
+// step uses.
+struct RotScale {
+  double d;
+  float f;
+  ff x;  // the double as float-float
+  static RotScale of(double v) {
+    RotScale r;
+    r.d = v;
+    r.f = static_cast<float>(v);
+    r.x.hi = r.f;
+    r.x.lo = static_cast<float>(v - static_cast<double>(r.f));
+    return r;
+  }
+};
+
+// c * factor in the state's own precision: FP64, FP32 (a C64 state in the
+// plain form) or float-float (the precision form's carried state).
+__device__ __forceinline__ double scale_in(double c, const RotScale& k) { return c * k.d; }
+__device__ __forceinline__ float scale_in(float c, const RotScale& k) { return c * k.f; }
+__device__ __forceinline__ ff scale_in(ff c, const RotScale& k) { return ff_mul(c, k.x); }
+
+// c * factor as a TV value.  In the state's precision when TV is it; an FP64
+// value (the re-merge of a cancelled segment) is formed in FP64 from the
+// state's value and the FP64 factor.
+template <typename TV, typename T>
+__device__ __forceinline__ cplx<TV> scaled(cplx<T> c, const RotScale& k) {
+  if constexpr (std::is_same<TV, double>::value && !std::is_same<T, double>::value) {
+    return {conv<double>(c.re) * k.d, conv<double>(c.im) * k.d};
+  } else {
+    return convc<TV>(cplx<T>{scale_in(c.re, k), scale_in(c.im, k)});
+  }
+}
+
 // The conjugated sum of a rotation step (Section III-B, eq. (5)), not
 // stored: record 2t is input term t, its coefficient times cos(theta) when
 // Q_t anticommutes with P (cnt[t] == 2); record 2t + 1 is the new term
 // -i sin(theta) P Q_t of an anticommuting Q_t, with the phase of the product
 // P Q_t (Section III-A) and the fingerprint fp(P) ^ fp(Q_t).  The values are
-// formed in T and then converted, as a stored copy of them would be.
+// formed in the state's precision T and then converted, as a stored copy of
+// them would be; FP64 values of a float-float state are formed in FP64.
 template <int WT, typename T>
 struct RotSrc {
   const uint64_t* X;
@@ -134,7 +169,7 @@ struct RotSrc {
   int nw;
   int py;
   uint64_t pfp;
-  T co, si;
+  RotScale co, si;
   uint32_t smask;  // bit q: P has a letter in word q
   uint64_t px[WT], pz[WT];
 
@@ -154,10 +189,8 @@ struct RotSrc {
   __device__ __forceinline__ cplx<TV> value(uint32_t id) const {
     const uint32_t t = id >> 1;
     const cplx<T> v = c[t];
-    if ((id & 1u) == 0) {
-      const cplx<T> u = cnt[t] == 2 ? cplx<T>{v.re * co, v.im * co} : v;
-      return rot_ik(ph[t], cplx<TV>{static_cast<TV>(u.re), static_cast<TV>(u.im)});
-    }
+    if ((id & 1u) == 0)
+      return rot_ik(ph[t], cnt[t] == 2 ? scaled<TV>(v, co) : convc<TV>(v));
     int k = py;
 #pragma unroll
     for (int q = 0; q < WT; ++q) {
@@ -167,8 +200,7 @@ struct RotSrc {
       const uint64_t x3 = px[q] ^ xq, z3 = pz[q] ^ zq;
       k += popc64(xq & zq) + 2 * popc64(pz[q] & xq) - popc64(x3 & z3);
     }
-    const cplx<T> u{v.re * si, v.im * si};
-    return rot_ik((ph[t] + k + 3) & 3, cplx<TV>{static_cast<TV>(u.re), static_cast<TV>(u.im)});
+    return rot_ik((ph[t] + k + 3) & 3, scaled<TV>(v, si));
   }
   __device__ __forceinline__ uint64_t xword(uint32_t id, int q) const {
     return X[q * ld + (id >> 1)] ^ ((id & 1u) ? px[q] : 0ull);
