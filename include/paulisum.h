@@ -149,6 +149,30 @@ pauli_status_t pauli_outer_product(paulisum_t a, paulisum_t b, paulisum_t* out, 
 pauli_status_t pauli_merge(paulisum_t s, const pauli_merge_opts_t* opts, paulisum_t* out,
                            void* stream);
 
+/* pauli_merge_into: pauli_merge for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The call allocates nothing: its temporaries live in a
+ * fixed device scratch array of 128 MiB that the library holds on each
+ * device it runs on until the process ends, and the result is written to
+ * arrays the caller passes (device memory, stream-ordered):
+ *   out_x, out_z   [W][out_ld] uint64: word w of term t at [w * out_ld + t]
+ *   out_phase      [out_ld] uint8 (written 0)
+ *   out_coef       [out_ld] interleaved (re, im): s's dtype in the plain
+ *                  mode, C64 in the compensated mode
+ *   out_fp         [out_ld] uint64 fingerprints
+ *   out_m          host: the number of merged terms written
+ * The result is merge(s) as pauli_merge defines it (same terms, same order,
+ * same values).  Limits: |s| <= 2^20 terms; CAPACITY if |s| is larger, if
+ * the merged terms exceed out_ld (out_ld >= |s| always suffices) or if the
+ * scratch array is exhausted; then nothing is written to *out_m.  Every call
+ * on one device shares that device's scratch array: calls that overlap on
+ * one device (other threads, or other streams in flight) race and must be
+ * serialised by the caller.  Synchronises the stream once.  Errors as
+ * pauli_merge, plus INVALID for a NULL output array or out_ld < 1. */
+pauli_status_t pauli_merge_into(paulisum_t s, const pauli_merge_opts_t* opts, uint64_t* out_x,
+                                uint64_t* out_z, uint8_t* out_phase, void* out_coef,
+                                uint64_t* out_fp, int64_t out_ld, int64_t* out_m, void* stream);
+
 /* pauli_outer_product_merged: merge(outer_product(a, b)) without storing
  * the |a|*|b| unmerged products.  Same output definition as pauli_merge.
  * Errors as pauli_outer_product. */

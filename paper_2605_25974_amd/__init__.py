@@ -30,6 +30,7 @@ EXPORTS = (
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
     "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford", "pauli_sort_lex",
+    "pauli_merge_into",
 )
 STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford", "lex",
           "filter")
@@ -93,6 +94,9 @@ def lib():
     L.pauli_outer_product.argtypes = [_vp, _vp, ctypes.POINTER(_vp), _vp]
     L.pauli_merge.restype = st
     L.pauli_merge.argtypes = [_vp, ctypes.POINTER(MergeOpts), ctypes.POINTER(_vp), _vp]
+    L.pauli_merge_into.restype = st
+    L.pauli_merge_into.argtypes = [_vp, ctypes.POINTER(MergeOpts), _vp, _vp, _vp, _vp, _vp,
+                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _vp]
     L.pauli_outer_product_merged.restype = st
     L.pauli_outer_product_merged.argtypes = [_vp, _vp, ctypes.POINTER(MergeOpts),
                                              ctypes.POINTER(_vp), _vp]
@@ -277,6 +281,22 @@ def merge(s: PauliSum, mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0, stream=No
     o = _opts(mode, drop_abs, tau, key_bits)
     _check(lib().pauli_merge(s.handle, ctypes.byref(o), ctypes.byref(out), _stream(stream)))
     return PauliSum(out)
+
+
+def merge_into(s: PauliSum, out_x, out_z, out_phase, out_coef, out_fp, out_ld: int,
+               mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0, stream=None) -> int:
+    """pauli_merge_into: merge(s) written to caller-owned device arrays
+    (device pointers as ints, or tensors: out_x/out_z (W, out_ld) uint64
+    words, out_phase (out_ld,) uint8, out_coef (out_ld,) complex of the
+    result's dtype, out_fp (out_ld,) uint64).  Returns the merged count."""
+    def ptr(a):
+        return a.data_ptr() if _is_torch(a) else int(a)
+    m = ctypes.c_int64(-1)
+    o = _opts(mode, drop_abs, tau, key_bits)
+    _check(lib().pauli_merge_into(s.handle, ctypes.byref(o), ptr(out_x), ptr(out_z),
+                                  ptr(out_phase), ptr(out_coef), ptr(out_fp), int(out_ld),
+                                  ctypes.byref(m), _stream(stream)))
+    return m.value
 
 
 def outer_product_merged(a: PauliSum, b: PauliSum, mode=PLAIN, drop_abs=-1.0, tau=0.0,

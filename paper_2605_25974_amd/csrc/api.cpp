@@ -45,11 +45,67 @@ void hip_check(hipError_t e, const char* what) {
   }
 }
 
-// Returns the cached blocks of device dev of at least min_bytes to the
-// runtime pool, each on the stream it was released on.
+// ------------------------------------------------- fixed scratch workspace
+//
+// pauli_merge_into runs the merge pipeline without allocating: its
+// temporaries come from `scratch`, one fixed array per device that the
+// library holds until the process ends, and its result goes to arrays the
+// caller passes.  In host code the array's name is not a device address;
+// its address on each device comes from hipGetSymbolAddress, made once per
+// device with that device current.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int64_t kScratchMaxTerms = int64_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on device dev (current on the calling thread).
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(PAULI_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      fail(PAULI_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+struct Workspace {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  paulisum out;  // the caller's output arrays; out.ld is their capacity
+  bool out_taken = false;
+};
+thread_local Workspace* g_ws = nullptr;
+
+// Makes ws the calling thread's workspace for the lifetime of the guard.
+struct WorkspaceGuard {
+  explicit WorkspaceGuard(Workspace* ws) { g_ws = ws; }
+  ~WorkspaceGuard() { g_ws = nullptr; }
+};
+}  // namespace
+
+bool workspace_active() { return g_ws != nullptr; }
+
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
   bytes = (bytes + 255) & ~size_t(255);
+  if (g_ws) {
+    if (bytes > g_ws->size - g_ws->used)
+      fail(PAULI_ERR_CAPACITY, "the fixed scratch array (" + std::to_string(g_ws->size) +
+                                   " bytes) is too small for this call");
+    void* p = g_ws->base + g_ws->used;
+    g_ws->used += bytes;
+    return p;
+  }
   const uint64_t budget = g_budget.load();
   if (budget && g_in_use.load() + bytes > budget)
     fail(PAULI_ERR_OOM, "device memory budget exceeded (" + std::to_string(bytes) +
@@ -70,6 +126,9 @@ void* dalloc(size_t bytes, hipStream_t s) {
 
 void dfree(void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
+  if (g_ws && static_cast<char*>(p) >= g_ws->base &&
+      static_cast<char*>(p) < g_ws->base + g_ws->size)
+    return;  // the workspace is released as a whole when its call ends
   bytes = (bytes + 255) & ~size_t(255);
   g_in_use -= bytes;
   if (g_alloc) {
@@ -81,6 +140,19 @@ void dfree(void* p, size_t bytes, hipStream_t s) {
 
 paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s) {
   const int W = words_for(n);
+  if (g_ws) {
+    // the result of a call that allocates nothing: the caller's arrays
+    paulisum* p = &g_ws->out;
+    if (g_ws->out_taken) fail(PAULI_ERR_DEVICE, "a second result in a call without allocation");
+    if (n != p->n || dt != p->dtype) fail(PAULI_ERR_DEVICE, "result shape differs from the output");
+    if (m > p->ld)
+      fail(PAULI_ERR_CAPACITY, "the result has " + std::to_string(m) +
+                                   " terms; the output arrays hold " + std::to_string(p->ld));
+    g_ws->out_taken = true;
+    p->m = m;
+    p->last_stream = s;
+    return p;
+  }
   const size_t L = static_cast<size_t>(ld);
   auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t bX = up(L * W * 8), bph = up(L), bc = up(L * coef_bytes(dt)), bfp = up(L * 8);
@@ -110,7 +182,7 @@ paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s) {
 }
 
 void free_sum(paulisum* p) {
-  if (!p) return;
+  if (!p || p->borrowed) return;
   if (p->block) dfree(p->block, p->block_bytes, p->last_stream);
   delete p;
 }
@@ -432,6 +504,48 @@ pauli_status_t pauli_merge(paulisum_t sum, const pauli_merge_opts_t* opts, pauli
     hipStream_t s = as_stream(stream);
     sum->last_stream = s;
     *out = merge_generic(sum, nullptr, m, s);
+  });
+}
+
+pauli_status_t pauli_merge_into(paulisum_t sum, const pauli_merge_opts_t* opts,
+                                uint64_t* out_x, uint64_t* out_z, uint8_t* out_phase,
+                                void* out_coef, uint64_t* out_fp, int64_t out_ld, int64_t* out_m,
+                                void* stream) {
+  return guarded([&] {
+    if (!out_m) fail(PAULI_ERR_INVALID, "out_m is NULL");
+    check_sum(sum, "s");
+    if (!out_x || !out_z || !out_phase || !out_coef || !out_fp)
+      fail(PAULI_ERR_INVALID, "an output array is NULL");
+    if (out_ld < 1) fail(PAULI_ERR_INVALID, "out_ld must be positive");
+    if (sum->m > kScratchMaxTerms)
+      fail(PAULI_ERR_CAPACITY, "pauli_merge_into takes at most " +
+                                   std::to_string(kScratchMaxTerms) + " terms (got " +
+                                   std::to_string(sum->m) + ")");
+    const MergeArgs m = merge_args(opts);
+    use_device(sum);
+    hipStream_t s = as_stream(stream);
+    sum->last_stream = s;
+    int dev = 0;
+    PAULI_HIP(hipGetDevice(&dev));
+    Workspace ws;
+    ws.base = static_cast<char*>(scratch_address(dev));
+    ws.size = kScratchBytes;
+    paulisum& o = ws.out;
+    o.n = sum->n;
+    o.W = sum->W;
+    o.ld = out_ld;
+    o.dtype = m.mode == PAULI_MERGE_COMPENSATED ? PAULI_C64 : sum->dtype;
+    o.device = dev;
+    o.X = out_x;
+    o.Z = out_z;
+    o.ph = out_phase;
+    o.coef = out_coef;
+    o.fp = out_fp;
+    o.borrowed = true;
+    WorkspaceGuard guard(&ws);
+    paulisum* r = merge_generic(sum, nullptr, m, s);
+    if (r != &ws.out) fail(PAULI_ERR_DEVICE, "the merge did not write the output arrays");
+    *out_m = r->m;
   });
 }
 

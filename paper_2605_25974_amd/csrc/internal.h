@@ -28,6 +28,7 @@ struct paulisum {
   void* coef = nullptr;   // [ld] interleaved (re, im) of dtype
   uint64_t* fp = nullptr; // [ld]
   hipStream_t last_stream = nullptr;
+  bool borrowed = false;  // arrays owned by the caller of pauli_merge_into
 };
 
 namespace pauli {
@@ -49,6 +50,12 @@ void arena_trim(int dev);  // returns the idle chunks of device dev
 
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, size_t bytes, hipStream_t s);
+
+// True while a call that allocates nothing (pauli_merge_into) runs on the
+// calling thread: dalloc then hands out consecutive pieces of the library's
+// fixed device scratch array, dfree releases nothing, new_sum returns the
+// caller's output arrays, and stage timing records no events.
+bool workspace_active();
 
 // RAII device buffer freed (stream-ordered) when it leaves scope.
 struct DBuf {

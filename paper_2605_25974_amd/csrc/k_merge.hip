@@ -19,6 +19,7 @@
 // outer product (pair source, no product is ever stored).
 #include <cmath>
 #include <memory>
+#include <optional>
 #include <type_traits>
 
 #include "common.h"
@@ -299,8 +300,8 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
   cplx<TV>* v = v_buf.as<cplx<TV>>();
 
   const unsigned g = grid_for(N);
-  auto sc_seg = std::make_unique<StageScope>(PAULI_STAGE_SEGMENT, s,
-                                             N * (12.0 + 4.0 + sizeof(cplx<TV>)));
+  std::optional<StageScope> sc_seg;
+  sc_seg.emplace(PAULI_STAGE_SEGMENT, s, N * (12.0 + 4.0 + sizeof(cplx<TV>)));
   hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
                      v, ctr + 0, 0);
   hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, head, N,

@@ -49,6 +49,7 @@ void flush_locked() {
 }  // namespace
 
 StageScope::StageScope(int st, hipStream_t str, double by) : stage(st), s(str), bytes(by) {
+  if (workspace_active()) return;  // a call that allocates nothing creates no events
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   a = take_event();
