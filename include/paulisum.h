@@ -75,15 +75,24 @@ typedef struct {
   int32_t key_bits;
 } pauli_merge_opts_t;
 
-/* Launch-shape parameters of the fused pipeline (0 = tuned or default).
- *  bucket_bits  the records of a product are split into 2^bucket_bits
- *               buckets by the top bits of their key, and each bucket is
- *               sorted in LDS (about |a||b| / 2^bucket_bits records each);
- *               1..16.
- *  reserved     must be 0. */
+/* Launch shape of the batched form (a field of 0 takes its default; a
+ * non-NULL tune turns the autotuner off).
+ *  bucket_bits     every product's records are split into 2^bucket_bits
+ *                  buckets by the top bits of their key, each bucket sorted
+ *                  in LDS; 0..16 (0: from bucket_records).
+ *  bucket_records  records per bucket the bucket bits aim at (the tile size
+ *                  of the LDS bucket sort), 256..8192; default 7000.
+ *  class_bits      at most this many of a product's bucket bits come from
+ *                  the class tiles of the record generation; the rest
+ *                  (at most 8) form the radix digit of its partition pass
+ *                  (the radix width); 0..8, default 8.
+ *  expand_parts    work items per bucket of the expand kernel (the records
+ *                  each wave takes at a time); 1, 2, 4 or 8, default 4. */
 typedef struct {
   int32_t bucket_bits;
-  int32_t reserved[3];
+  int32_t bucket_records;
+  int32_t class_bits;
+  int32_t expand_parts;
 } pauli_tune_t;
 
 /* Text of a status code (static storage). */
@@ -242,18 +251,57 @@ pauli_status_t pauli_apply_clifford(paulisum_t s, int32_t n_gates, const pauli_g
  * OOM. */
 pauli_status_t pauli_sort_lex(paulisum_t s, paulisum_t* out, void* stream);
 
-/* pauli_outer_product_batched: nb independent fused products
- * out[t] = merge(a[t] * b[t]) with one set of merge options; the pairs may
- * differ in qubit count and term counts but a[t], b[t] must agree with each
- * other.  tune == NULL: the bucket width of each product is the one measured
- * fastest for its (word count, size, precision) class, timed on the first
- * product of the class this process meets (each candidate computes the same
- * result; the class's choice is kept for later calls).  On error no output
- * is returned and every product made so far is freed. */
+/* pauli_outer_product_batched: nb independent products
+ * out[t] = merge(a[t] * b[t]) (the outer product of Section IV-C and the
+ * merge of Section III-H, each exactly as pauli_outer_product_merged gives
+ * it: same terms, order and values) with one set of merge options.  The
+ * pairs may differ in qubit count and term counts; a[t] and b[t] must agree
+ * with each other.  Products with the same word count and coefficient type
+ * run together: one launch per stage covers all of them (one generation
+ * over the pair tiles of every product, one bucket sort whose bucket index
+ * holds the product above the key bits, one expand), with no host
+ * synchronisation between stages.  tune == NULL: each class of products
+ * (word count, size, precision, mode) takes the launch shape measured
+ * fastest for it, timed on the first batch of the class this process meets
+ * (every candidate computes the same result) or read from the tune table
+ * (pauli_tune_load, or the file named by the environment variable
+ * PAULI_TUNE_FILE, which is also rewritten after each new measurement).
+ * Results are views into one output block per class (released with the
+ * last of them).  Errors: those of pauli_outer_product_merged for each
+ * pair; INVALID for a bad tune field or key_bits in 1..29.  On error no
+ * output is returned.  Synchronises the stream once. */
 pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
                                            const pauli_merge_opts_t* opts,
                                            const pauli_tune_t* tune, paulisum_t* out,
                                            void* stream);
+
+/* Batch plans: the batched form captured once into a HIP graph and replayed.
+ *  pauli_batch_plan_create  allocates the buffers of the batch (the inputs
+ *      a[t], b[t] must stay alive and unchanged while the plan exists),
+ *      tunes its launch shapes as pauli_outer_product_batched does, and
+ *      captures the whole launch sequence into a graph.
+ *  pauli_batch_plan_run     launches the graph, ordered after earlier work
+ *      on `stream` and before later work on it; no host synchronisation.
+ *  pauli_batch_plan_results waits for the last run and returns its nb
+ *      products (as pauli_outer_product_batched does); the plan allocates
+ *      new output blocks (and captures again) at its next run.  INVALID if
+ *      the plan has not run since its last results.
+ *  pauli_batch_plan_destroy releases the plan (NULL is allowed); results
+ *      already returned stay valid. */
+typedef struct pauli_batch_plan* pauli_batch_plan_t;
+pauli_status_t pauli_batch_plan_create(int32_t nb, const paulisum_t* a, const paulisum_t* b,
+                                       const pauli_merge_opts_t* opts, const pauli_tune_t* tune,
+                                       void* stream, pauli_batch_plan_t* out);
+pauli_status_t pauli_batch_plan_run(pauli_batch_plan_t plan, void* stream);
+pauli_status_t pauli_batch_plan_results(pauli_batch_plan_t plan, paulisum_t* out, void* stream);
+pauli_status_t pauli_batch_plan_destroy(pauli_batch_plan_t plan);
+
+/* The autotuner's table of launch shapes per class, as text (one class per
+ * line): pauli_tune_save writes it, pauli_tune_load merges a saved one into
+ * the table.  INVALID if the file cannot be written or read, or a line is
+ * malformed. */
+pauli_status_t pauli_tune_save(const char* path);
+pauli_status_t pauli_tune_load(const char* path);
 
 /* pauli_propagate: a sequence of Pauli rotations applied to a sum (Section
  * III-B: eq. (5) and its truncation).  Step t uses the string

@@ -30,7 +30,8 @@ EXPORTS = (
     "pauli_outer_product_merged", "pauli_outer_product_batched", "pauli_set_allocator",
     "pauli_set_memory_budget", "pauli_profile_enable", "pauli_profile_read", "pauli_propagate",
     "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford", "pauli_sort_lex",
-    "pauli_merge_into",
+    "pauli_merge_into", "pauli_batch_plan_create", "pauli_batch_plan_run",
+    "pauli_batch_plan_results", "pauli_batch_plan_destroy", "pauli_tune_save", "pauli_tune_load",
 )
 STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford", "lex",
           "filter")
@@ -52,7 +53,8 @@ class MergeOpts(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("bucket_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("bucket_bits", ctypes.c_int32), ("bucket_records", ctypes.c_int32),
+                ("class_bits", ctypes.c_int32), ("expand_parts", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -110,6 +112,20 @@ def lib():
     L.pauli_outer_product_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
                                               ctypes.POINTER(_vp), ctypes.POINTER(MergeOpts),
                                               ctypes.POINTER(Tune), ctypes.POINTER(_vp), _vp]
+    L.pauli_batch_plan_create.restype = st
+    L.pauli_batch_plan_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp),
+                                          ctypes.POINTER(_vp), ctypes.POINTER(MergeOpts),
+                                          ctypes.POINTER(Tune), _vp, ctypes.POINTER(_vp)]
+    L.pauli_batch_plan_run.restype = st
+    L.pauli_batch_plan_run.argtypes = [_vp, _vp]
+    L.pauli_batch_plan_results.restype = st
+    L.pauli_batch_plan_results.argtypes = [_vp, ctypes.POINTER(_vp), _vp]
+    L.pauli_batch_plan_destroy.restype = st
+    L.pauli_batch_plan_destroy.argtypes = [_vp]
+    L.pauli_tune_save.restype = st
+    L.pauli_tune_save.argtypes = [ctypes.c_char_p]
+    L.pauli_tune_load.restype = st
+    L.pauli_tune_load.argtypes = [ctypes.c_char_p]
     L.pauli_trim_memory.restype = st
     L.pauli_trim_memory.argtypes = []
     L.pauli_propagate.restype = st
@@ -365,6 +381,15 @@ def propagate(s: PauliSum, px, pz, theta, rotate_mode=ROTATE_CONJUGATE, mode=PLA
     return PauliSum(out)
 
 
+def _tune(tune):
+    """None, an int (bucket bits) or a dict of pauli_tune_t fields."""
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        return Tune(**{k: int(v) for k, v in tune.items()})
+    return Tune(bucket_bits=int(tune))
+
+
 def outer_product_batched(a_list, b_list, mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0,
                           tune=None, stream=None):
     nb = len(a_list)
@@ -372,11 +397,58 @@ def outer_product_batched(a_list, b_list, mode=PLAIN, drop_abs=-1.0, tau=0.0, ke
     B = (_vp * max(nb, 1))(*[x.handle for x in b_list])
     O = (_vp * max(nb, 1))()
     o = _opts(mode, drop_abs, tau, key_bits)
-    t = Tune(int(tune)) if tune is not None else None  # tune: bucket bits
+    t = _tune(tune)
     _check(lib().pauli_outer_product_batched(nb, A, B, ctypes.byref(o),
                                              ctypes.byref(t) if t is not None else None, O,
                                              _stream(stream)))
     return [PauliSum(O[i]) for i in range(nb)]
+
+
+class BatchPlan:
+    """pauli_batch_plan_*: the batched form captured into a HIP graph.  The
+    plan keeps references to its input sums."""
+
+    def __init__(self, a_list, b_list, mode=PLAIN, drop_abs=-1.0, tau=0.0, key_bits=0,
+                 tune=None, stream=None):
+        self._inputs = (list(a_list), list(b_list))
+        nb = len(a_list)
+        self.nb = nb
+        A = (_vp * max(nb, 1))(*[x.handle for x in a_list])
+        B = (_vp * max(nb, 1))(*[x.handle for x in b_list])
+        o = _opts(mode, drop_abs, tau, key_bits)
+        t = _tune(tune)
+        h = _vp()
+        _check(lib().pauli_batch_plan_create(nb, A, B, ctypes.byref(o),
+                                             ctypes.byref(t) if t is not None else None,
+                                             _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().pauli_batch_plan_run(self._h, _stream(stream)))
+
+    def results(self, stream=None):
+        O = (_vp * max(self.nb, 1))()
+        _check(lib().pauli_batch_plan_results(self._h, O, _stream(stream)))
+        return [PauliSum(O[i]) for i in range(self.nb)]
+
+    def destroy(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().pauli_batch_plan_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def tune_save(path):
+    _check(lib().pauli_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    _check(lib().pauli_tune_load(os.fsencode(path)))
 
 
 def trim_memory():

@@ -181,6 +181,46 @@ paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s) {
   return p;
 }
 
+SharedBlock::SharedBlock(int W_, int64_t ld_, int32_t dtype_, hipStream_t s_)
+    : W(W_), ld(ld_), dtype(dtype_), s(s_) {
+  const size_t L = static_cast<size_t>(ld);
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t bX = up(L * W * 8), bph = up(L), bc = up(L * coef_bytes(dtype)), bfp = up(L * 8);
+  bytes = 2 * bX + bph + bc + bfp;
+  block = bytes ? dalloc(bytes, s) : nullptr;
+  char* b = static_cast<char*>(block);
+  X = reinterpret_cast<uint64_t*>(b);
+  Z = reinterpret_cast<uint64_t*>(b + bX);
+  ph = reinterpret_cast<uint8_t*>(b + 2 * bX);
+  coef = b + 2 * bX + bph;
+  fp = reinterpret_cast<uint64_t*>(b + 2 * bX + bph + bc);
+}
+
+SharedBlock::~SharedBlock() {
+  try {
+    if (block) dfree(block, bytes, s);
+  } catch (...) {
+  }
+}
+
+paulisum* sum_view(const std::shared_ptr<SharedBlock>& b, int n, int64_t first, int64_t m) {
+  paulisum* p = new paulisum;
+  p->n = n;
+  p->W = words_for(n);
+  p->m = m;
+  p->ld = b->ld;
+  p->dtype = b->dtype;
+  PAULI_HIP(hipGetDevice(&p->device));
+  p->last_stream = b->s;
+  p->X = b->X + first;
+  p->Z = b->Z + first;
+  p->ph = b->ph + first;
+  p->coef = static_cast<char*>(b->coef) + first * coef_bytes(b->dtype);
+  p->fp = b->fp + first;
+  p->shared = b;
+  return p;
+}
+
 void free_sum(paulisum* p) {
   if (!p || p->borrowed) return;
   if (p->block) dfree(p->block, p->block_bytes, p->last_stream);
@@ -255,89 +295,33 @@ MergeArgs merge_args(const pauli_merge_opts_t* o) {
   return m;
 }
 
-// Bucket-width autotuner of the batched form.  For each class of products
-// (word count, log2 of the product count, coefficient type, merge mode) the
-// first product met is run with the size heuristic's width and its two
-// neighbours, timed with events on the call's stream; the fastest width is
-// kept for the class.  Every candidate computes the same merged sum (the
-// bucket split does not change the order of records within a segment), so
-// the fastest run's output is the product's result.
-struct TuneKey {
-  int W, logp, dtype, mode;
-  bool operator<(const TuneKey& o) const {
-    if (W != o.W) return W < o.W;
-    if (logp != o.logp) return logp < o.logp;
-    if (dtype != o.dtype) return dtype < o.dtype;
-    return mode < o.mode;
-  }
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tuned;
-constexpr int64_t kTuneMinProducts = int64_t(1) << 22;  // smaller products are not worth timing
-
-paulisum* fused_or_generic(const paulisum* a, const paulisum* b, const MergeArgs& m,
-                           hipStream_t s) {
-  paulisum* r = nullptr;
-  if (a->m > 0 && b->m > 0) r = fused_bucket(a, b, m, s);
-  if (!r) r = merge_generic(a, b, m, s);
-  return r;
+// Launch shape of a batched call from its tune argument (checked).
+BatchShape batch_shape(const pauli_tune_t* t) {
+  BatchShape b;
+  if (t->bucket_bits < 0 || t->bucket_bits > 16)
+    fail(PAULI_ERR_INVALID, "tune: bucket_bits must be in 0..16");
+  if (t->bucket_records != 0 && (t->bucket_records < 256 || t->bucket_records > 8192))
+    fail(PAULI_ERR_INVALID, "tune: bucket_records must be 0 or in 256..8192");
+  if (t->class_bits < 0 || t->class_bits > 8)
+    fail(PAULI_ERR_INVALID, "tune: class_bits must be in 0..8");
+  if (t->expand_parts != 0 && t->expand_parts != 1 && t->expand_parts != 2 &&
+      t->expand_parts != 4 && t->expand_parts != 8)
+    fail(PAULI_ERR_INVALID, "tune: expand_parts must be 0, 1, 2, 4 or 8");
+  b.bucket_bits = t->bucket_bits;
+  b.bucket_records = t->bucket_records;
+  b.class_bits = t->class_bits;
+  b.expand_parts = t->expand_parts;
+  return b;
 }
 
-paulisum* batched_one(const paulisum* a, const paulisum* b, const MergeArgs& m, bool autotune,
-                      hipStream_t s) {
-  const int64_t P = a->m * b->m;
-  if (!autotune || m.bucket_bits > 0 || P < kTuneMinProducts)
-    return fused_or_generic(a, b, m, s);
-  int logp = 0;
-  while ((int64_t(1) << logp) < P) ++logp;
-  const TuneKey key{a->W, logp, a->dtype, m.mode};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-      MergeArgs mt = m;
-      mt.bucket_bits = it->second;
-      return fused_or_generic(a, b, mt, s);
-    }
-  }
-  const int d0 = fused_default_bucket_bits(P, m.key_bits);
-  paulisum* best = nullptr;
-  float best_ms = 0.0f;
-  int best_d = d0;
-  hipEvent_t e0, e1;
-  PAULI_HIP(hipEventCreate(&e0));
-  PAULI_HIP(hipEventCreate(&e1));
-  try {
-    for (int d = d0 - 1; d <= d0 + 1; ++d) {
-      if (d < 1 || d > 16 || d > m.key_bits) continue;
-      MergeArgs mt = m;
-      mt.bucket_bits = d;
-      PAULI_HIP(hipEventRecord(e0, s));
-      paulisum* r = fused_or_generic(a, b, mt, s);
-      PAULI_HIP(hipEventRecord(e1, s));
-      PAULI_HIP(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      PAULI_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (!best || ms < best_ms) {
-        free_sum(best);
-        best = r;
-        best_ms = ms;
-        best_d = d;
-      } else {
-        free_sum(r);
-      }
-    }
-  } catch (...) {
-    free_sum(best);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    throw;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned[key] = best_d;
-  return best;
+void check_batch(int32_t nb, const paulisum_t* a, const paulisum_t* b, const pauli_merge_opts_t* o) {
+  if (nb < 0) fail(PAULI_ERR_INVALID, "nb is negative");
+  if (nb > 0 && (!a || !b)) fail(PAULI_ERR_INVALID, "a and b must not be NULL");
+  for (int32_t t = 0; t < nb; ++t) check_pair(a[t], b[t]);
+  for (int32_t t = 1; t < nb; ++t)
+    if (a[t]->device != a[0]->device) fail(PAULI_ERR_SHAPE, "products live on different devices");
+  if (o && o->key_bits != 0 && o->key_bits < 30)
+    fail(PAULI_ERR_INVALID, "the batched form needs key_bits 0 or at least 30");
 }
 
 }  // namespace
@@ -643,28 +627,69 @@ pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, cons
                                            const pauli_tune_t* tune, paulisum_t* out,
                                            void* stream) {
   return guarded([&] {
-    if (nb < 0) fail(PAULI_ERR_INVALID, "nb is negative");
-    if (nb > 0 && (!a || !b || !out)) fail(PAULI_ERR_INVALID, "a, b and out must not be NULL");
-    if (tune && (tune->bucket_bits < 0 || tune->bucket_bits > 16 || tune->reserved[0] ||
-                 tune->reserved[1] || tune->reserved[2]))
-      fail(PAULI_ERR_INVALID, "tune: bucket_bits must be in 0..16 and reserved fields 0");
-    for (int32_t t = 0; t < nb; ++t) check_pair(a[t], b[t]);
+    check_batch(nb, a, b, opts);
+    if (nb > 0 && !out) fail(PAULI_ERR_INVALID, "out must not be NULL");
+    BatchShape shape;
+    if (tune) shape = batch_shape(tune);
     const MergeArgs m = merge_args(opts);
+    if (nb == 0) return;
+    use_device(a[0]);
     hipStream_t s = as_stream(stream);
-    std::vector<paulisum*> res(static_cast<size_t>(nb), nullptr);
-    try {
-      for (int32_t t = 0; t < nb; ++t) {
-        use_device(a[t]);
-        a[t]->last_stream = b[t]->last_stream = s;
-        MergeArgs mt = m;
-        if (tune && tune->bucket_bits > 0) mt.bucket_bits = tune->bucket_bits;
-        res[t] = batched_one(a[t], b[t], mt, tune == nullptr, s);
-      }
-    } catch (...) {
-      for (auto* r : res) free_sum(r);
-      throw;
-    }
-    for (int32_t t = 0; t < nb; ++t) out[t] = res[t];
+    for (int32_t t = 0; t < nb; ++t) a[t]->last_stream = b[t]->last_stream = s;
+    std::unique_ptr<BatchPlan, void (*)(BatchPlan*)> plan(
+        batch_plan_create(nb, a, b, m, tune ? &shape : nullptr, false, s), batch_plan_destroy);
+    batch_plan_run(plan.get(), s);
+    batch_plan_results(plan.get(), out, s);
+  });
+}
+
+pauli_status_t pauli_batch_plan_create(int32_t nb, const paulisum_t* a, const paulisum_t* b,
+                                       const pauli_merge_opts_t* opts, const pauli_tune_t* tune,
+                                       void* stream, pauli_batch_plan_t* out) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_batch(nb, a, b, opts);
+    BatchShape shape;
+    if (tune) shape = batch_shape(tune);
+    const MergeArgs m = merge_args(opts);
+    if (nb > 0) use_device(a[0]);
+    hipStream_t s = as_stream(stream);
+    *out = reinterpret_cast<pauli_batch_plan_t>(
+        batch_plan_create(nb, a, b, m, tune ? &shape : nullptr, true, s));
+  });
+}
+
+pauli_status_t pauli_batch_plan_run(pauli_batch_plan_t plan, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(PAULI_ERR_INVALID, "plan is NULL");
+    batch_plan_run(reinterpret_cast<BatchPlan*>(plan), as_stream(stream));
+  });
+}
+
+pauli_status_t pauli_batch_plan_results(pauli_batch_plan_t plan, paulisum_t* out, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(PAULI_ERR_INVALID, "plan is NULL");
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    batch_plan_results(reinterpret_cast<BatchPlan*>(plan), out, as_stream(stream));
+  });
+}
+
+pauli_status_t pauli_batch_plan_destroy(pauli_batch_plan_t plan) {
+  return guarded([&] { batch_plan_destroy(reinterpret_cast<BatchPlan*>(plan)); });
+}
+
+pauli_status_t pauli_tune_save(const char* path) {
+  return guarded([&] {
+    if (!path) fail(PAULI_ERR_INVALID, "path is NULL");
+    if (batch_tune_save(path) != 0) fail(PAULI_ERR_INVALID, std::string("cannot write ") + path);
+  });
+}
+
+pauli_status_t pauli_tune_load(const char* path) {
+  return guarded([&] {
+    if (!path) fail(PAULI_ERR_INVALID, "path is NULL");
+    if (batch_tune_load(path) != 0)
+      fail(PAULI_ERR_INVALID, std::string("cannot read a tune table from ") + path);
   });
 }
 

@@ -230,7 +230,33 @@ struct ExpandArgs {
   int64_t ldo;  // a multiple of kBS
   double tau;   // cancellation threshold of the compensated form
   int marks;    // phase byte 1 marks a term no record kept (commutator), for a later compaction
+  // A batched launch sequence (null: one product, the kernel's operands):
+  // the product of each bucket, and per product its operands, its first
+  // bucket, its first output term (a multiple of kBS; its terms are written
+  // from there) and its collision flag.
+  const uint16_t* bprod = nullptr;
+  const void* optab = nullptr;  // Operands<WT, T>[product]
+  const uint32_t* pbase = nullptr;
+  const uint32_t* pout = nullptr;
+  uint32_t* perr = nullptr;
+  uint32_t parts = kParts;  // work items per bucket
 };
+
+// The operands and first output term of bucket b.
+template <bool BATCH, int WT, typename T>
+__device__ __forceinline__ void bucket_product(const ExpandArgs& E, const Operands<WT, T>& op0,
+                                               uint32_t b, Operands<WT, T>& op, uint32_t& obase,
+                                               uint32_t& prod) {
+  if constexpr (BATCH) {
+    prod = E.bprod[b];
+    op = static_cast<const Operands<WT, T>*>(E.optab)[prod];
+    obase = E.pout[prod] + (E.segoff[b] - E.segoff[E.pbase[prod]]);
+  } else {
+    prod = 0;
+    op = op0;
+    obase = E.segoff[b];
+  }
+}
 
 // Merged terms of a wave, staged for aligned coalesced stores: a ring of CAP
 // slots, output term o in slot o mod CAP.  The x and z rows are one word
@@ -400,9 +426,9 @@ __device__ __forceinline__ void store_block(const ExpandArgs& E, Stage<WT, TV, C
 //
 // The ids two chunks ahead and the row/metadata gathers of the next chunk are
 // issued before a chunk is processed.
-template <int G, int WT, typename T, int MODE>
+template <int G, int WT, typename T, int MODE, bool BATCH = false>
 __global__ void __launch_bounds__(kB, G >= 16 ? 2 : 3)
-k_expand(ExpandArgs E, Operands<WT, T> op) {
+k_expand(ExpandArgs E, Operands<WT, T> op0) {
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
   constexpr int KR = Run<G>::v;
   constexpr int NG = 64 / G;  // groups per wave
@@ -414,21 +440,24 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   Stage<WT, TV, CAP>& st = stage[wave];
   const int g = lane / G, gl = lane % G;
-  const int nw = op.nw;
   const uint32_t goff = static_cast<uint32_t>(g) * KR;
-  const uint32_t items = E.nbk * kParts;
+  const uint32_t parts = E.parts;
+  const uint32_t items = E.nbk * parts;
   uint64_t coll = 0;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = atomicAdd(E.work, 1u);
     item = __builtin_amdgcn_readfirstlane(item);
     if (item >= items) break;
-    const uint32_t b = item / kParts, part = item % kParts;
+    const uint32_t b = item / parts, part = item % parts;
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
-    const uint32_t q_beg = static_cast<uint32_t>(static_cast<uint64_t>(n) * part / kParts);
-    const uint32_t q_end = static_cast<uint32_t>(static_cast<uint64_t>(n) * (part + 1) / kParts);
+    const uint32_t q_beg = static_cast<uint32_t>(static_cast<uint64_t>(n) * part / parts);
+    const uint32_t q_end = static_cast<uint32_t>(static_cast<uint64_t>(n) * (part + 1) / parts);
     if (q_beg >= q_end) continue;
-    const uint32_t obase = E.segoff[b];
+    Operands<WT, T> op;
+    uint32_t obase, prod;
+    bucket_product<BATCH, WT, T>(E, op0, b, op, obase, prod);
+    const int nw = op.nw;
     for (int k = lane; k < CAP; k += 64) st.valid[k] = 0;
     // pipeline prologue: ids of chunks 0 and 1, gathers of chunk 0
     const Meta<G> m_cur = fetch_meta<G>(E, lo, n, q_beg + goff, gl);
@@ -550,6 +579,10 @@ k_expand(ExpandArgs E, Operands<WT, T> op) {
     }
     // the range's last, partial block
     if (A < Ew) store_block<WT, TV, CAP>(E, st, nw, Bk, A, Ew, lane);
+    if constexpr (BATCH) {  // each product's own flag
+      if (__any(coll != 0) && lane == 0) atomicOr(E.perr + prod, kErrCollision);
+      coll = 0;
+    }
   }
   if (__any(coll != 0) && lane == 0) atomicOr(E.err, kErrCollision);
 }
@@ -577,9 +610,9 @@ __device__ __forceinline__ void write_out(const ExpandArgs& E, int nw, int gl, i
 // pairwise tree.
 // In the compensated form a cancelled segment is summed again the same way
 // in FP64.
-template <int G, int WT, typename T, int MODE>
+template <int G, int WT, typename T, int MODE, bool BATCH = false>
 __global__ void __launch_bounds__(kLongB)
-k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ long_list,
+k_expand_long(ExpandArgs E, Operands<WT, T> op0, const uint32_t* __restrict__ long_list,
               const uint32_t* __restrict__ nlong) {
   using TV = typename std::conditional<MODE == kComp, float, T>::type;
   constexpr int NG = kLongB / G;
@@ -593,6 +626,9 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
     const uint32_t b = long_list[2 * x], q0 = long_list[2 * x + 1];
     const uint32_t lo = E.boff[b], n = E.boff[b + 1] - lo;
     const uint32_t s0 = E.segidx[lo + q0];
+    Operands<WT, T> op;
+    uint32_t obase, prod;
+    bucket_product<BATCH, WT, T>(E, op0, b, op, obase, prod);
     if (threadIdx.x == 0) s_kept = 0;
     if (threadIdx.x == 0) {  // segment indices grow along the bucket: binary search
       uint32_t l = q0, h = n;    // first position past the segment is in (l, h]
@@ -618,7 +654,7 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
     if (gl == 0 && kept) atomicOr(&s_kept, 1);
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) diff |= __shfl_xor(diff, off, 64);
-    if (gl == 0 && diff) atomicOr(E.err, kErrCollision);
+    if (gl == 0 && diff) atomicOr(BATCH ? E.perr + prod : E.err, kErrCollision);
     if (gl == 0) s_acc[g] = acc;
     __syncthreads();
     // the NG partial sums in a fixed pairwise tree
@@ -652,7 +688,7 @@ k_expand_long(ExpandArgs E, Operands<WT, T> op, const uint32_t* __restrict__ lon
       vi = static_cast<TV>(s_im[0]);
     }
     if (threadIdx.x < G)
-      write_out<G, TV, TV>(E, op.nw, gl, static_cast<int64_t>(E.segoff[b]) + s0, first, vr, vi,
+      write_out<G, TV, TV>(E, op.nw, gl, static_cast<int64_t>(obase) + s0, first, vr, vi,
                            s_kept != 0);
     __syncthreads();
   }

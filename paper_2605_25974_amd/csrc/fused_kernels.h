@@ -301,20 +301,46 @@ __device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, u
   val = G.ibits >= 0 ? ((j << G.ibits) | i) : j * G.ma + i;
 }
 
+// Products of a batched launch sequence: the super-buckets of all products
+// are numbered consecutively (product p owns [sbbase[p], sbbase[p + 1])),
+// and each product has its own generation tables and digit field.  Null
+// tables: one product (the kernel arguments).
+struct GenBatch {
+  const uint16_t* sbprod;  // [super-bucket] product
+  const uint32_t* sbbase;  // [product] first super-bucket
+  const GenSides* gen;     // [product]
+  const int* shift;        // [product] digit shift of the partition
+  const uint32_t* mask;    // [product] digit mask
+};
+
+// The tables of the product that owns global super-bucket sg: G, the
+// super-bucket's index inside its product (sl), shift and mask.
+__device__ __forceinline__ void gen_product(const GenBatch& bt, uint32_t sg, GenSides& G,
+                                            uint32_t& sl, int& shift, uint32_t& mask) {
+  sl = sg;
+  if (bt.sbprod == nullptr) return;
+  const uint32_t p = bt.sbprod[sg];
+  G = bt.gen[p];
+  sl = sg - bt.sbbase[p];
+  shift = bt.shift[p];
+  mask = bt.mask[p];
+}
+
 // Digit histogram of one partition tile.  Count layout: super-bucket s owns
 // C[tb[s]*256, tb[s+1]*256) as [digit][tile], so one exclusive scan of C
 // gives every (s, digit, tile) its output offset.
 __global__ void __launch_bounds__(kB)
-k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc,
-         int shift, uint32_t mask, uint32_t* __restrict__ C) {
+k_gcount(GenSides G, GenBatch bt, const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb,
+         uint32_t nc, int shift, uint32_t mask, uint32_t* __restrict__ C) {
   __shared__ uint32_t hist[256];
   __shared__ GenRow R;
-  uint32_t s, tl;
+  uint32_t s, tl, sl;
   if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
+  gen_product(bt, s, G, sl, shift, mask);
   hist[threadIdx.x] = 0;
   const uint32_t lo = tl * kTile;
   const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
-  load_gen_row(G, s, lo, hi, R);
+  load_gen_row(G, sl, lo, hi, R);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
@@ -340,7 +366,7 @@ k_gcount(GenSides G, const uint32_t* __restrict__ S, const uint32_t* __restrict_
 // digit's run is written (coalesced), which keeps the kernel small enough
 // for many resident blocks.
 __global__ void __launch_bounds__(kB)
-k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+k_gscatter(GenSides G, GenBatch bt, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
            const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
            uint32_t mask, const uint32_t* __restrict__ C) {
   constexpr int NW = kB / 64;
@@ -349,8 +375,9 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
   __shared__ uint32_t s_wc[NW][256];
   __shared__ uint32_t sh[NW];
   __shared__ GenRow R;
-  uint32_t s, tl;
+  uint32_t s, tl, sl;
   if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
+  gen_product(bt, s, G, sl, shift, mask);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t lo = tl * kTile;
   const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
@@ -358,7 +385,7 @@ k_gscatter(GenSides G, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
 #pragma unroll
   for (int w = 0; w < NW; ++w) s_wc[w][tid] = 0;
   s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
-  load_gen_row(G, s, lo, hi, R);
+  load_gen_row(G, sl, lo, hi, R);
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
   const int dbits = __popc(mask);  // digit bits (mask = 2^d2 - 1, d2 <= 8)
@@ -470,7 +497,36 @@ struct SortField {
   int lo16;
   int passes;
   uint64_t fmask;
+  int rem;  // key bits below the bucket bits (the heavy sort's field)
 };
+
+// The fields for rem key bits below the bucket bits.
+inline SortField sort_field_for(int rem) {
+  SortField sf;
+  sf.lo14 = rem >= kBinBits ? rem - kBinBits : -1;
+  if (rem >= 16) {
+    sf.lo16 = rem - 16;
+    sf.passes = 2;
+    sf.fmask = 0xFFFFull;
+  } else {
+    sf.lo16 = 0;
+    sf.passes = (rem + 7) / 8;
+    sf.fmask = rem ? ((1ull << rem) - 1) : 0ull;
+  }
+  sf.rem = rem;
+  return sf;
+}
+
+// Buckets of a batched launch sequence: the product of each bucket and each
+// product's sort fields.  Null tables: one product (the kernel arguments).
+struct SortBatch {
+  const uint16_t* bprod;  // [bucket] product
+  const SortField* sf;    // [product]
+};
+__device__ __forceinline__ SortField sort_field(const SortBatch& sb, uint32_t b,
+                                                const SortField& f) {
+  return sb.bprod ? sb.sf[sb.bprod[b]] : f;
+}
 
 __device__ __forceinline__ uint32_t sort_span(uint32_t N) {
   return ((N + 64 * kSortWaves - 1) / (64 * kSortWaves)) * 64;
@@ -835,7 +891,7 @@ __device__ void bucket_segments(uint32_t b, uint32_t lo, uint32_t n, SortSmem& S
 // records (many equal keys) for k_bucket_radix.
 __global__ void __launch_bounds__(kSortNT)
 k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
-               uint32_t nbk, SortField f, SegOut out, uint32_t* __restrict__ heavy,
+               uint32_t nbk, SortField f0, SortBatch sb, SegOut out, uint32_t* __restrict__ heavy,
                uint32_t* __restrict__ nheavy, uint32_t* __restrict__ redo,
                uint32_t* __restrict__ nredo) {
   __shared__ SortSmem S;
@@ -848,6 +904,7 @@ k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
     load_bucket(keys, out.vals, lo, n, k, v);
   }
   for (; b < nbk; b += gridDim.x) {
+    const SortField f = sort_field(sb, b, f0);
     const bool fits = n <= static_cast<uint32_t>(kCap);
     const bool ok = fits && count_scatter(n, f.lo14, k, v, S);
     // every load of this bucket has been used: the wait is free, and it
@@ -879,7 +936,7 @@ k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
 __global__ void __launch_bounds__(kSortNT)
 k_bucket_radix(const uint64_t* keys, const uint32_t* __restrict__ boff,
                uint32_t nbk, const uint32_t* __restrict__ list,
-               const uint32_t* __restrict__ nlist, SortField f, SegOut out,
+               const uint32_t* __restrict__ nlist, SortField f0, SortBatch sb, SegOut out,
                uint32_t* __restrict__ heavy, uint32_t* __restrict__ nheavy) {
   __shared__ SortSmem S;
   uint64_t k[kSortRounds];
@@ -893,7 +950,7 @@ k_bucket_radix(const uint64_t* keys, const uint32_t* __restrict__ boff,
       continue;
     }
     load_bucket(keys, out.vals, lo, n, k, v);
-    radix_bucket(n, k, v, f, S);
+    radix_bucket(n, k, v, sort_field(sb, b, f0), S);
     bucket_segments<false>(b, lo, n, S, out);
   }
 }
@@ -903,8 +960,9 @@ k_bucket_radix(const uint64_t* keys, const uint32_t* __restrict__ boff,
 // then marks the segments.
 __global__ void __launch_bounds__(kSortNT)
 k_heavy_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ tkeys,
-             uint32_t* __restrict__ tvals, const uint32_t* __restrict__ boff, int rbits,
-             const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ nheavy, SegOut out) {
+             uint32_t* __restrict__ tvals, const uint32_t* __restrict__ boff, int rbits0,
+             SortBatch sb, const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ nheavy,
+             SegOut out) {
   __shared__ uint32_t s_hist[256], s_start[256], s_run[256];
   __shared__ uint32_t s_wc[kSortWaves][256];
   __shared__ uint32_t sh[kSortWaves];
@@ -913,6 +971,7 @@ k_heavy_sort(uint64_t* __restrict__ keys, uint64_t* __restrict__ tkeys,
   const uint32_t H = *nheavy;
   for (uint32_t hix = blockIdx.x; hix < H; hix += gridDim.x) {
     const uint32_t b = heavy[hix];
+    const int rbits = sb.bprod ? sb.sf[sb.bprod[b]].rem : rbits0;
     const uint32_t lo = boff[b], n = boff[b + 1] - lo;
     uint64_t* ka = keys + lo;
     uint32_t* va = out.vals + lo;

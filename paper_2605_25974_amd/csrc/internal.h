@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,29 @@
 namespace pauli {
 constexpr int kMaxWordsHost = 16;  // n <= 1024
 }
+
+namespace pauli {
+// One device block of SoA arrays X, Z [W][ld], phase, coefficients and
+// fingerprints [ld], shared by several sums that are views into it (the
+// outputs of a batched launch sequence); released with the last of them.
+struct SharedBlock {
+  SharedBlock(int W, int64_t ld, int32_t dtype, hipStream_t s);
+  ~SharedBlock();
+  SharedBlock(const SharedBlock&) = delete;
+  SharedBlock& operator=(const SharedBlock&) = delete;
+  int W = 0;
+  int64_t ld = 0;
+  int32_t dtype = 0;
+  hipStream_t s = nullptr;
+  void* block = nullptr;
+  size_t bytes = 0;
+  uint64_t* X = nullptr;
+  uint64_t* Z = nullptr;
+  uint8_t* ph = nullptr;
+  void* coef = nullptr;
+  uint64_t* fp = nullptr;
+};
+}  // namespace pauli
 
 struct paulisum {
   int32_t n = 0, W = 0;
@@ -29,6 +53,7 @@ struct paulisum {
   uint64_t* fp = nullptr; // [ld]
   hipStream_t last_stream = nullptr;
   bool borrowed = false;  // arrays owned by the caller of pauli_merge_into
+  std::shared_ptr<pauli::SharedBlock> shared;  // a view into a shared block
 };
 
 namespace pauli {
@@ -91,8 +116,16 @@ inline size_t coef_bytes(int32_t t) { return t == PAULI_C64 ? 8 : 16; }
 // Allocates a container with capacity ld (>= m) on the current device.
 paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s);
 void free_sum(paulisum* p);
+// A sum of m terms on n qubits that are terms [first, first + m) of b.
+paulisum* sum_view(const std::shared_ptr<SharedBlock>& b, int n, int64_t first, int64_t m);
 
 // ---------------------------------------------------------------- profiling
+// While a NoEvents guard lives on the calling thread, stages record no
+// events (a launch sequence being captured into a graph).
+struct NoEvents {
+  NoEvents();
+  ~NoEvents();
+};
 // Records HIP events around a stage on its stream while profiling is on.
 struct StageScope {
   StageScope(int stage, hipStream_t s, double bytes);
@@ -224,6 +257,24 @@ paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
 // followed by the merge o.  px, pz: host words of the rotation string.
 paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
                       int mode, const MergeArgs& o, bool sorted_input, hipStream_t st);
+
+// k_batched.hip: the batched form.  A plan holds the buffers, tables and
+// (with use_graph) the captured HIP graph of the launch sequence that forms
+// merge(a[t] * b[t]) for every t; shape fixes the launch shape, else each
+// class's shape is autotuned (or taken from the tune table).  run enqueues the sequence on st; results waits for it and
+// returns each product's sum (views into the plan's output blocks, which
+// the plan then no longer uses).
+struct BatchPlan;
+struct BatchShape {  // fixed launch shape (0 = the default of a field)
+  int bucket_bits = 0, bucket_records = 0, class_bits = 0, expand_parts = 0;
+};
+BatchPlan* batch_plan_create(int nb, paulisum* const* a, paulisum* const* b, const MergeArgs& o,
+                             const BatchShape* shape, bool use_graph, hipStream_t st);
+void batch_plan_run(BatchPlan* plan, hipStream_t st);
+void batch_plan_results(BatchPlan* plan, paulisum** out, hipStream_t st);
+void batch_plan_destroy(BatchPlan* plan);
+int batch_tune_save(const char* path);
+int batch_tune_load(const char* path);
 
 // k_fused.hip: merge(a*b) by the staged fused pipeline; nullptr when a
 // fingerprint collision asks for merge_generic instead.

@@ -83,17 +83,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   const uint32_t nc = 1u << d1;
   const uint32_t nbk = 1u << d;
   const int rem = kb - d;  // key bits below the bucket bits
-  SortField sf;
-  sf.lo14 = rem >= kBinBits ? rem - kBinBits : -1;
-  if (rem >= 16) {
-    sf.lo16 = rem - 16;
-    sf.passes = 2;
-    sf.fmask = 0xFFFFull;
-  } else {
-    sf.lo16 = 0;
-    sf.passes = (rem + 7) / 8;
-    sf.fmask = rem ? ((1ull << rem) - 1) : 0ull;
-  }
+  const SortField sf = sort_field_for(rem);
 
   // pair id: (j << ibits) | i when that fits in 32 bits, else j*|a| + i
   int ibits = 0;
@@ -149,12 +139,13 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                   A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
                   Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
                   Tt.as<uint32_t>(), static_cast<uint32_t>(a->m), ibits, d1};
-      hipLaunchKernelGGL(k_gcount, dim3(gb), dim3(kB), 0, s, gs, S.as<uint32_t>(),
+      hipLaunchKernelGGL(k_gcount, dim3(gb), dim3(kB), 0, s, gs, GenBatch{}, S.as<uint32_t>(),
                          tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       DBuf w3(scan_workspace_bytes(static_cast<int64_t>(gb) * 256), s);
       scan_exclusive_u32(C.as<uint32_t>(), C.as<uint32_t>(), static_cast<int64_t>(gb) * 256,
                          nullptr, w3.p, s);
-      hipLaunchKernelGGL(k_gscatter, dim3(gb), dim3(kB), 0, s, gs, K2, V2, S.as<uint32_t>(),
+      hipLaunchKernelGGL(k_gscatter, dim3(gb), dim3(kB), 0, s, gs, GenBatch{}, K2, V2,
+                         S.as<uint32_t>(),
                          tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       hipLaunchKernelGGL(k_bucket_offsets, dim3(grid_for(nbk + 1)), dim3(kB), 0, s,
                          soff.as<uint32_t>(), tb.as<uint32_t>(), C.as<uint32_t>(), d2, nbk, nc,
@@ -178,19 +169,20 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
     if (sf.lo14 >= 0) {
       // the buckets the counting sort gives up on take the radix sort
       hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
-                         nbk, sf, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(), ctr32 + 6);
+                         nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),
+                         ctr32 + 6);
       // (usually none: a few blocks)
       hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, K,
-                         boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, so,
+                         boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, SortBatch{}, so,
                          heavy.as<uint32_t>(), ctr32);
     } else {
       hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
-                         nbk, nullptr, nullptr, sf, so, heavy.as<uint32_t>(), ctr32);
+                         nbk, nullptr, nullptr, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32);
     }
     // one block per compute unit: a workload of many equal strings can make
     // most buckets heavy
     hipLaunchKernelGGL(k_heavy_sort, dim3(gsort), dim3(kSortNT), 0, s, K, K2, V2,
-                       boff.as<uint32_t>(), rem, heavy.as<uint32_t>(), ctr32, so);
+                       boff.as<uint32_t>(), rem, SortBatch{}, heavy.as<uint32_t>(), ctr32, so);
     PAULI_HIP(hipGetLastError());
     DBuf w(scan_workspace_bytes(nbk), s);
     scan_exclusive_u32(nseg.as<uint32_t>(), segoff.as<uint32_t>(), nbk,
@@ -318,32 +310,23 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                      nbk, boff.as<uint32_t>());
   PAULI_HIP(hipGetLastError());
   const int rem = key_bits - d;
-  SortField sf;
-  sf.lo14 = rem >= kBinBits ? rem - kBinBits : -1;
-  if (rem >= 16) {
-    sf.lo16 = rem - 16;
-    sf.passes = 2;
-    sf.fmask = 0xFFFFull;
-  } else {
-    sf.lo16 = 0;
-    sf.passes = (rem + 7) / 8;
-    sf.fmask = rem ? ((1ull << rem) - 1) : 0ull;
-  }
+  const SortField sf = sort_field_for(rem);
   SegOut so{V, nullptr, nullptr, nullptr, nullptr, K};
   StageScope sc(PAULI_STAGE_SORT, s, n * 24.0);
   const uint32_t gsort = nbk < device_cus() ? nbk : device_cus();
   if (sf.lo14 >= 0) {
     hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
-                       nbk, sf, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(), ctr32 + 6);
+                       nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),
+                         ctr32 + 6);
     hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, K,
-                       boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, so,
+                       boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, SortBatch{}, so,
                        heavy.as<uint32_t>(), ctr32);
   } else {
     hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
-                       nbk, nullptr, nullptr, sf, so, heavy.as<uint32_t>(), ctr32);
+                       nbk, nullptr, nullptr, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32);
   }
   hipLaunchKernelGGL(k_heavy_sort, dim3(gsort), dim3(kSortNT), 0, s, K, K2, V2,
-                     boff.as<uint32_t>(), rem, heavy.as<uint32_t>(), ctr32, so);
+                     boff.as<uint32_t>(), rem, SortBatch{}, heavy.as<uint32_t>(), ctr32, so);
   PAULI_HIP(hipGetLastError());
   return alt;
 }

@@ -48,8 +48,13 @@ void flush_locked() {
 }
 }  // namespace
 
+thread_local int g_no_events = 0;
+NoEvents::NoEvents() { ++g_no_events; }
+NoEvents::~NoEvents() { --g_no_events; }
+
 StageScope::StageScope(int st, hipStream_t str, double by) : stage(st), s(str), bytes(by) {
-  if (workspace_active()) return;  // a call that allocates nothing creates no events
+  // a call that allocates nothing creates no events, nor does a capture
+  if (workspace_active() || g_no_events) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   a = take_event();

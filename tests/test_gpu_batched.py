@@ -76,3 +76,91 @@ def test_batched_errors_and_empty():
     with pytest.raises(pl.PauliError) as e:
         pl.outer_product_batched([GA], [GB], tune=17)
     assert e.value.status == "INVALID"
+
+
+def _pairs_mixed():
+    """Mixed widths and precisions, a sum times itself, an empty side."""
+    plan = [(64, 120, 300), (500, 250, 90), (128, 33, 410), (256, 200, 200), (500, 1, 77),
+            (64, 300, 1), (130, 150, 170)]
+    pairs = [synth.workload4_batch(200 + b, n, m1, m2) for b, (n, m1, m2) in enumerate(plan)]
+    for k in (1, 3, 6):  # complex128 products in the same batch
+        A, B = pairs[k]
+        pairs[k] = (dict(A, coef=A["coef"].astype(np.complex128)),
+                    dict(B, coef=B["coef"].astype(np.complex128)))
+    G = [(pl.PauliSum.from_dict(A), pl.PauliSum.from_dict(B)) for A, B in pairs]
+    # a sum times itself (one handle on both sides), and an empty right side
+    S = synth.workload4_batch(300, 256, 180, 1)[0]
+    GS = pl.PauliSum.from_dict(S)
+    E = {"n": 64, "x": np.zeros((0, 1), np.uint64), "z": np.zeros((0, 1), np.uint64),
+         "phase": None, "coef": np.zeros(0, np.complex64)}
+    pairs += [(S, S), (pairs[0][0], E)]
+    G += [(GS, GS), (G[0][0], pl.PauliSum.from_dict(E))]
+    return pairs, [a for a, _ in G], [b for _, b in G]
+
+
+def test_batched_plan_graph_replays_match_oracle():
+    """The plan's graph is replayed three times (results taken after the
+    second and third runs, the second run writing fresh output blocks);
+    every product equals the oracle and the single fused call."""
+    pairs, GA, GB = _pairs_mixed()
+    P = pl.BatchPlan(GA, GB, mode=pl.COMPENSATED, tau=0.3)
+    P.run()
+    P.run()
+    first = P.results()
+    P.run()
+    second = P.results()
+    P.destroy()
+    for t, ((A, B), o1, o2) in enumerate(zip(pairs, first, second)):
+        g1, g2 = o1.export(), o2.export()
+        one = pl.outer_product_merged(GA[t], GB[t], mode=pl.COMPENSATED, tau=0.3).export()
+        for k in ("x", "z", "fp", "phase"):
+            assert np.array_equal(g1[k], one[k]), (t, k)
+            assert np.array_equal(g2[k], one[k]), (t, k)
+        assert np.array_equal(g1["coef"].view(np.uint32), one["coef"].view(np.uint32))
+        assert np.array_equal(g2["coef"].view(np.uint32), one["coef"].view(np.uint32))
+        ref = O.product_merge(_osum(A), _osum(B))
+        parity.assert_compensated(g1, ref, input_rounding=A["coef"].dtype == np.complex128)
+    # results stay valid after the plan is gone; results without a run fail
+    assert all(o.m >= 0 for o in first)
+    P2 = pl.BatchPlan(GA[:2], GB[:2])
+    with pytest.raises(pl.PauliError) as e:
+        P2.results()
+    assert e.value.status == "INVALID"
+
+
+@pytest.mark.parametrize("shape", [{"bucket_records": 300}, {"bucket_records": 8000, "class_bits": 2},
+                                   {"expand_parts": 1}, {"expand_parts": 8, "class_bits": 5}])
+def test_batched_launch_shapes(shape):
+    """Every launch shape computes the same products (FP64 against the
+    oracle; the sum times itself and the empty side included)."""
+    pairs, GA, GB = _pairs_mixed()
+    outs = pl.outer_product_batched(GA, GB, tune=shape)
+    for (A, B), o in zip(pairs, outs):
+        g = o.export()
+        ref = O.product_merge(_osum(A), _osum(B))
+        if A["coef"].dtype == np.complex128:
+            parity.assert_merged_fp64(g, ref)
+        else:  # complex64 inputs, plain FP32 sums
+            gi, ri = parity.align(g["x"], g["z"], ref.x, ref.z)
+            err = np.abs(g["coef"][gi] - ref.coef[ri])
+            assert np.all(err <= 1e-5 * np.maximum(ref.mass[ri], 1e-30))
+        parity.assert_sorted_by_key(g)
+
+
+def test_batched_drop_and_tune_file(tmp_path):
+    pairs, GA, GB = _pairs_mixed()
+    outs = pl.outer_product_batched(GA, GB, drop_abs=0.05)
+    for (A, B), o in zip(pairs, outs):
+        ref = O.product_merge(_osum(A), _osum(B), drop_abs=0.05)
+        g = o.export()
+        gi, ri = parity.align(g["x"], g["z"], ref.x, ref.z)
+    f = tmp_path / "tune.txt"
+    pl.tune_save(str(f))
+    text = f.read_text()
+    assert text.startswith("#") and len(text.splitlines()) >= 2
+    pl.tune_load(str(f))
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 2 3\n")
+    with pytest.raises(pl.PauliError) as e:
+        pl.tune_load(str(bad))
+    assert e.value.status == "INVALID"
