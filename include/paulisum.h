@@ -332,6 +332,35 @@ pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
                                const uint64_t* p_z, const double* theta, int32_t rotate_mode,
                                const pauli_merge_opts_t* opts, paulisum_t* out, void* stream);
 
+/* Propagation plans: the loop of pauli_propagate captured once into a HIP
+ * graph (Section III-B eq. (5) and its truncation, step after step) with
+ * every size kept on the device, so a run has no host synchronisation.
+ * The input is first merged (so the state is in key order from the start;
+ * the same sum as pauli_propagate up to the summation order of the first
+ * step), then each step is merged into the next state.  Every state holds
+ * at most max_terms terms; the plan allocates two such states (three in
+ * the compensated mode, whose last step writes C64) and the temporaries of
+ * one step (about 200 bytes per term of max_terms).
+ *  pauli_propagate_plan_create  arguments as pauli_propagate plus
+ *      max_terms (1..2^31-1); s must stay alive and unchanged while the plan
+ *      exists; the rotation strings and angles are copied.
+ *  pauli_propagate_plan_run     launches the graph, ordered after earlier
+ *      work on `stream` and before later work on it.
+ *  pauli_propagate_plan_result  waits for the last run and returns its
+ *      state (the plan allocates a new state and captures again at its next
+ *      run); CAPACITY if a state would have exceeded max_terms; INVALID if
+ *      the plan has not run since its last result.
+ *  pauli_propagate_plan_destroy releases the plan (NULL is allowed). */
+typedef struct pauli_propagate_plan* pauli_propagate_plan_t;
+pauli_status_t pauli_propagate_plan_create(paulisum_t s, int32_t steps, const uint64_t* p_x,
+                                           const uint64_t* p_z, const double* theta,
+                                           int32_t rotate_mode, const pauli_merge_opts_t* opts,
+                                           int64_t max_terms, void* stream,
+                                           pauli_propagate_plan_t* out);
+pauli_status_t pauli_propagate_plan_run(pauli_propagate_plan_t plan, void* stream);
+pauli_status_t pauli_propagate_plan_result(pauli_propagate_plan_t plan, paulisum_t* out);
+pauli_status_t pauli_propagate_plan_destroy(pauli_propagate_plan_t plan);
+
 /* Replaces the device allocator used for every buffer the library makes
  * (NULL, NULL restores the default: the library's own arena, which reserves
  * memory from the runtime in chunks of at least 256 MiB, hands out blocks by

@@ -32,6 +32,8 @@ EXPORTS = (
     "pauli_trim_memory", "pauli_commutator", "pauli_apply_clifford", "pauli_sort_lex",
     "pauli_merge_into", "pauli_batch_plan_create", "pauli_batch_plan_run",
     "pauli_batch_plan_results", "pauli_batch_plan_destroy", "pauli_tune_save", "pauli_tune_load",
+    "pauli_propagate_plan_create", "pauli_propagate_plan_run", "pauli_propagate_plan_result",
+    "pauli_propagate_plan_destroy",
 )
 STAGES = ("outer_product", "prep", "sort", "segment", "write", "long", "clifford", "lex",
           "filter")
@@ -126,6 +128,16 @@ def lib():
     L.pauli_tune_save.argtypes = [ctypes.c_char_p]
     L.pauli_tune_load.restype = st
     L.pauli_tune_load.argtypes = [ctypes.c_char_p]
+    L.pauli_propagate_plan_create.restype = st
+    L.pauli_propagate_plan_create.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32,
+                                              ctypes.POINTER(MergeOpts), ctypes.c_int64, _vp,
+                                              ctypes.POINTER(_vp)]
+    L.pauli_propagate_plan_run.restype = st
+    L.pauli_propagate_plan_run.argtypes = [_vp, _vp]
+    L.pauli_propagate_plan_result.restype = st
+    L.pauli_propagate_plan_result.argtypes = [_vp, ctypes.POINTER(_vp)]
+    L.pauli_propagate_plan_destroy.restype = st
+    L.pauli_propagate_plan_destroy.argtypes = [_vp]
     L.pauli_trim_memory.restype = st
     L.pauli_trim_memory.argtypes = []
     L.pauli_propagate.restype = st
@@ -434,6 +446,48 @@ class BatchPlan:
     def destroy(self):
         if getattr(self, "_h", None) and self._h.value:
             _check(lib().pauli_batch_plan_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class PropagatePlan:
+    """pauli_propagate_plan_*: the propagation loop captured into a HIP
+    graph, every state holding at most max_terms terms.  The plan keeps a
+    reference to its input sum."""
+
+    def __init__(self, s, px, pz, theta, max_terms, rotate_mode=ROTATE_CONJUGATE, mode=PLAIN,
+                 drop_abs=-1.0, tau=0.0, key_bits=0, stream=None):
+        self._input = s
+        W = _words(s.info()[0])
+        px = np.ascontiguousarray(px, dtype=np.uint64).reshape(-1, W)
+        pz = np.ascontiguousarray(pz, dtype=np.uint64).reshape(-1, W)
+        th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+        if not (px.shape[0] == pz.shape[0] == th.size):
+            raise ValueError("px, pz and theta must have one entry per step")
+        o = _opts(mode, drop_abs, tau, key_bits)
+        h = _vp()
+        _check(lib().pauli_propagate_plan_create(s.handle, int(th.size), px.ctypes.data,
+                                                 pz.ctypes.data, th.ctypes.data, int(rotate_mode),
+                                                 ctypes.byref(o), int(max_terms),
+                                                 _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().pauli_propagate_plan_run(self._h, _stream(stream)))
+
+    def result(self):
+        out = _vp()
+        _check(lib().pauli_propagate_plan_result(self._h, ctypes.byref(out)))
+        return PauliSum(out)
+
+    def destroy(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().pauli_propagate_plan_destroy(self._h))
             self._h = _vp()
 
     def __del__(self):

@@ -95,6 +95,24 @@ struct WorkspaceGuard {
 
 bool workspace_active() { return g_ws != nullptr; }
 
+ScratchScope::ScratchScope(void* base, size_t bytes) : ws_(new Workspace) {
+  if (g_ws) {
+    delete static_cast<Workspace*>(ws_);
+    fail(PAULI_ERR_DEVICE, "nested scratch regions");
+  }
+  Workspace* w = static_cast<Workspace*>(ws_);
+  w->base = static_cast<char*>(base);
+  w->size = bytes;
+  w->out_taken = true;  // no result container: every merge writes to a given state
+  g_ws = w;
+}
+ScratchScope::~ScratchScope() {
+  g_ws = nullptr;
+  delete static_cast<Workspace*>(ws_);
+}
+void ScratchScope::rewind() { static_cast<Workspace*>(ws_)->used = 0; }
+size_t ScratchScope::used() const { return static_cast<Workspace*>(ws_)->used; }
+
 void* dalloc(size_t bytes, hipStream_t s) {
   if (bytes == 0) return nullptr;
   bytes = (bytes + 255) & ~size_t(255);
@@ -143,7 +161,7 @@ paulisum* new_sum(int n, int64_t m, int64_t ld, int32_t dt, hipStream_t s) {
   if (g_ws) {
     // the result of a call that allocates nothing: the caller's arrays
     paulisum* p = &g_ws->out;
-    if (g_ws->out_taken) fail(PAULI_ERR_DEVICE, "a second result in a call without allocation");
+    if (g_ws->out_taken) fail(PAULI_ERR_DEVICE, "a result container inside a fixed scratch region");
     if (n != p->n || dt != p->dtype) fail(PAULI_ERR_DEVICE, "result shape differs from the output");
     if (m > p->ld)
       fail(PAULI_ERR_CAPACITY, "the result has " + std::to_string(m) +
@@ -312,6 +330,21 @@ BatchShape batch_shape(const pauli_tune_t* t) {
   b.class_bits = t->class_bits;
   b.expand_parts = t->expand_parts;
   return b;
+}
+
+void check_rotations(const paulisum* s, int32_t steps, const uint64_t* p_x, const uint64_t* p_z,
+                     const double* theta, int32_t rotate_mode) {
+  if (steps < 0) fail(PAULI_ERR_INVALID, "steps is negative");
+  if (steps > 0 && (!p_x || !p_z || !theta))
+    fail(PAULI_ERR_INVALID, "p_x, p_z and theta must not be NULL");
+  if (rotate_mode != PAULI_ROTATE_PRODUCT && rotate_mode != PAULI_ROTATE_CONJUGATE)
+    fail(PAULI_ERR_INVALID, "unknown rotate_mode " + std::to_string(rotate_mode));
+  const int W = s->W;
+  const int tail = s->n - 64 * (W - 1);
+  const uint64_t pad = tail == 64 ? 0 : ~((uint64_t(1) << tail) - 1);
+  for (int32_t t = 0; t < steps; ++t)
+    if ((p_x[static_cast<size_t>(t) * W + W - 1] | p_z[static_cast<size_t>(t) * W + W - 1]) & pad)
+      fail(PAULI_ERR_INVALID, "rotation string " + std::to_string(t) + " has a bit at or above n");
 }
 
 void check_batch(int32_t nb, const paulisum_t* a, const paulisum_t* b, const pauli_merge_opts_t* o) {
@@ -699,18 +732,9 @@ pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
   return guarded([&] {
     if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
     check_sum(s, "s");
-    if (steps < 0) fail(PAULI_ERR_INVALID, "steps is negative");
-    if (steps > 0 && (!p_x || !p_z || !theta))
-      fail(PAULI_ERR_INVALID, "p_x, p_z and theta must not be NULL");
-    if (rotate_mode != PAULI_ROTATE_PRODUCT && rotate_mode != PAULI_ROTATE_CONJUGATE)
-      fail(PAULI_ERR_INVALID, "unknown rotate_mode " + std::to_string(rotate_mode));
-    const int W = s->W;
-    const int tail = s->n - 64 * (W - 1);
-    const uint64_t pad = tail == 64 ? 0 : ~((uint64_t(1) << tail) - 1);
-    for (int32_t t = 0; t < steps; ++t)
-      if ((p_x[static_cast<size_t>(t) * W + W - 1] | p_z[static_cast<size_t>(t) * W + W - 1]) & pad)
-        fail(PAULI_ERR_INVALID, "rotation string " + std::to_string(t) + " has a bit at or above n");
+    check_rotations(s, steps, p_x, p_z, theta, rotate_mode);
     const MergeArgs m = merge_args(opts);
+    const int W = s->W;
     use_device(s);
     hipStream_t st = as_stream(stream);
     s->last_stream = st;
@@ -748,6 +772,45 @@ pauli_status_t pauli_propagate(paulisum_t s, int32_t steps, const uint64_t* p_x,
     }
     *out = cur;
   });
+}
+
+pauli_status_t pauli_propagate_plan_create(paulisum_t s, int32_t steps, const uint64_t* p_x,
+                                           const uint64_t* p_z, const double* theta,
+                                           int32_t rotate_mode, const pauli_merge_opts_t* opts,
+                                           int64_t max_terms, void* stream,
+                                           pauli_propagate_plan_t* out) {
+  return guarded([&] {
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    check_sum(s, "s");
+    check_rotations(s, steps, p_x, p_z, theta, rotate_mode);
+    if (max_terms < 1 || max_terms > 0x7FFFFFFFll)
+      fail(PAULI_ERR_INVALID, "max_terms must be in 1..2^31-1");
+    const MergeArgs m = merge_args(opts);
+    use_device(s);
+    hipStream_t st = as_stream(stream);
+    s->last_stream = st;
+    *out = reinterpret_cast<pauli_propagate_plan_t>(
+        prop_plan_create(s, steps, p_x, p_z, theta, rotate_mode, m, max_terms, st));
+  });
+}
+
+pauli_status_t pauli_propagate_plan_run(pauli_propagate_plan_t plan, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(PAULI_ERR_INVALID, "plan is NULL");
+    prop_plan_run(reinterpret_cast<PropPlan*>(plan), as_stream(stream));
+  });
+}
+
+pauli_status_t pauli_propagate_plan_result(pauli_propagate_plan_t plan, paulisum_t* out) {
+  return guarded([&] {
+    if (!plan) fail(PAULI_ERR_INVALID, "plan is NULL");
+    if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
+    *out = prop_plan_result(reinterpret_cast<PropPlan*>(plan));
+  });
+}
+
+pauli_status_t pauli_propagate_plan_destroy(pauli_propagate_plan_t plan) {
+  return guarded([&] { prop_plan_destroy(reinterpret_cast<PropPlan*>(plan)); });
 }
 
 pauli_status_t pauli_set_allocator(pauli_alloc_fn alloc, pauli_free_fn free_fn, void* ctx) {

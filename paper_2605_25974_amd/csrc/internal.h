@@ -82,6 +82,23 @@ void dfree(void* p, size_t bytes, hipStream_t s);
 // caller's output arrays, and stage timing records no events.
 bool workspace_active();
 
+// While alive on the calling thread, temporaries (dalloc) come from the
+// device region [base, base + bytes) as they do for pauli_merge_into, with
+// no result container (CAPACITY when the region is exhausted).  rewind()
+// hands the region out again from its start (the caller orders the reuse).
+class ScratchScope {
+ public:
+  ScratchScope(void* base, size_t bytes);
+  ~ScratchScope();
+  ScratchScope(const ScratchScope&) = delete;
+  ScratchScope& operator=(const ScratchScope&) = delete;
+  void rewind();
+  size_t used() const;
+
+ private:
+  void* ws_;
+};
+
 // RAII device buffer freed (stream-ordered) when it leaves scope.
 struct DBuf {
   void* p = nullptr;
@@ -163,8 +180,11 @@ void launch_prep_side(const paulisum* t, uint64_t* rows, uint8_t* e, hipStream_t
 // k_sort.hip
 size_t scan_workspace_bytes(int64_t n);
 // out[i] = sum_{j<i} in[i]; *total (device) = sum of all; in may alias out.
+// Device counts: with nd, the element count is *nd (device memory, read by
+// the kernels) and n is only the host's upper bound of it (grid sizes and
+// workspaces); likewise below.
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                        void* work, hipStream_t s);
+                        void* work, hipStream_t s, const uint32_t* nd = nullptr);
 size_t radix_workspace_bytes(int64_t n);
 // Stable LSD radix sort of (key, val) by key bits [0, key_bits).  The sorted
 // result ends up in (keys, vals) or (keys_alt, vals_alt): returns true if in
@@ -172,11 +192,12 @@ size_t radix_workspace_bytes(int64_t n);
 // the same for every key and is not sorted on.
 bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                       int64_t n, int key_bits, void* work, hipStream_t s,
-                      uint64_t vary = ~0ull);
+                      uint64_t vary = ~0ull, const uint32_t* nd = nullptr);
 // Stable passes on the 8-bit digits at the given shifts, in order (a key's
 // digit is (key >> shift) & 255).  Same result convention.
 bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                   int64_t n, const int* shifts, int nshifts, void* work, hipStream_t s);
+                   int64_t n, const int* shifts, int nshifts, void* work, hipStream_t s,
+                   const uint32_t* nd = nullptr);
 
 // k_fused.hip: (key, val) records of a key_bits-bit key put in key order by
 // a partition on the top key bits and an LDS sort per bucket, for uniformly
@@ -185,7 +206,8 @@ bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
 // the same order when the vals ascend in input order).  Small inputs take
 // radix_sort_pairs.  Same result convention as radix_sort_pairs.
 bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
-                           uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s);
+                           uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s,
+                           const uint32_t* nd = nullptr);
 
 // k_merge.hip
 // Internal merge mode: the precision form on float-float record values (a
@@ -200,8 +222,22 @@ struct MergeArgs {
   int bucket_bits = 0;  // fused pipeline: 0 = the size heuristic
   int comm = 0;         // the commutator [a, b] instead of the product
 };
-// merge(a*b) (pair source) or merge(s) (term source, b == nullptr).
-paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s);
+// Device-count form of a merge (a step of a captured propagation loop):
+// the record count is *N on the device (the host passes its upper bound;
+// null: the host count), the merged terms go to `into` (capacity into->ld)
+// and their number to *U (device); a result larger than the capacity is
+// cut and sets *flag.  No host synchronisation.
+struct DevRun {
+  const uint32_t* N = nullptr;
+  paulisum* into = nullptr;
+  uint32_t* U = nullptr;
+  uint32_t* flag = nullptr;
+};
+
+// merge(a*b) (pair source) or merge(s) (term source, b == nullptr; with dv,
+// written to a state as DevRun says).
+paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s,
+                        const DevRun* dv = nullptr);
 
 // merge(a) from records (key = fingerprint >> (64 - o.key_bits), index of a
 // term of a), one per term, already in key order (equal keys adjacent).
@@ -251,7 +287,7 @@ struct RotString {
 // (equal keys adjacent), used as scratch.
 paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
                         const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
-                        const MergeArgs& o, hipStream_t st);
+                        const MergeArgs& o, hipStream_t st, const DevRun* dv = nullptr);
 
 // k_rotate.hip: one rotation step (product or conjugation semantics),
 // followed by the merge o.  px, pz: host words of the rotation string.
@@ -275,6 +311,16 @@ void batch_plan_results(BatchPlan* plan, paulisum** out, hipStream_t st);
 void batch_plan_destroy(BatchPlan* plan);
 int batch_tune_save(const char* path);
 int batch_tune_load(const char* path);
+
+// k_rotate.hip: propagation plans (pauli_propagate_plan_*): the loop of
+// pauli_propagate in device-count form, captured into one HIP graph.
+struct PropPlan;
+PropPlan* prop_plan_create(const paulisum* s, int steps, const uint64_t* px, const uint64_t* pz,
+                           const double* theta, int mode, const MergeArgs& o, int64_t cap,
+                           hipStream_t st);
+void prop_plan_run(PropPlan* pl, hipStream_t st);
+paulisum* prop_plan_result(PropPlan* pl);
+void prop_plan_destroy(PropPlan* pl);
 
 // k_fused.hip: merge(a*b) by the staged fused pipeline; nullptr when a
 // fingerprint collision asks for merge_generic instead.

@@ -265,8 +265,10 @@ namespace {
 
 // boff[b] = first record whose key has top bits >= b (keys in bucket order),
 // boff[nbk] = n.
-__global__ void k_bucket_bounds(const uint64_t* __restrict__ keys, int64_t n, int shift,
-                                uint32_t nbk, uint32_t* __restrict__ boff) {
+__global__ void k_bucket_bounds(const uint64_t* __restrict__ keys, int64_t n,
+                                const uint32_t* __restrict__ nd, int shift, uint32_t nbk,
+                                uint32_t* __restrict__ boff) {
+  if (nd && *nd < n) n = *nd;  // the device count, clamped to the host bound
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= n;
        r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t cur = r < n ? static_cast<int64_t>(keys[r] >> shift) : nbk;
@@ -278,16 +280,17 @@ __global__ void k_bucket_bounds(const uint64_t* __restrict__ keys, int64_t n, in
 }  // namespace
 
 bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
-                           uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s) {
+                           uint32_t* vals_alt, int64_t n, int key_bits, hipStream_t s,
+                           const uint32_t* nd) {
   // small sorts: the radix passes (the bucket pipeline's fixed costs dominate)
   if (n < (int64_t(1) << 16) || key_bits < 24 || n > 0xFFFFFFFFll) {
     DBuf w(radix_workspace_bytes(n), s);
-    return radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, key_bits, w.p, s);
+    return radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, key_bits, w.p, s, ~0ull, nd);
   }
   const int d = fused_default_bucket_bits(n, key_bits);
   if (d == 0) {
     DBuf w(radix_workspace_bytes(n), s);
-    return radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, key_bits, w.p, s);
+    return radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, key_bits, w.p, s, ~0ull, nd);
   }
   const uint32_t nbk = 1u << d;
   bool alt = false;
@@ -297,7 +300,7 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     shifts[ns++] = key_bits - d;
     if (d > 8) shifts[ns++] = key_bits - d + 8;
     DBuf w(radix_workspace_bytes(n), s);
-    alt = radix_sort_at(keys, vals, keys_alt, vals_alt, n, shifts, ns, w.p, s);
+    alt = radix_sort_at(keys, vals, keys_alt, vals_alt, n, shifts, ns, w.p, s, nd);
   }
   uint64_t* K = alt ? keys_alt : keys;
   uint32_t* V = alt ? vals_alt : vals;
@@ -306,8 +309,8 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   DBuf boff((nbk + 1) * 4ull, s), ctr(64, s), heavy(nbk * 4ull, s), redo(nbk * 4ull, s);
   uint32_t* ctr32 = ctr.as<uint32_t>();  // [0] heavy count [6] radix redo count
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctr32, 16u, 0u);
-  hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for(n + 1)), dim3(kB), 0, s, K, n, key_bits - d,
-                     nbk, boff.as<uint32_t>());
+  hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for(n + 1)), dim3(kB), 0, s, K, n, nd,
+                     key_bits - d, nbk, boff.as<uint32_t>());
   PAULI_HIP(hipGetLastError());
   const int rem = key_bits - d;
   const SortField sf = sort_field_for(rem);

@@ -69,9 +69,10 @@ __global__ void k_term_records(const uint64_t* __restrict__ f, int64_t m, int ks
 template <int WT, typename TV, typename Src>
 __global__ void __launch_bounds__(kBlock)
 k_heads(Src src, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t N,
-        uint32_t* __restrict__ head, cplx<TV>* __restrict__ v, uint32_t* __restrict__ dirty,
-        int second_pass) {
+        const uint32_t* __restrict__ nd, uint32_t* __restrict__ head, cplx<TV>* __restrict__ v,
+        uint32_t* __restrict__ dirty, int second_pass) {
   if (second_pass && *dirty == 0) return;
+  if (nd && *nd < N) N = *nd;  // the device count, clamped to the host bound
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
        r += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t id = vals[r];
@@ -93,8 +94,9 @@ k_heads(Src src, const uint64_t* __restrict__ keys, const uint32_t* __restrict__
 template <int WT, typename Src>
 __global__ void k_fix_runs(Src src, const uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                            const uint32_t* __restrict__ head, int64_t N,
-                           const uint32_t* __restrict__ dirty) {
+                           const uint32_t* __restrict__ nd, const uint32_t* __restrict__ dirty) {
   if (*dirty == 0) return;
+  if (nd && *nd < N) N = *nd;
   uint64_t a[2 * WT], b[2 * WT];
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
        r += (int64_t)gridDim.x * blockDim.x) {
@@ -124,8 +126,9 @@ __global__ void k_fix_runs(Src src, const uint64_t* __restrict__ keys, uint32_t*
 }
 
 __global__ void k_seg_starts(const uint32_t* __restrict__ head, const uint32_t* __restrict__ segid,
-                             int64_t N, const uint32_t* __restrict__ nseg,
-                             uint32_t* __restrict__ seg_start) {
+                             int64_t N, const uint32_t* __restrict__ nd,
+                             const uint32_t* __restrict__ nseg, uint32_t* __restrict__ seg_start) {
+  if (nd && *nd < N) N = *nd;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N;
        r += (int64_t)gridDim.x * blockDim.x)
     if (head[r]) seg_start[segid[r]] = static_cast<uint32_t>(r);
@@ -252,6 +255,7 @@ k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __res
        u += (int64_t)gridDim.x * blockDim.x) {
     if (!keep[u]) continue;
     const int64_t o = outidx[u];
+    if (o >= ldo) continue;  // past a state's capacity (flagged by the caller)
     const uint32_t id = vals[seg_start[u]];
     src.string(id, w);
 #pragma unroll
@@ -271,9 +275,19 @@ k_write_output(Src src, const uint32_t* __restrict__ vals, const uint32_t* __res
 // presorted: the records are already in key order (equal keys adjacent).
 // MODE kFF (record values in float-float) writes a float-float sum when
 // o.ff_out is set, else a C64 sum rounded from it.
+// A result count cut to a state's capacity; the flag records the cut.
+__global__ void k_take_count(const uint32_t* __restrict__ U, uint32_t cap,
+                             uint32_t* __restrict__ out, uint32_t* __restrict__ flag) {
+  const uint32_t u = *U;
+  *out = u < cap ? u : cap;
+  if (u > cap) atomicOr(flag, 1u);
+}
+
 template <int WT, typename T, int MODE, typename Src>
 paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* keys,
-                       uint32_t* vals, const MergeArgs& o, hipStream_t s, bool presorted = false) {
+                       uint32_t* vals, const MergeArgs& o, hipStream_t s, bool presorted = false,
+                       const DevRun* dv = nullptr) {
+  const uint32_t* nd = dv ? dv->N : nullptr;  // device count (N is then its bound)
   using TV = typename std::conditional<MODE == kComp, float,
                                        typename std::conditional<MODE == kFF, ff, T>::type>::type;
   if (MODE == kComp) dt = PAULI_C64;
@@ -283,7 +297,7 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
     keys_alt = DBuf(N * sizeof(uint64_t), s);
     vals_alt = DBuf(N * sizeof(uint32_t), s);
     if (sort_records_bucketed(keys, vals, keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(), N,
-                              o.key_bits, s)) {
+                              o.key_bits, s, nd)) {
       keys = keys_alt.as<uint64_t>();
       vals = vals_alt.as<uint32_t>();
     }
@@ -302,19 +316,20 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
   const unsigned g = grid_for(N);
   std::optional<StageScope> sc_seg;
   sc_seg.emplace(PAULI_STAGE_SEGMENT, s, N * (12.0 + 4.0 + sizeof(cplx<TV>)));
-  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
-                     v, ctr + 0, 0);
+  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, nd,
+                     head, v, ctr + 0, 0);
   hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, head, N,
-                     ctr + 0);
-  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, head,
-                     v, ctr + 0, 1);
+                     nd, ctr + 0);
+  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, nd,
+                     head, v, ctr + 0, 1);
   PAULI_HIP(hipGetLastError());
 
   DBuf swork(scan_workspace_bytes(N), s);
-  scan_exclusive_u32(head, segid, N, ctr + 1, swork.p, s);
+  scan_exclusive_u32(head, segid, N, ctr + 1, swork.p, s, nd);
   DBuf seg_buf((N + 1) * sizeof(uint32_t), s);
   uint32_t* seg_start = seg_buf.as<uint32_t>();
-  hipLaunchKernelGGL(k_seg_starts, dim3(g), dim3(kBlock), 0, s, head, segid, N, ctr + 1, seg_start);
+  hipLaunchKernelGGL(k_seg_starts, dim3(g), dim3(kBlock), 0, s, head, segid, N, nd, ctr + 1,
+                     seg_start);
   head_buf.reset();
 
   DBuf coef_buf(N * sizeof(cplx<TV>), s);
@@ -336,8 +351,25 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
   // affect outidx[u] for u < #segments (an exclusive scan looks backwards).
   DBuf outidx_buf(N * sizeof(uint32_t), s);
   uint32_t* outidx = outidx_buf.as<uint32_t>();
-  scan_exclusive_u32(keep, outidx, N, nullptr, swork.p, s);
+  scan_exclusive_u32(keep, outidx, N, nullptr, swork.p, s, nd);
   hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(1), 0, s, keep, outidx, ctr + 1, ctr + 2);
+  if (dv) {
+    // no host read: the terms go to the state's arrays, cut to its capacity
+    paulisum* out = dv->into;
+    hipLaunchKernelGGL(k_take_count, dim3(1), dim3(1), 0, s, ctr + 2,
+                       static_cast<uint32_t>(out->ld), dv->U, dv->flag);
+    StageScope sc_w(PAULI_STAGE_WRITE, s, 0.0);
+    if (out->dtype == PAULI_C64 && MODE == kFF)
+      hipLaunchKernelGGL((k_write_output<WT, TV, float, Src>), dim3(g), dim3(kBlock), 0, s, src,
+                         vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z, out->ph,
+                         static_cast<cplx<float>*>(out->coef), out->fp, out->ld);
+    else
+      hipLaunchKernelGGL((k_write_output<WT, TV, TV, Src>), dim3(g), dim3(kBlock), 0, s, src,
+                         vals, seg_start, ctr + 1, keep, outidx, coef, out->X, out->Z, out->ph,
+                         static_cast<cplx<TV>*>(out->coef), out->fp, out->ld);
+    PAULI_HIP(hipGetLastError());
+    return out;
+  }
 
   uint32_t host_ctr[4];
   PAULI_HIP(hipMemcpyAsync(host_ctr, ctr, sizeof(host_ctr), hipMemcpyDeviceToHost, s));
@@ -362,7 +394,8 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
 }
 
 template <int WT, typename T>
-paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s,
+                  const DevRun* dv) {
   const int kshift = 64 - o.key_bits;
   if (b == nullptr) {
     const int64_t N = a->m;
@@ -374,12 +407,12 @@ paulisum* merge_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
     TermSrc<WT, T> src{a->X, a->Z, a->ph, static_cast<const cplx<T>*>(a->coef), a->fp, a->ld, a->W};
     if (o.mode == kModeFF)
       return run_pipeline<WT, T, kFF>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
-                                       vals.as<uint32_t>(), o, s);
+                                       vals.as<uint32_t>(), o, s, false, dv);
     return o.mode == PAULI_MERGE_COMPENSATED
                ? run_pipeline<WT, T, kComp>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
-                                            vals.as<uint32_t>(), o, s)
+                                            vals.as<uint32_t>(), o, s, false, dv)
                : run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys.as<uint64_t>(),
-                                             vals.as<uint32_t>(), o, s);
+                                             vals.as<uint32_t>(), o, s, false, dv);
   }
   const int64_t N = a->m * b->m;
   const int W = a->W;
@@ -458,17 +491,18 @@ paulisum* merge_sorted_w(const paulisum* a, uint64_t* keys, uint32_t* vals, cons
 }
 
 template <typename T>
-paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s,
+                  const DevRun* dv) {
   switch (a->W) {
-    case 1: return merge_t<1, T>(a, b, o, s);
-    case 2: return merge_t<2, T>(a, b, o, s);
-    case 3: return merge_t<3, T>(a, b, o, s);
-    case 4: return merge_t<4, T>(a, b, o, s);
-    case 5: return merge_t<5, T>(a, b, o, s);
-    case 6: return merge_t<6, T>(a, b, o, s);
-    case 7: return merge_t<7, T>(a, b, o, s);
-    case 8: return merge_t<8, T>(a, b, o, s);
-    default: return merge_t<kMaxWords, T>(a, b, o, s);
+    case 1: return merge_t<1, T>(a, b, o, s, dv);
+    case 2: return merge_t<2, T>(a, b, o, s, dv);
+    case 3: return merge_t<3, T>(a, b, o, s, dv);
+    case 4: return merge_t<4, T>(a, b, o, s, dv);
+    case 5: return merge_t<5, T>(a, b, o, s, dv);
+    case 6: return merge_t<6, T>(a, b, o, s, dv);
+    case 7: return merge_t<7, T>(a, b, o, s, dv);
+    case 8: return merge_t<8, T>(a, b, o, s, dv);
+    default: return merge_t<kMaxWords, T>(a, b, o, s, dv);
   }
 }
 
@@ -616,7 +650,7 @@ namespace {
 template <int WT, typename T>
 paulisum* merge_rotated_t(const paulisum* a, const RotString& P, double theta,
                           const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
-                          const MergeArgs& o, hipStream_t s) {
+                          const MergeArgs& o, hipStream_t s, const DevRun* dv) {
   RotSrc<WT, T> src{};
   src.X = a->X;
   src.Z = a->Z;
@@ -639,25 +673,25 @@ paulisum* merge_rotated_t(const paulisum* a, const RotString& P, double theta,
   // a float-float state (the precision form) merges in float-float; a
   // stored FP64 or FP32 state in its own precision
   if constexpr (std::is_same<T, ff>::value)
-    return run_pipeline<WT, T, kFF>(src, a->n, N, a->dtype, keys, vals, o, s, true);
+    return run_pipeline<WT, T, kFF>(src, a->n, N, a->dtype, keys, vals, o, s, true, dv);
   else
-    return run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s, true);
+    return run_pipeline<WT, T, kPlain>(src, a->n, N, a->dtype, keys, vals, o, s, true, dv);
 }
 
 template <typename T>
 paulisum* merge_rotated_w(const paulisum* a, const RotString& P, double theta,
                           const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
-                          const MergeArgs& o, hipStream_t s) {
+                          const MergeArgs& o, hipStream_t s, const DevRun* dv) {
   switch (a->W) {  // the source reads exactly WT words when WT <= 8
-    case 1: return merge_rotated_t<1, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 2: return merge_rotated_t<2, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 3: return merge_rotated_t<3, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 4: return merge_rotated_t<4, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 5: return merge_rotated_t<5, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 6: return merge_rotated_t<6, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 7: return merge_rotated_t<7, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    case 8: return merge_rotated_t<8, T>(a, P, theta, cnt, keys, vals, N, o, s);
-    default: return merge_rotated_t<kMaxWords, T>(a, P, theta, cnt, keys, vals, N, o, s);
+    case 1: return merge_rotated_t<1, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 2: return merge_rotated_t<2, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 3: return merge_rotated_t<3, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 4: return merge_rotated_t<4, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 5: return merge_rotated_t<5, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 6: return merge_rotated_t<6, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 7: return merge_rotated_t<7, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    case 8: return merge_rotated_t<8, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
+    default: return merge_rotated_t<kMaxWords, T>(a, P, theta, cnt, keys, vals, N, o, s, dv);
   }
 }
 
@@ -819,17 +853,18 @@ paulisum* commutator_filtered(const paulisum* a, const paulisum* b, const MergeA
 
 paulisum* merge_rotated(const paulisum* s, const RotString& P, double theta,
                         const uint32_t* cnt, uint64_t* keys, uint32_t* vals, int64_t N,
-                        const MergeArgs& o, hipStream_t st) {
+                        const MergeArgs& o, hipStream_t st, const DevRun* dv) {
   if (s->dtype == kDtypeFF) {
     if (o.mode != kModeFF) fail(PAULI_ERR_INVALID, "a float-float state needs its own merge mode");
-    if (N == 0) return new_sum(s->n, 0, 0, o.ff_out ? kDtypeFF : PAULI_C64, st);
-    return merge_rotated_w<ff>(s, P, theta, cnt, keys, vals, N, o, st);
+    if (N == 0 && !dv) return new_sum(s->n, 0, 0, o.ff_out ? kDtypeFF : PAULI_C64, st);
+    return merge_rotated_w<ff>(s, P, theta, cnt, keys, vals, N, o, st, dv);
   }
   if (o.mode != PAULI_MERGE_PLAIN)
     fail(PAULI_ERR_INVALID, "a rotation step on a stored FP64/FP32 state merges in its precision");
-  if (N == 0) return new_sum(s->n, 0, 0, s->dtype, st);
-  if (s->dtype == PAULI_C128) return merge_rotated_w<double>(s, P, theta, cnt, keys, vals, N, o, st);
-  return merge_rotated_w<float>(s, P, theta, cnt, keys, vals, N, o, st);
+  if (N == 0 && !dv) return new_sum(s->n, 0, 0, s->dtype, st);
+  if (s->dtype == PAULI_C128)
+    return merge_rotated_w<double>(s, P, theta, cnt, keys, vals, N, o, st, dv);
+  return merge_rotated_w<float>(s, P, theta, cnt, keys, vals, N, o, st, dv);
 }
 
 paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals,
@@ -839,16 +874,18 @@ paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals
   return merge_sorted_w<float>(a, keys, vals, o, s);
 }
 
-paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s) {
+paulisum* merge_generic(const paulisum* a, const paulisum* b, const MergeArgs& o, hipStream_t s,
+                        const DevRun* dv) {
   if (a->dtype == kDtypeFF) {
-    if (b != nullptr || o.mode != kModeFF)
+    if (b != nullptr || o.mode != kModeFF || dv)
       fail(PAULI_ERR_INVALID, "a float-float state is only merged on its own");
     return merge_ff(a, o, s);
   }
   if (o.mode == kModeFF && b != nullptr)
     fail(PAULI_ERR_INVALID, "the float-float merge takes one stored sum");
-  if (a->dtype == PAULI_C128) return merge_w<double>(a, b, o, s);
-  return merge_w<float>(a, b, o, s);
+  if (dv && b != nullptr) fail(PAULI_ERR_INVALID, "a merge into a state takes one stored sum");
+  if (a->dtype == PAULI_C128) return merge_w<double>(a, b, o, s, dv);
+  return merge_w<float>(a, b, o, s, dv);
 }
 
 }  // namespace pauli

@@ -8,7 +8,10 @@
 //                     -i sin(theta) P Q.  The 1 or 2 terms per input term are
 //                     written by one streaming kernel, then merged.
 // Both end with the merge options' truncation.
+#include <algorithm>
 #include <cmath>
+#include <memory>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -31,7 +34,9 @@ inline unsigned grid_for(int64_t n) {
 // cnt[t] = 1 + (term t anticommutes with P): the parity of the symplectic
 // product (Section III-F), sum over words of |X_t & Z_P| + |Z_t & X_P|.
 __global__ void k_rot_count(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
-                            int64_t ld, int64_t m, RotString P, uint32_t* __restrict__ cnt) {
+                            int64_t ld, int64_t m, const uint32_t* __restrict__ md, RotString P,
+                            uint32_t* __restrict__ cnt) {
+  if (md && *md < m) m = *md;  // the device count, clamped to the host bound
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x) {
     int s = 0;
@@ -86,9 +91,11 @@ __global__ void k_rot_write(const uint64_t* __restrict__ X, const uint64_t* __re
 // Record ids address the conjugated sum without storing it: 2t is input
 // term t, 2t + 1 its new term.
 __global__ void k_rot_records(const uint64_t* __restrict__ fp, const uint32_t* __restrict__ cnt,
-                              const uint32_t* __restrict__ off, int64_t m, uint64_t pfp,
-                              int kshift, uint64_t* __restrict__ kk, uint32_t* __restrict__ kv,
+                              const uint32_t* __restrict__ off, int64_t m,
+                              const uint32_t* __restrict__ md, uint64_t pfp, int kshift,
+                              uint64_t* __restrict__ kk, uint32_t* __restrict__ kv,
                               uint64_t* __restrict__ nk, uint32_t* __restrict__ nv) {
+  if (md && *md < m) m = *md;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t f = fp[t];
@@ -124,7 +131,10 @@ __device__ __forceinline__ int64_t corank(const uint64_t* a, int64_t na, const u
 __global__ void __launch_bounds__(kBlock)
 k_merge_path(const uint64_t* __restrict__ ak, const uint32_t* __restrict__ av, int64_t na,
              const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, int64_t nb,
+             const uint32_t* __restrict__ nad, const uint32_t* __restrict__ nbd,
              uint64_t* __restrict__ ok, uint32_t* __restrict__ ov) {
+  if (nad && *nad < na) na = *nad;  // device counts, clamped to the host bounds
+  if (nbd && *nbd < nb) nb = *nbd;
   __shared__ uint64_t sk[kMergeOut];
   __shared__ uint32_t sv[kMergeOut];
   __shared__ uint64_t so_k[kMergeOut];
@@ -197,7 +207,8 @@ RotString rot_string(int n, const uint64_t* px, const uint64_t* pz) {
 }
 
 // Every term gives two records: (cos theta) Q_t and (-i sin theta) P Q_t.
-__global__ void k_rot_all(int64_t m, uint32_t* __restrict__ cnt) {
+__global__ void k_rot_all(int64_t m, const uint32_t* __restrict__ md, uint32_t* __restrict__ cnt) {
+  if (md && *md < m) m = *md;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m;
        t += (int64_t)gridDim.x * blockDim.x)
     cnt[t] = 2u;
@@ -224,10 +235,10 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
   {
     StageScope sc(PAULI_STAGE_PREP, st, m * (16.0 * s->W + 8));
     if (all_new)
-      hipLaunchKernelGGL(k_rot_all, dim3(g), dim3(kBlock), 0, st, m, cnt.as<uint32_t>());
+      hipLaunchKernelGGL(k_rot_all, dim3(g), dim3(kBlock), 0, st, m, nullptr, cnt.as<uint32_t>());
     else
-      hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, m, P,
-                         cnt.as<uint32_t>());
+      hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, m, nullptr,
+                         P, cnt.as<uint32_t>());
     scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), m, tot.as<uint32_t>(), work.p, st);
     PAULI_HIP(hipMemcpyAsync(&M2, tot.p, 4, hipMemcpyDeviceToHost, st));
     PAULI_HIP(hipStreamSynchronize(st));
@@ -243,7 +254,7 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
     {
       StageScope sc(PAULI_STAGE_SORT, st, m * 24.0 + nb * 12.0 * 2 + M2 * 36.0);
       hipLaunchKernelGGL(k_rot_records, dim3(g), dim3(kBlock), 0, st, s->fp, cnt.as<uint32_t>(),
-                         off.as<uint32_t>(), m, P.fp, kshift, kk.as<uint64_t>(),
+                         off.as<uint32_t>(), m, nullptr, P.fp, kshift, kk.as<uint64_t>(),
                          kv.as<uint32_t>(), nk.as<uint64_t>(), nv.as<uint32_t>());
       PAULI_HIP(hipGetLastError());
       uint64_t* bk = nk.as<uint64_t>();
@@ -257,7 +268,7 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
       if (blocks > 65536) blocks = 65536;
       if (blocks < 1) blocks = 1;
       hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
-                         kk.as<uint64_t>(), kv.as<uint32_t>(), na, bk, bv, nb,
+                         kk.as<uint64_t>(), kv.as<uint32_t>(), na, bk, bv, nb, nullptr, nullptr,
                          keys.as<uint64_t>(), vals.as<uint32_t>());
       PAULI_HIP(hipGetLastError());
     }
@@ -330,7 +341,267 @@ paulisum* rotation_sum(const paulisum* s, const RotString& P, double theta, hipS
   return R;
 }
 
+__global__ void k_clear_u32(uint32_t* __restrict__ p, int n) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
+}
+
+// nb = M2 - m: the new records of a step (both counts on the device).
+__global__ void k_new_count(const uint32_t* __restrict__ M2, const uint32_t* __restrict__ m,
+                            uint32_t* __restrict__ nb) {
+  *nb = *M2 - *m;
+}
+
+// One rotation step in device-count form: the sorted state s holds *md
+// terms (at most mb); the merged successor goes to dv.into, its count to
+// *dv.U.  The same kernels as the host-count steps, every size read on the
+// device (no host synchronisation), grids and buffers sized for the bounds.
+template <typename T>
+void conjugate_dev(const paulisum* s, const RotString& P, double theta, const MergeArgs& o,
+                   bool all_new, int64_t mb, const uint32_t* md, const DevRun& dv0,
+                   hipStream_t st) {
+  const int64_t M2b = 2 * mb;
+  DBuf cnt((mb + 1) * 4, st), off((mb + 1) * 4, st), ctr(64, st);
+  DBuf work(scan_workspace_bytes(mb), st);
+  uint32_t* M2d = ctr.as<uint32_t>();
+  uint32_t* nbd = M2d + 1;
+  const unsigned g = grid_for(mb);
+  if (all_new)
+    hipLaunchKernelGGL(k_rot_all, dim3(g), dim3(kBlock), 0, st, mb, md, cnt.as<uint32_t>());
+  else
+    hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, mb, md, P,
+                       cnt.as<uint32_t>());
+  scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), mb, M2d, work.p, st, md);
+  hipLaunchKernelGGL(k_new_count, dim3(1), dim3(1), 0, st, M2d, md, nbd);
+  const int kshift = 64 - o.key_bits;
+  DBuf keys(M2b * 8ull + 8, st), vals(M2b * 4ull + 4, st), kk(mb * 8 + 8, st), kv(mb * 4 + 4, st);
+  DBuf nk(mb * 8 + 8, st), nv(mb * 4 + 4, st), nk2(mb * 8 + 8, st), nv2(mb * 4 + 4, st);
+  hipLaunchKernelGGL(k_rot_records, dim3(g), dim3(kBlock), 0, st, s->fp, cnt.as<uint32_t>(),
+                     off.as<uint32_t>(), mb, md, P.fp, kshift, kk.as<uint64_t>(), kv.as<uint32_t>(),
+                     nk.as<uint64_t>(), nv.as<uint32_t>());
+  PAULI_HIP(hipGetLastError());
+  uint64_t* bk = nk.as<uint64_t>();
+  uint32_t* bv = nv.as<uint32_t>();
+  if (mb > 1 && sort_records_bucketed(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), mb,
+                                      o.key_bits, st, nbd)) {
+    bk = nk2.as<uint64_t>();
+    bv = nv2.as<uint32_t>();
+  }
+  int64_t blocks = (M2b + kMergeOut - 1) / kMergeOut;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
+                     kk.as<uint64_t>(), kv.as<uint32_t>(), mb, bk, bv, mb, md, nbd,
+                     keys.as<uint64_t>(), vals.as<uint32_t>());
+  PAULI_HIP(hipGetLastError());
+  DevRun dv = dv0;
+  dv.N = M2d;
+  merge_rotated(s, P, theta, cnt.as<uint32_t>(), keys.as<uint64_t>(), vals.as<uint32_t>(), M2b, o,
+                st, &dv);
+}
+
 }  // namespace
+
+// ------------------------------------------------------- propagation plans
+//
+// The whole loop in device-count form, captured once into a HIP graph: the
+// input is merged into state 0, and step t merges the rotated state t % 2
+// into state (t + 1) % 2 (the precision form's last step into a C64 state),
+// every state an array set of capacity max_terms with its term count on the
+// device.  The host bound of step t's state is min(capacity, |s| 2^t) (a
+// step at most doubles the terms); a state that would exceed the capacity
+// is cut and raises a flag, which the results call turns into CAPACITY.
+// The temporaries of a step come from one region, reused by every step.
+struct PropPlan {
+  const paulisum* in = nullptr;
+  int steps = 0;
+  std::vector<uint64_t> px, pz;
+  std::vector<double> theta;
+  int mode = PAULI_ROTATE_CONJUGATE;
+  MergeArgs o;
+  int64_t cap = 0;
+  bool ff = false;
+  std::shared_ptr<SharedBlock> blk[3];
+  paulisum state[3];
+  DBuf counts;  // [0..2] term counts of the states, [3] the capacity flag
+  DBuf tmp;
+  size_t tmp_bytes = 0;
+  hipStream_t home = nullptr, priv = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int last = 0;  // the state holding the result
+  bool ran = false;
+  ~PropPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (priv && ev_out) {
+      (void)hipEventRecord(ev_out, priv);
+      (void)hipStreamWaitEvent(home, ev_out, 0);
+    }
+    counts.reset();
+    tmp.reset();
+    for (auto& b : blk) b.reset();
+    if (priv) {
+      (void)hipStreamSynchronize(priv);
+      (void)hipStreamDestroy(priv);
+    }
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+  }
+};
+
+namespace {
+
+void bind_state(PropPlan& pl, int k, int32_t dt) {
+  pl.blk[k] = std::make_shared<SharedBlock>(pl.in->W, pl.cap, dt, pl.home);
+  paulisum& c = pl.state[k];
+  c.n = pl.in->n;
+  c.W = pl.in->W;
+  c.m = 0;
+  c.ld = pl.cap;
+  c.dtype = dt;
+  c.device = pl.in->device;
+  c.X = pl.blk[k]->X;
+  c.Z = pl.blk[k]->Z;
+  c.ph = pl.blk[k]->ph;
+  c.coef = pl.blk[k]->coef;
+  c.fp = pl.blk[k]->fp;
+  c.last_stream = pl.home;
+  c.borrowed = true;
+}
+
+int32_t state_dtype(const PropPlan& pl) { return pl.ff ? kDtypeFF : pl.in->dtype; }
+
+// The loop's launch sequence on stream st (no host synchronisation).
+void launch_loop(PropPlan& pl, hipStream_t st) {
+  uint32_t* cnt = pl.counts.as<uint32_t>();
+  hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, cnt, 4);  // counts and flag
+  ScratchScope scratch(pl.tmp.p, pl.tmp_bytes);
+  // state 0: the merged input, in key order
+  MergeArgs m0 = pl.o;
+  m0.drop_abs = -1.0;
+  if (pl.ff) {
+    m0.mode = kModeFF;
+    m0.ff_out = 1;
+  }
+  int cur = 0;
+  if (pl.ff && pl.steps == 0) {
+    m0.ff_out = 0;  // no step: the merged input is the result, in C64
+    cur = 2;
+  }
+  DevRun dv{nullptr, &pl.state[cur], cnt + cur, cnt + 3};
+  merge_generic(pl.in, nullptr, m0, st, &dv);
+  MergeArgs ms = pl.o;
+  if (pl.ff) ms.mode = kModeFF;
+  int64_t bound = pl.in->m;
+  for (int t = 0; t < pl.steps; ++t) {
+    scratch.rewind();  // the previous step's temporaries are dead (stream order)
+    const int nxt = (pl.ff && t + 1 == pl.steps) ? 2 : 1 - cur;
+    ms.ff_out = (pl.ff && t + 1 < pl.steps) ? 1 : 0;
+    const int64_t mb = bound < pl.cap ? bound : pl.cap;
+    const RotString P = rot_string(pl.in->n, pl.px.data() + static_cast<size_t>(t) * pl.in->W,
+                                   pl.pz.data() + static_cast<size_t>(t) * pl.in->W);
+    DevRun d{nullptr, &pl.state[nxt], cnt + nxt, cnt + 3};
+    const bool all_new = pl.mode == PAULI_ROTATE_PRODUCT;
+    if (pl.ff)
+      conjugate_dev<ff>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+    else if (pl.in->dtype == PAULI_C128)
+      conjugate_dev<double>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+    else
+      conjugate_dev<float>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+    bound = 2 * mb;
+    cur = nxt;
+  }
+  pl.last = cur;
+}
+
+void capture_loop(PropPlan& pl) {
+  if (pl.exec) {
+    PAULI_HIP(hipGraphExecDestroy(pl.exec));
+    pl.exec = nullptr;
+  }
+  NoEvents ne;
+  hipGraph_t graph = nullptr;
+  PAULI_HIP(hipStreamBeginCapture(pl.priv, hipStreamCaptureModeThreadLocal));
+  try {
+    launch_loop(pl, pl.priv);
+  } catch (...) {
+    (void)hipStreamEndCapture(pl.priv, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  PAULI_HIP(hipStreamEndCapture(pl.priv, &graph));
+  const hipError_t e = hipGraphInstantiate(&pl.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  PAULI_HIP(e);
+}
+
+}  // namespace
+
+PropPlan* prop_plan_create(const paulisum* s, int steps, const uint64_t* px, const uint64_t* pz,
+                           const double* theta, int mode, const MergeArgs& o, int64_t cap,
+                           hipStream_t st) {
+  auto pl = std::make_unique<PropPlan>();
+  pl->in = s;
+  pl->steps = steps;
+  pl->px.assign(px, px + static_cast<size_t>(steps) * s->W);
+  pl->pz.assign(pz, pz + static_cast<size_t>(steps) * s->W);
+  pl->theta.assign(theta, theta + steps);
+  pl->mode = mode;
+  pl->o = o;
+  pl->cap = cap;
+  pl->ff = o.mode == PAULI_MERGE_COMPENSATED;
+  pl->home = st;
+  PAULI_HIP(hipStreamCreateWithFlags(&pl->priv, hipStreamNonBlocking));
+  PAULI_HIP(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
+  PAULI_HIP(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+  pl->counts = DBuf(64, st);
+  bind_state(*pl, 0, state_dtype(*pl));
+  bind_state(*pl, 1, state_dtype(*pl));
+  if (pl->ff) bind_state(*pl, 2, PAULI_C64);
+  // temporaries of the largest step (about 172 bytes per term of its bound,
+  // with room for the alignment of each piece)
+  const int64_t mmax = std::max<int64_t>(cap, s->m);
+  pl->tmp_bytes = static_cast<size_t>(mmax) * 200 + (size_t(64) << 20);
+  pl->tmp = DBuf(pl->tmp_bytes, st);
+  PAULI_HIP(hipStreamSynchronize(st));  // the buffers exist before the capture
+  capture_loop(*pl);
+  return pl.release();
+}
+
+void prop_plan_run(PropPlan* pl, hipStream_t st) {
+  bool fresh = false;
+  for (int k = 0; k < (pl->ff ? 3 : 2); ++k)
+    if (!pl->blk[k]) {
+      bind_state(*pl, k, k == 2 ? PAULI_C64 : state_dtype(*pl));
+      fresh = true;
+    }
+  if (fresh || !pl->exec) capture_loop(*pl);
+  PAULI_HIP(hipEventRecord(pl->ev_in, st));
+  PAULI_HIP(hipStreamWaitEvent(pl->priv, pl->ev_in, 0));
+  if (st != pl->home) {
+    PAULI_HIP(hipEventRecord(pl->ev_in, pl->home));
+    PAULI_HIP(hipStreamWaitEvent(pl->priv, pl->ev_in, 0));
+  }
+  PAULI_HIP(hipGraphLaunch(pl->exec, pl->priv));
+  PAULI_HIP(hipEventRecord(pl->ev_out, pl->priv));
+  PAULI_HIP(hipStreamWaitEvent(st, pl->ev_out, 0));
+  pl->ran = true;
+}
+
+paulisum* prop_plan_result(PropPlan* pl) {
+  if (!pl->ran) fail(PAULI_ERR_INVALID, "the plan has not run since its last result");
+  pl->ran = false;
+  PAULI_HIP(hipStreamSynchronize(pl->priv));
+  uint32_t c[4] = {0, 0, 0, 0};
+  PAULI_HIP(hipMemcpy(c, pl->counts.p, sizeof(c), hipMemcpyDeviceToHost));
+  if (c[3] != 0)
+    fail(PAULI_ERR_CAPACITY, "a propagation state exceeded the plan's capacity of " +
+                                 std::to_string(pl->cap) + " terms");
+  paulisum* r = sum_view(pl->blk[pl->last], pl->in->n, 0, c[pl->last]);
+  pl->blk[pl->last].reset();  // the result owns that block now
+  return r;
+}
+
+void prop_plan_destroy(PropPlan* pl) { delete pl; }
 
 paulisum* rotate_step(const paulisum* s, const uint64_t* px, const uint64_t* pz, double theta,
                       int mode, const MergeArgs& o, bool sorted_input, hipStream_t st) {

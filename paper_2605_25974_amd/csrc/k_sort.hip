@@ -52,7 +52,9 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* total) {
 }
 
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ partial) {
+k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __restrict__ nd,
+              uint32_t* __restrict__ partial) {
+  if (nd && *nd < n) n = *nd;  // the count on the device, clamped to the host bound
   const int64_t base = blockIdx.x * (int64_t)kScanTile;
   uint32_t s = 0;
 #pragma unroll
@@ -80,7 +82,9 @@ k_scan_partials(uint32_t* __restrict__ partial, int64_t nb, uint32_t* __restrict
 }
 
 __global__ void __launch_bounds__(kScanBlock)
-k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __restrict__ partial) {
+k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __restrict__ nd,
+            const uint32_t* __restrict__ partial) {
+  if (nd && *nd < n) n = *nd;
   const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -102,9 +106,10 @@ k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __rest
 // ----------------------------------------------------------------- radix
 
 __global__ void __launch_bounds__(kRsBlock)
-k_rs_count(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __restrict__ counts,
-           int64_t ntiles) {
+k_rs_count(const uint64_t* __restrict__ keys, int64_t n, const uint32_t* __restrict__ nd, int shift,
+           uint32_t* __restrict__ counts, int64_t ntiles) {
   __shared__ uint32_t hist[256];
+  if (nd && *nd < n) n = *nd;  // tiles past the device count write zero counts
   hist[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = blockIdx.x * (int64_t)kRsTile;
@@ -130,8 +135,10 @@ k_rs_count(const uint64_t* __restrict__ keys, int64_t n, int shift, uint32_t* __
 // out in LDS order so that each digit's run is stored contiguously.
 __global__ void __launch_bounds__(kRsBlock)
 k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
-             const uint32_t* __restrict__ offsets, int64_t ntiles) {
+             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
+             const uint32_t* __restrict__ nd, int shift, const uint32_t* __restrict__ offsets,
+             int64_t ntiles) {
+  if (nd && *nd < n) n = *nd;
   __shared__ uint64_t s_k[kRsTile];
   __shared__ uint32_t s_v[kRsTile];
   __shared__ uint32_t s_start[256], s_goff[256];
@@ -217,14 +224,15 @@ size_t scan_workspace_bytes(int64_t n) {
 }
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                        void* work, hipStream_t s) {
+                        void* work, hipStream_t s, const uint32_t* nd) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   uint32_t* partial = static_cast<uint32_t*>(work);
   if (n > 0)
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, partial);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, nd,
+                       partial);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBlock), 0, s, partial, nb, total);
   if (n > 0)
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n,
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, n, nd,
                        partial);
   PAULI_HIP(hipGetLastError());
 }
@@ -238,7 +246,8 @@ size_t radix_workspace_bytes(int64_t n) {
 }
 
 bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                   int64_t n, const int* shifts, int nshifts, void* work, hipStream_t s) {
+                   int64_t n, const int* shifts, int nshifts, void* work, hipStream_t s,
+                   const uint32_t* nd) {
   if (n <= 1) return false;
   int64_t ntiles = (n + kRsTile - 1) / kRsTile;
   uint32_t* counts = static_cast<uint32_t*>(work);
@@ -254,12 +263,12 @@ bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
     // one pass reads the keys for the counts, then reads and writes the
     // 12-byte records
     StageScope sc(PAULI_STAGE_SORT, s, 32.0 * n);
-    hipLaunchKernelGGL(k_rs_count, dim3((unsigned)ntiles), dim3(kRsBlock), 0, s, kin, n, shift,
-                       counts, ntiles);
+    hipLaunchKernelGGL(k_rs_count, dim3((unsigned)ntiles), dim3(kRsBlock), 0, s, kin, n, nd,
+                       shift, counts, ntiles);
     PAULI_HIP(hipGetLastError());
     scan_exclusive_u32(counts, counts, 256 * ntiles, nullptr, scan_work, s);
     hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsBlock), 0, s, kin, vin,
-                       kout, vout, n, shift, counts, ntiles);
+                       kout, vout, n, nd, shift, counts, ntiles);
     PAULI_HIP(hipGetLastError());
     alt = !alt;
   }
@@ -267,13 +276,14 @@ bool radix_sort_at(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t*
 }
 
 bool radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                      int64_t n, int key_bits, void* work, hipStream_t s, uint64_t vary) {
+                      int64_t n, int key_bits, void* work, hipStream_t s, uint64_t vary,
+                      const uint32_t* nd) {
   if (n <= 1 || key_bits <= 0) return false;
   int shifts[8];
   int ns = 0;
   for (int shift = 0; shift < key_bits; shift += 8)
     if (((vary >> shift) & 0xFFull) != 0) shifts[ns++] = shift;  // else the same digit in every key
-  return radix_sort_at(keys, vals, keys_alt, vals_alt, n, shifts, ns, work, s);
+  return radix_sort_at(keys, vals, keys_alt, vals_alt, n, shifts, ns, work, s, nd);
 }
 
 }  // namespace pauli
