@@ -345,6 +345,12 @@ __global__ void k_clear_u32(uint32_t* __restrict__ p, int n) {
   for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
 
+// A state count above the bound its step was sized for raises the flag.
+__global__ void k_check_bound(const uint32_t* __restrict__ m, int64_t bound,
+                              uint32_t* __restrict__ flag) {
+  if (static_cast<int64_t>(*m) > bound) atomicOr(flag, 1u);
+}
+
 // nb = M2 - m: the new records of a step (both counts on the device).
 __global__ void k_new_count(const uint32_t* __restrict__ M2, const uint32_t* __restrict__ m,
                             uint32_t* __restrict__ nb) {
@@ -430,6 +436,9 @@ struct PropPlan {
   hipGraphExec_t exec = nullptr;
   int last = 0;  // the state holding the result
   bool ran = false;
+  // host bounds of the state entering each step and of the result (from a
+  // measuring run of the same sequence; empty: min(capacity, |s| 2^t))
+  std::vector<int64_t> bounds;
   ~PropPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (priv && ev_out) {
@@ -470,8 +479,18 @@ void bind_state(PropPlan& pl, int k, int32_t dt) {
 
 int32_t state_dtype(const PropPlan& pl) { return pl.ff ? kDtypeFF : pl.in->dtype; }
 
-// The loop's launch sequence on stream st (no host synchronisation).
-void launch_loop(PropPlan& pl, hipStream_t st) {
+// The state count c (device) read back on the host (measuring run only).
+int64_t read_count(const uint32_t* c, hipStream_t st) {
+  uint32_t h = 0;
+  PAULI_HIP(hipMemcpyAsync(&h, c, 4, hipMemcpyDeviceToHost, st));
+  PAULI_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+// The loop's launch sequence on stream st (no host synchronisation).  With
+// `measured`, the sequence runs eagerly and the count of every state is
+// read back after it is formed (the plan's measuring run).
+void launch_loop(PropPlan& pl, hipStream_t st, std::vector<int64_t>* measured = nullptr) {
   uint32_t* cnt = pl.counts.as<uint32_t>();
   hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, cnt, 4);  // counts and flag
   ScratchScope scratch(pl.tmp.p, pl.tmp_bytes);
@@ -489,6 +508,7 @@ void launch_loop(PropPlan& pl, hipStream_t st) {
   }
   DevRun dv{nullptr, &pl.state[cur], cnt + cur, cnt + 3};
   merge_generic(pl.in, nullptr, m0, st, &dv);
+  if (measured) measured->push_back(read_count(cnt + cur, st));
   MergeArgs ms = pl.o;
   if (pl.ff) ms.mode = kModeFF;
   int64_t bound = pl.in->m;
@@ -496,9 +516,11 @@ void launch_loop(PropPlan& pl, hipStream_t st) {
     scratch.rewind();  // the previous step's temporaries are dead (stream order)
     const int nxt = (pl.ff && t + 1 == pl.steps) ? 2 : 1 - cur;
     ms.ff_out = (pl.ff && t + 1 < pl.steps) ? 1 : 0;
-    const int64_t mb = bound < pl.cap ? bound : pl.cap;
+    int64_t mb = bound < pl.cap ? bound : pl.cap;
+    if (static_cast<size_t>(t) < pl.bounds.size()) mb = pl.bounds[t];
     const RotString P = rot_string(pl.in->n, pl.px.data() + static_cast<size_t>(t) * pl.in->W,
                                    pl.pz.data() + static_cast<size_t>(t) * pl.in->W);
+    hipLaunchKernelGGL(k_check_bound, dim3(1), dim3(1), 0, st, cnt + cur, mb, cnt + 3);
     DevRun d{nullptr, &pl.state[nxt], cnt + nxt, cnt + 3};
     const bool all_new = pl.mode == PAULI_ROTATE_PRODUCT;
     if (pl.ff)
@@ -507,6 +529,7 @@ void launch_loop(PropPlan& pl, hipStream_t st) {
       conjugate_dev<double>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
     else
       conjugate_dev<float>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+    if (measured) measured->push_back(read_count(cnt + nxt, st));
     bound = 2 * mb;
     cur = nxt;
   }
@@ -563,6 +586,19 @@ PropPlan* prop_plan_create(const paulisum* s, int steps, const uint64_t* px, con
   pl->tmp_bytes = static_cast<size_t>(mmax) * 200 + (size_t(64) << 20);
   pl->tmp = DBuf(pl->tmp_bytes, st);
   PAULI_HIP(hipStreamSynchronize(st));  // the buffers exist before the capture
+  // measuring run: the same sequence, eagerly, reading back every state's
+  // size; the graph's kernels are then sized for those (with a margin; a
+  // count above a bound is cut on the device and raises the flag)
+  {
+    NoEvents ne;
+    std::vector<int64_t> sizes;
+    launch_loop(*pl, st, &sizes);
+    pl->bounds.clear();
+    for (size_t k = 0; k < sizes.size(); ++k) {
+      const int64_t b = sizes[k] + sizes[k] / 64 + 4096;
+      pl->bounds.push_back(b < cap ? b : cap);
+    }
+  }
   capture_loop(*pl);
   return pl.release();
 }
