@@ -67,3 +67,14 @@ def test_capacity_of_caller_arrays():
     with pytest.raises(pl.PauliError) as e:
         pl.merge_into(G, o, o, p, c, o, U - 1)
     assert e.value.status == "CAPACITY"
+
+
+def test_narrow_key_bounded():
+    """A key narrower than 54 bits is refused for more than 2^(key_bits + 10)
+    records (the runs of equal keys are ordered one run per thread)."""
+    S = synth.random_sum(synth.rng_for(752), 40, 3000, wmax=6)
+    G = pl.PauliSum.from_dict(S)
+    with pytest.raises(pl.PauliError) as e:
+        pl.merge(G, key_bits=1)  # 3000 > 2^11 records
+    assert e.value.status == "INVALID"
+    parity.assert_merged_fp64(pl.merge(G, key_bits=2).export(), O.merge(_osum(S)))
