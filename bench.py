@@ -55,6 +55,8 @@ WORKLOADS = {
        "1e6-term n=500 propagation state, complex128",
     8: "lexicographic order of the merged product of the n=500 10,000 x 10,000 "
        "Jordan-Wigner-shaped sums (about 1e8 terms), complex128",
+    9: "1e6 terms at n=500 through 64 conjugation steps, drop |c| < 1e-10, complex128: the "
+       "whole loop as one captured HIP graph (pauli_propagate_plan), replayed",
 }
 # sources of the kernel each stage's traffic figure was measured on
 STAGE_SOURCES = {
@@ -417,6 +419,39 @@ def _propagation(pl, torch, args):
     }
 
 
+def _propagation_graph(pl, torch, args):
+    """The 64-step conjugation loop as one graph launch, replayed `steps`
+    times after one warm-up run (each run recomputes the whole loop from the
+    input state)."""
+    import synth
+    S = synth.workload5_state()
+    theta, px, pz = synth.workload5_rotations()
+    G = pl.PauliSum.from_dict(S)
+    plan = pl.PropagatePlan(G, px, pz, theta, max_terms=100_000_000, drop_abs=1e-10)
+    plan.run()
+    plan.result().destroy()
+    plan.run()  # new state block and capture after the result
+    torch.cuda.synchronize()
+    _log("propagation graph: timed replays")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = plan.result()
+    rec = {
+        "metric": "64 conjugation steps per second as one graph launch",
+        "value": 1.0 / dt, "unit": "loops/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(1e3 * dt, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators of the workload's shape)",
+        "config": {"workload": WORKLOADS[9], "final_terms": out.m},
+    }
+    out.destroy()
+    plan.destroy()
+    return rec
+
+
 def _hh(pl, torch, args):
     """The cancellation case: H*H with 20,000 Jordan-Wigner-shaped terms
     (4e8 products), FP64 and the precision form at tau = 0.3 and 1e-3,
@@ -715,9 +750,9 @@ def main():
     import paper_2605_25974_amd as pl
 
     torch.cuda.set_device(0)
-    if args.workload in (4, 5, 6, 7, 8):
+    if args.workload in (4, 5, 6, 7, 8, 9):
         rec = {4: _batched, 5: _propagation, 6: _commutator,
-               7: _clifford, 8: _lex}[args.workload](pl, torch, args)
+               7: _clifford, 8: _lex, 9: _propagation_graph}[args.workload](pl, torch, args)
         print(json.dumps(rec), flush=True)
         return
     A, B = _inputs(args.workload)

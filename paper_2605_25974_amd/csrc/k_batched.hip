@@ -636,7 +636,7 @@ void launch_class(ClassRun& cr, hipStream_t s) {
     const uint32_t gsort = cr.nbk < cr.cus ? cr.nbk : cr.cus;
     hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, cr.K, cr.boff, cr.nbk,
                        f0, sb, so, cr.heavy, cr.ctr, cr.redo, cr.ctr + 6);
-    hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, cr.K,
+    hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, cr.K,
                        cr.boff, cr.nbk, cr.redo, cr.ctr + 6, f0, sb, so, cr.heavy, cr.ctr);
     hipLaunchKernelGGL(k_heavy_sort, dim3(gsort), dim3(kSortNT), 0, s, cr.K, cr.K2, cr.V2,
                        cr.boff, 64, sb, cr.heavy, cr.ctr, so);

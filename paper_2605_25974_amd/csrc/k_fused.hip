@@ -172,7 +172,7 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                          nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),
                          ctr32 + 6);
       // (usually none: a few blocks)
-      hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, K,
+      hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K,
                          boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, SortBatch{}, so,
                          heavy.as<uint32_t>(), ctr32);
     } else {
@@ -321,7 +321,7 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
                        nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),
                          ctr32 + 6);
-    hipLaunchKernelGGL(k_bucket_radix, dim3(gsort < 64u ? gsort : 64u), dim3(kSortNT), 0, s, K,
+    hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K,
                        boff.as<uint32_t>(), nbk, redo.as<uint32_t>(), ctr32 + 6, sf, SortBatch{}, so,
                        heavy.as<uint32_t>(), ctr32);
   } else {
