@@ -414,11 +414,11 @@ pauli_status_t paulisum_create(int32_t n_qubits, int64_t n_terms, const uint64_t
         if (phase)
           PAULI_HIP(hipMemcpyAsync(p->ph, phase, m, kind, s));
         else
-          PAULI_HIP(hipMemsetAsync(p->ph, 0, m, s));
+          launch_zero_bytes(p->ph, static_cast<int64_t>(m), s);
         PAULI_HIP(hipMemcpyAsync(p->coef, coef, m * coef_bytes(dtype), kind, s));
         if (dev) {
           DBuf err(4, s);
-          PAULI_HIP(hipMemsetAsync(err.p, 0, 4, s));
+          launch_zero_bytes(err.p, 4, s);
           launch_validate(rx.as<uint64_t>(), rz.as<uint64_t>(), p->ph, n_qubits, n_terms,
                           err.as<uint32_t>(), s);
           uint32_t herr = 0;

@@ -164,6 +164,7 @@ void launch_soa_to_rows(const uint64_t* soa, int W, int64_t m, int64_t ld, uint6
 void launch_validate(const uint64_t* xr, const uint64_t* zr, const uint8_t* ph, int n, int64_t m,
                      uint32_t* err, hipStream_t s);
 void launch_fingerprint(const paulisum* t, hipStream_t s);
+void launch_zero_bytes(void* p, int64_t n, hipStream_t s);
 void launch_outer_product(const paulisum* a, const paulisum* b, paulisum* out, hipStream_t s);
 
 // Per-term data of one operand of a pair product, gathered row-major so that

@@ -273,6 +273,23 @@ void launch_soa_to_rows(const uint64_t* soa, int W, int64_t m, int64_t ld, uint6
   PAULI_HIP(hipGetLastError());
 }
 
+// Bytes [0, n) of p set to zero by a kernel (no memset node in a caller's
+// captured graph).
+__global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = 0;
+}
+
+void launch_zero_bytes(void* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_zero_bytes, dim3(static_cast<unsigned>(g)), dim3(kBlock), 0, s,
+                     static_cast<uint8_t*>(p), n);
+  PAULI_HIP(hipGetLastError());
+}
+
 void launch_validate(const uint64_t* xr, const uint64_t* zr, const uint8_t* ph, int n, int64_t m,
                      uint32_t* err, hipStream_t s) {
   if (m == 0) return;

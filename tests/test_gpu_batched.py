@@ -164,3 +164,24 @@ def test_batched_drop_and_tune_file(tmp_path):
     with pytest.raises(pl.PauliError) as e:
         pl.tune_load(str(bad))
     assert e.value.status == "INVALID"
+
+
+def test_batched_collisions_recomputed():
+    """A 32-bit key makes fingerprint collisions certain in 1e6-record
+    products: those products are recomputed by the general pipeline after
+    the sequence and still equal the oracle; keys below 30 bits are refused."""
+    plan = [(128, 1000, 1000), (500, 900, 1100), (64, 40, 50)]
+    pairs = [synth.workload4_batch(400 + b, n, m1, m2) for b, (n, m1, m2) in enumerate(plan)]
+    for k, (A, B) in enumerate(pairs):
+        pairs[k] = (dict(A, coef=A["coef"].astype(np.complex128)),
+                    dict(B, coef=B["coef"].astype(np.complex128)))
+    GA = [pl.PauliSum.from_dict(A) for A, _ in pairs]
+    GB = [pl.PauliSum.from_dict(B) for _, B in pairs]
+    outs = pl.outer_product_batched(GA, GB, key_bits=32)
+    for (A, B), o in zip(pairs, outs):
+        g = o.export()
+        parity.assert_merged_fp64(g, O.product_merge(_osum(A), _osum(B)))
+        parity.assert_sorted_by_key(g, key_bits=32)
+    with pytest.raises(pl.PauliError) as e:
+        pl.outer_product_batched(GA, GB, key_bits=29)
+    assert e.value.status == "INVALID"
