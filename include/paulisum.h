@@ -66,8 +66,8 @@ typedef struct paulisum* paulisum_t;
  *  key_bits    0 for the default; otherwise the sort uses only the top
  *              key_bits bits of the 64-bit string fingerprint (testing aid:
  *              forces fingerprint collisions, which are resolved exactly).
- *              A merge of more than 2^(key_bits + 10) records with a key
- *              narrower than 54 bits is refused (INVALID): the strings of a
+ *              A merge of more than 2^(key_bits + 12) records with a key
+ *              narrower than 52 bits is refused (INVALID): the strings of a
  *              run of equal keys are put in order one run per thread.
  */
 typedef enum { PAULI_MERGE_PLAIN = 0, PAULI_MERGE_COMPENSATED = 1 } pauli_merge_mode_t;

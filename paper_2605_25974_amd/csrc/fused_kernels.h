@@ -57,12 +57,13 @@ namespace {
 
 constexpr int kTile = 4096;  // records per partition tile
 constexpr int kItems = kTile / kB;
-constexpr int kSortNT = 1024;
+constexpr int kSortNT = 512;
 constexpr int kSortWaves = kSortNT / 64;
-constexpr int kCap = 8192;  // records of a bucket sorted in LDS
+constexpr int kSortBlocksPerCU = 2;  // two bucket sorts share a compute unit's LDS
+constexpr int kCap = 4096;  // records of a bucket sorted in LDS
 constexpr int kSortRounds = kCap / kSortWaves / 64;
 constexpr int kMaxBits = 16;
-constexpr double kTargetBucket = 7000.0;  // records per bucket; the LDS sort takes up to kCap
+constexpr double kTargetBucket = 3500.0;  // records per bucket; the LDS sort takes up to kCap
 
 inline unsigned grid_for(int64_t n, int per = kB, int64_t cap = 65536) {
   int64_t g = (n + per - 1) / per;
@@ -471,7 +472,7 @@ __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32
 // Counting sort of a bucket: 2^14 bins on the key bits just below the bucket
 // bits, two 16-bit counters per word (a bucket holds at most kCap = 8192
 // records, so neither counts nor starts carry into the other half).
-constexpr int kBinBits = 14;
+constexpr int kBinBits = 13;
 constexpr int kBins = 1 << kBinBits;
 constexpr int kBinWords = kBins / 2;
 constexpr uint32_t kMaxBin = 64;  // a bucket with a larger bin takes k_heavy_sort

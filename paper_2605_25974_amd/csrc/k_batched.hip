@@ -197,7 +197,7 @@ struct ClassKey {
 
 // Launch-shape parameters of a class.
 struct ClassParams {
-  double target = 7000.0;  // records per bucket
+  double target = kTargetBucket;  // records per bucket
   int d1cap = 8;           // class bits of the generation (at most)
   int parts = 4;           // expand work items per bucket
   int fixed_d = 0;         // > 0: every product's bucket bits
@@ -633,7 +633,8 @@ void launch_class(ClassRun& cr, hipStream_t s) {
   const SortField f0 = sort_field_for(64);
   {
     StageScope sc(PAULI_STAGE_SEGMENT, s, static_cast<double>(cr.rec) * 20.0);
-    const uint32_t gsort = cr.nbk < cr.cus ? cr.nbk : cr.cus;
+    const uint32_t gs_cap = kSortBlocksPerCU * cr.cus;
+    const uint32_t gsort = cr.nbk < gs_cap ? cr.nbk : gs_cap;
     hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, cr.K, cr.boff, cr.nbk,
                        f0, sb, so, cr.heavy, cr.ctr, cr.redo, cr.ctr + 6);
     hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, cr.K,
@@ -715,7 +716,7 @@ int log2_bucket(uint64_t r) {
 
 const std::vector<ClassParams>& candidates() {
   static const std::vector<ClassParams> c = {
-      {7000.0, 8, 4}, {3500.0, 8, 4}, {7000.0, 6, 4}, {7000.0, 8, 2}, {7000.0, 8, 8}};
+      {3500.0, 8, 4}, {1750.0, 8, 4}, {3500.0, 6, 4}, {3500.0, 8, 2}, {3500.0, 8, 8}};
   return c;
 }
 
@@ -744,7 +745,7 @@ bool load_tune_locked(const std::string& path) {
     ClassKey k{};
     ClassParams p;
     if (!(ls >> k.W >> k.logp >> k.dtype >> k.mode >> p.target >> p.d1cap >> p.parts)) return false;
-    if (!(p.target >= 256.0 && p.target <= 8192.0) || p.d1cap < 0 || p.d1cap > 8 ||
+    if (!(p.target >= 256.0 && p.target <= kCap) || p.d1cap < 0 || p.d1cap > 8 ||
         (p.parts != 1 && p.parts != 2 && p.parts != 4 && p.parts != 8))
       return false;
     g_tune[k] = p;

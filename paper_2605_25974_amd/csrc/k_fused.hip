@@ -165,7 +165,8 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   {
     StageScope sc(PAULI_STAGE_SEGMENT, s, Peff * 20.0);
     // one block per compute unit (the LDS of a block fills most of one)
-    const uint32_t gsort = nbk < static_cast<uint32_t>(device_cus()) ? nbk : device_cus();
+    const uint32_t cus = kSortBlocksPerCU * device_cus();
+    const uint32_t gsort = nbk < cus ? nbk : cus;
     if (sf.lo14 >= 0) {
       // the buckets the counting sort gives up on take the radix sort
       hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
@@ -316,7 +317,8 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   const SortField sf = sort_field_for(rem);
   SegOut so{V, nullptr, nullptr, nullptr, nullptr, K};
   StageScope sc(PAULI_STAGE_SORT, s, n * 24.0);
-  const uint32_t gsort = nbk < device_cus() ? nbk : device_cus();
+  const uint32_t cus = kSortBlocksPerCU * device_cus();
+  const uint32_t gsort = nbk < cus ? nbk : cus;
   if (sf.lo14 >= 0) {
     hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
                        nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),

@@ -291,9 +291,9 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
   const uint32_t* nd = dv ? dv->N : nullptr;  // device count (N is then its bound)
   // a narrow key makes runs of about N / 2^key_bits records that one thread
   // each puts in string order (k_fix_runs): keep those runs short
-  if (o.key_bits < 54 && N > (int64_t(1) << (o.key_bits + 10)))
+  if (o.key_bits < 52 && N > (int64_t(1) << (o.key_bits + 12)))
     fail(PAULI_ERR_INVALID, "key_bits " + std::to_string(o.key_bits) + " is too narrow for " +
-                                std::to_string(N) + " records (at most 2^(key_bits + 10))");
+                                std::to_string(N) + " records (at most 2^(key_bits + 12))");
   using TV = typename std::conditional<MODE == kComp, float,
                                        typename std::conditional<MODE == kFF, ff, T>::type>::type;
   if (MODE == kComp) dt = PAULI_C64;

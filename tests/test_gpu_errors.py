@@ -70,11 +70,11 @@ def test_capacity_of_caller_arrays():
 
 
 def test_narrow_key_bounded():
-    """A key narrower than 54 bits is refused for more than 2^(key_bits + 10)
+    """A key narrower than 52 bits is refused for more than 2^(key_bits + 12)
     records (the runs of equal keys are ordered one run per thread)."""
-    S = synth.random_sum(synth.rng_for(752), 40, 3000, wmax=6)
+    S = synth.random_sum(synth.rng_for(752), 40, 9000, wmax=6)
     G = pl.PauliSum.from_dict(S)
     with pytest.raises(pl.PauliError) as e:
-        pl.merge(G, key_bits=1)  # 3000 > 2^11 records
+        pl.merge(G, key_bits=1)  # 9000 > 2^13 records
     assert e.value.status == "INVALID"
     parity.assert_merged_fp64(pl.merge(G, key_bits=2).export(), O.merge(_osum(S)))
