@@ -270,9 +270,12 @@ pauli_status_t pauli_sort_lex(paulisum_t s, paulisum_t* out, void* stream);
  * (pauli_tune_load, or the file named by the environment variable
  * PAULI_TUNE_FILE, which is also rewritten after each new measurement).
  * Results are views into one output block per class (released with the
- * last of them).  Errors: those of pauli_outer_product_merged for each
- * pair; INVALID for a bad tune field or key_bits in 1..29.  On error no
- * output is returned.  Synchronises the stream once. */
+ * last of them); with opts->drop_abs >= 0 one compaction per class moves
+ * the kept terms of all its products into a block of exactly their size
+ * (one more synchronisation).  Errors: those of pauli_outer_product_merged
+ * for each pair; INVALID for a bad tune field or key_bits in 1..29.  On
+ * error no output is returned.  Synchronises the stream once (twice with a
+ * drop). */
 pauli_status_t pauli_outer_product_batched(int32_t nb, const paulisum_t* a, const paulisum_t* b,
                                            const pauli_merge_opts_t* opts,
                                            const pauli_tune_t* tune, paulisum_t* out,

@@ -251,6 +251,14 @@ paulisum* merge_sorted_records(const paulisum* a, uint64_t* keys, uint32_t* vals
 // marked, terms whose phase byte is nonzero are removed too (the expand
 // kernel marks the strings of a commutator that no anticommuting pair gave).
 paulisum* drop_terms(const paulisum* s, double drop_abs, hipStream_t st, bool marked = false);
+// The same drop over several sums held in one block, the ranges
+// [r0[k], r0[k] + rm[k]) of in, in one keep count, one scan and one
+// compaction: returns a block of exactly the kept terms, range k's at
+// [first[k], first[k] + kept[k]), in range order.  Waits for the stream.
+std::shared_ptr<SharedBlock> drop_ranges(const SharedBlock& in, const std::vector<int64_t>& r0,
+                                         const std::vector<int64_t>& rm, double drop_abs,
+                                         std::vector<int64_t>& first, std::vector<int64_t>& kept,
+                                         hipStream_t s);
 
 // k_merge.hip: the commutator [a, b] = sum over anticommuting pairs of
 // 2 a_i b_j, the pairs found by a tiled parity test before any sorting and

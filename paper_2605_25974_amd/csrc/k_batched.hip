@@ -977,39 +977,51 @@ void batch_plan_run(BatchPlan* plan, hipStream_t st) {
 
 // Per product, a view of its terms in its class's output block (products
 // with an empty side get an empty sum); a product whose records collided on
-// a fingerprint is recomputed by the general pipeline.  Waits for the run.
+// a fingerprint is recomputed by the general pipeline (which applies the
+// drop itself).  With a drop threshold, one compaction per class moves the
+// kept terms of all its products into a block of exactly their size, and
+// the views point there.  Waits for the run.
 void batch_plan_results(BatchPlan* plan, paulisum** out, hipStream_t st) {
   if (!plan->ran) fail(PAULI_ERR_INVALID, "the plan has not run since its last results");
   if (plan->priv) PAULI_HIP(hipStreamSynchronize(plan->priv));
   PAULI_HIP(hipStreamSynchronize(plan->home));
+  const bool drop = plan->o.drop_abs >= 0.0;
   std::vector<paulisum*> res(static_cast<size_t>(plan->nb), nullptr);
   try {
     for (auto& cr : plan->classes) {
       const uint32_t np = static_cast<uint32_t>(cr->prods.size());
       std::vector<uint32_t> info(2 * np);
       PAULI_HIP(hipMemcpy(info.data(), cr->info, 8ull * np, hipMemcpyDeviceToHost));
+      std::vector<uint32_t> direct;  // products read from the class block
+      std::vector<int64_t> r0, rm;
       for (uint32_t k = 0; k < np; ++k) {
         const Product& p = cr->prods[k];
         if (info[2 * k + 1] != 0) {
           res[p.idx] = merge_generic(p.a, p.b, plan->o, st);
           continue;
         }
-        res[p.idx] = sum_view(cr->out, p.a->n, static_cast<int64_t>(p.out0), info[2 * k]);
+        direct.push_back(k);
+        r0.push_back(static_cast<int64_t>(p.out0));
+        rm.push_back(info[2 * k]);
+      }
+      std::shared_ptr<SharedBlock> blk = cr->out;
+      std::vector<int64_t> first = r0, kept = rm;
+      if (drop && !direct.empty())
+        blk = drop_ranges(*cr->out, r0, rm, plan->o.drop_abs, first, kept, plan->home);
+      for (size_t j = 0; j < direct.size(); ++j) {
+        const Product& p = cr->prods[direct[j]];
+        res[p.idx] = sum_view(blk, p.a->n, first[j], kept[j]);
       }
       cr->out.reset();  // the views own the block now
     }
-    for (int t = 0; t < plan->nb; ++t) {
+    // the compactions ran on the plan's stream: done before the caller's work
+    if (drop) PAULI_HIP(hipStreamSynchronize(plan->home));
+    for (int t = 0; t < plan->nb; ++t)
       if (!res[t]) {
         const int32_t odt =
             plan->o.mode == PAULI_MERGE_COMPENSATED ? PAULI_C64 : plan->a[t]->dtype;
         res[t] = new_sum(plan->a[t]->n, 0, 0, odt, st);
       }
-      if (plan->o.drop_abs >= 0.0 && res[t]->m > 0) {
-        paulisum* kept = drop_terms(res[t], plan->o.drop_abs, st);
-        free_sum(res[t]);
-        res[t] = kept;
-      }
-    }
   } catch (...) {
     for (paulisum* r : res) free_sum(r);
     throw;

@@ -17,6 +17,7 @@
 //
 // The same pipeline serves a materialised sum (term source) and the fused
 // outer product (pair source, no product is ever stored).
+#include <algorithm>
 #include <cmath>
 #include <memory>
 #include <optional>
@@ -518,7 +519,9 @@ paulisum* merge_w(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
 // finds the same flags again and copies the kept terms.  Wave w of a block
 // owns the tile positions [w*64*kRoundsC, (w+1)*64*kRoundsC) in rounds of 64
 // and ranks its kept terms by ballots.  Only the phase bytes (and, for a
-// drop, the coefficients) are read twice.
+// drop, the coefficients) are read twice.  Tile b is [b*kTileC, min(m,
+// (b+1)*kTileC)) of one sum, or, given a tile table tb, [tb[2b], tb[2b+1])
+// (at most kTileC terms) of a block holding several sums.
 constexpr int kCompact = 256;
 constexpr int kRoundsC = 16;
 constexpr int kTileC = kCompact * kRoundsC;
@@ -533,25 +536,40 @@ __device__ __forceinline__ bool keep_term(const cplx<T>* __restrict__ c,
 // Kept terms of the wave's part of tile blockIdx.x.
 template <typename T>
 __device__ __forceinline__ uint32_t wave_kept(const cplx<T>* __restrict__ c,
-                                              const uint8_t* __restrict__ ph, int64_t m,
+                                              const uint8_t* __restrict__ ph, int64_t end,
                                               double drop, int marked, int64_t w0, int lane) {
   uint32_t n = 0;
 #pragma unroll 4
   for (int r = 0; r < kRoundsC; ++r) {
     const int64_t t = w0 + r * 64 + lane;
-    n += static_cast<uint32_t>(__popcll(__ballot(t < m && keep_term(c, ph, t, drop, marked))));
+    n += static_cast<uint32_t>(__popcll(__ballot(t < end && keep_term(c, ph, t, drop, marked))));
   }
   return n;
+}
+
+// First and end position of this block's tile.
+__device__ __forceinline__ void tile_range(const int64_t* __restrict__ tb, int64_t m,
+                                           int64_t& base, int64_t& end) {
+  if (tb) {
+    base = tb[2 * blockIdx.x];
+    end = tb[2 * blockIdx.x + 1];
+  } else {
+    base = blockIdx.x * static_cast<int64_t>(kTileC);
+    end = m;
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kCompact)
 k_keep_count(const cplx<T>* __restrict__ c, const uint8_t* __restrict__ ph, int64_t m,
-             double drop, int marked, uint32_t* __restrict__ bcount) {
+             const int64_t* __restrict__ tb, double drop, int marked,
+             uint32_t* __restrict__ bcount) {
   __shared__ uint32_t sw[kCompact / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t w0 = blockIdx.x * static_cast<int64_t>(kTileC) + wave * (64 * kRoundsC);
-  const uint32_t n = wave_kept(c, ph, m, drop, marked, w0, lane);
+  int64_t base, end;
+  tile_range(tb, m, base, end);
+  const int64_t w0 = base + wave * (64 * kRoundsC);
+  const uint32_t n = wave_kept(c, ph, end, drop, marked, w0, lane);
   if (lane == 0) sw[wave] = n;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -566,16 +584,17 @@ template <typename T>
 __global__ void __launch_bounds__(kCompact)
 k_compact(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
           const uint8_t* __restrict__ ph, const cplx<T>* __restrict__ c,
-          const uint64_t* __restrict__ fp, int W, int64_t m, int64_t ld, double drop, int marked,
-          const uint32_t* __restrict__ boff, uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ,
-          uint8_t* __restrict__ Oph, cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp,
-          int64_t ldo) {
+          const uint64_t* __restrict__ fp, int W, int64_t m, const int64_t* __restrict__ tb,
+          int64_t ld, double drop, int marked, const uint32_t* __restrict__ boff,
+          uint64_t* __restrict__ OX, uint64_t* __restrict__ OZ, uint8_t* __restrict__ Oph,
+          cplx<T>* __restrict__ Oc, uint64_t* __restrict__ Ofp, int64_t ldo) {
   __shared__ uint32_t sw[kCompact / 64];
   __shared__ uint16_t s_pos[kTileC];  // tile positions of the kept terms, in order
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kTileC);
+  int64_t base, end;
+  tile_range(tb, m, base, end);
   const int64_t w0 = base + wave * (64 * kRoundsC);
-  const uint32_t n = wave_kept(c, ph, m, drop, marked, w0, lane);
+  const uint32_t n = wave_kept(c, ph, end, drop, marked, w0, lane);
   if (lane == 0) sw[wave] = n;
   __syncthreads();
   uint32_t o = 0, total = 0;
@@ -586,7 +605,7 @@ k_compact(const uint64_t* __restrict__ X, const uint64_t* __restrict__ Z,
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int r = 0; r < kRoundsC; ++r) {
     const int64_t t = w0 + r * 64 + lane;
-    const bool k = t < m && keep_term(c, ph, t, drop, marked);
+    const bool k = t < end && keep_term(c, ph, t, drop, marked);
     const uint64_t bal = __ballot(k);
     if (k) s_pos[o + __popcll(bal & lt)] = static_cast<uint16_t>(t - base);
     o += static_cast<uint32_t>(__popcll(bal));
@@ -628,7 +647,7 @@ paulisum* drop_t(const paulisum* a, double drop_abs, bool marked, hipStream_t s)
   DBuf work(scan_workspace_bytes(nb), s);
   const auto c = static_cast<const cplx<T>*>(a->coef);
   hipLaunchKernelGGL(k_keep_count<T>, dim3(static_cast<unsigned>(nb)), dim3(kCompact), 0, s, c,
-                     a->ph, m, drop, marked ? 1 : 0, cnt.as<uint32_t>());
+                     a->ph, m, nullptr, drop, marked ? 1 : 0, cnt.as<uint32_t>());
   scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), nb, tot.as<uint32_t>(), work.p, s);
   uint32_t kept = 0;
   PAULI_HIP(hipMemcpyAsync(&kept, tot.p, 4, hipMemcpyDeviceToHost, s));
@@ -636,7 +655,7 @@ paulisum* drop_t(const paulisum* a, double drop_abs, bool marked, hipStream_t s)
   paulisum* out = new_sum(a->n, kept, kept, a->dtype, s);
   if (kept > 0)
     hipLaunchKernelGGL(k_compact<T>, dim3(static_cast<unsigned>(nb)), dim3(kCompact), 0, s, a->X,
-                       a->Z, a->ph, c, a->fp, a->W, m, a->ld, drop, marked ? 1 : 0,
+                       a->Z, a->ph, c, a->fp, a->W, m, nullptr, a->ld, drop, marked ? 1 : 0,
                        off.as<uint32_t>(), out->X, out->Z, out->ph,
                        static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
   PAULI_HIP(hipGetLastError());
@@ -649,6 +668,71 @@ paulisum* drop_terms(const paulisum* a, double drop_abs, hipStream_t s, bool mar
   if (a->m == 0) return new_sum(a->n, 0, 0, a->dtype, s);
   if (a->dtype == PAULI_C128) return drop_t<double>(a, drop_abs, marked, s);
   return drop_t<float>(a, drop_abs, marked, s);
+}
+
+namespace {
+
+template <typename T>
+std::shared_ptr<SharedBlock> drop_ranges_t(const SharedBlock& in, const std::vector<int64_t>& r0,
+                                           const std::vector<int64_t>& rm, double drop_abs,
+                                           std::vector<int64_t>& first,
+                                           std::vector<int64_t>& kept, hipStream_t s) {
+  const size_t nr = r0.size();
+  std::vector<int64_t> tiles;   // (first, end) of every tile
+  std::vector<size_t> tile0(nr + 1);  // first tile of every range
+  for (size_t k = 0; k < nr; ++k) {
+    tile0[k] = tiles.size() / 2;
+    for (int64_t b = r0[k]; b < r0[k] + rm[k]; b += kTileC) {
+      tiles.push_back(b);
+      tiles.push_back(std::min<int64_t>(b + kTileC, r0[k] + rm[k]));
+    }
+  }
+  const int64_t nt = static_cast<int64_t>(tiles.size() / 2);
+  tile0[nr] = static_cast<size_t>(nt);
+  first.assign(nr, 0);
+  kept.assign(nr, 0);
+  if (nt == 0) return std::make_shared<SharedBlock>(in.W, 0, in.dtype, s);
+  const double drop = drop_abs >= 0.0 ? drop_abs : -1.0;  // threshold, not squared
+  DBuf tb(static_cast<size_t>(nt) * 16, s), cnt((nt + 1) * 4, s), off((nt + 1) * 4, s),
+      tot(4, s), work(scan_workspace_bytes(nt), s);
+  PAULI_HIP(hipMemcpyAsync(tb.p, tiles.data(), tb.bytes, hipMemcpyHostToDevice, s));
+  const auto c = static_cast<const cplx<T>*>(in.coef);
+  hipLaunchKernelGGL(k_keep_count<T>, dim3(static_cast<unsigned>(nt)), dim3(kCompact), 0, s, c,
+                     in.ph, int64_t{0}, tb.as<int64_t>(), drop, 0, cnt.as<uint32_t>());
+  scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), nt, tot.as<uint32_t>(), work.p, s);
+  std::vector<uint32_t> offs(static_cast<size_t>(nt) + 1);
+  PAULI_HIP(hipMemcpyAsync(offs.data(), off.p, 4 * nt, hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipMemcpyAsync(offs.data() + nt, tot.p, 4, hipMemcpyDeviceToHost, s));
+  PAULI_HIP(hipStreamSynchronize(s));
+  for (size_t k = 0; k < nr; ++k) {
+    first[k] = offs[tile0[k]];
+    kept[k] = static_cast<int64_t>(offs[tile0[k + 1]]) - first[k];
+  }
+  const int64_t total = offs[static_cast<size_t>(nt)];
+  auto out = std::make_shared<SharedBlock>(in.W, total, in.dtype, s);
+  if (total > 0)
+    hipLaunchKernelGGL(k_compact<T>, dim3(static_cast<unsigned>(nt)), dim3(kCompact), 0, s, in.X,
+                       in.Z, in.ph, c, in.fp, in.W, int64_t{0}, tb.as<int64_t>(), in.ld, drop, 0,
+                       off.as<uint32_t>(), out->X, out->Z, out->ph,
+                       static_cast<cplx<T>*>(out->coef), out->fp, out->ld);
+  PAULI_HIP(hipGetLastError());
+  return out;
+}
+
+}  // namespace
+
+std::shared_ptr<SharedBlock> drop_ranges(const SharedBlock& in, const std::vector<int64_t>& r0,
+                                         const std::vector<int64_t>& rm, double drop_abs,
+                                         std::vector<int64_t>& first, std::vector<int64_t>& kept,
+                                         hipStream_t s) {
+  if (r0.size() != rm.size()) fail(PAULI_ERR_INVALID, "range lists of different lengths");
+  for (size_t k = 0; k < r0.size(); ++k)
+    if (r0[k] < 0 || rm[k] < 0 || r0[k] + rm[k] > in.ld)
+      fail(PAULI_ERR_INVALID, "a range outside the block");
+  if (in.dtype == PAULI_C128)
+    return drop_ranges_t<double>(in, r0, rm, drop_abs, first, kept, s);
+  if (in.dtype == PAULI_C64) return drop_ranges_t<float>(in, r0, rm, drop_abs, first, kept, s);
+  fail(PAULI_ERR_INVALID, "a block of stored coefficients is complex128 or complex64");
 }
 
 namespace {

@@ -166,6 +166,55 @@ def test_batched_drop_and_tune_file(tmp_path):
     assert e.value.status == "INVALID"
 
 
+def _threshold_between(vals, q):
+    """A threshold halfway between two neighbouring distinct moduli near
+    quantile q, so that no modulus lies within rounding of it."""
+    u = np.unique(vals)
+    k = max(1, min(len(u) - 1, int(q * len(u))))
+    t = 0.5 * (u[k - 1] + u[k])
+    assert np.min(np.abs(vals - t)) > 1e-9 * t
+    return float(t)
+
+
+@pytest.mark.parametrize("key_bits", [0, 32])
+def test_batched_drop_is_one_compaction_of_the_kept_terms(key_bits):
+    """The drop of a batched call keeps, product by product and in order,
+    exactly the terms of the undropped batched result with |c| >= drop_abs,
+    every array bit for bit; products span several 4096-term tiles with a
+    ragged end, one product loses every term, and with a 32-bit key one
+    product collides and is recomputed (its drop applied there)."""
+    plan = [(500, 150, 100), (64, 300, 40), (128, 1, 3), (500, 90, 130), (256, 70, 70),
+            (500, 1000, 1000)]
+    pairs = [synth.workload4_batch(700 + b, n, m1, m2) for b, (n, m1, m2) in enumerate(plan)]
+    for k in (0, 2, 5):
+        A, B = pairs[k]
+        pairs[k] = (dict(A, coef=A["coef"].astype(np.complex128)),
+                    dict(B, coef=B["coef"].astype(np.complex128)))
+    A, B = pairs[4]
+    pairs[4] = (dict(A, coef=(A["coef"] * np.float32(1e-9)).astype(A["coef"].dtype)), B)
+    GA = [pl.PauliSum.from_dict(A) for A, _ in pairs]
+    GB = [pl.PauliSum.from_dict(B) for _, B in pairs]
+    full = [o.export() for o in pl.outer_product_batched(GA, GB, key_bits=key_bits)]
+    mods = np.concatenate([np.abs(g["coef"].astype(np.complex128)) for g in full])
+    t = _threshold_between(np.concatenate(
+        [np.abs(g["coef"].astype(np.complex128)) for k, g in enumerate(full) if k != 4]), 0.4)
+    assert np.min(np.abs(mods - t)) > 1e-9 * t
+    assert np.max(np.abs(full[4]["coef"].astype(np.complex128))) < t
+    outs = pl.outer_product_batched(GA, GB, drop_abs=t, key_bits=key_bits)
+    kept_total = 0
+    for g, o in zip(full, outs):
+        d = o.export()
+        keep = np.abs(g["coef"].astype(np.complex128)) >= t
+        kept_total += int(keep.sum())
+        for k in ("x", "z", "fp", "phase"):
+            assert np.array_equal(d[k], g[k][keep]), k
+        assert d["coef"].dtype == g["coef"].dtype
+        assert np.array_equal(d["coef"].view(np.uint8), g["coef"][keep].view(np.uint8))
+    assert len(outs[4].export()["x"]) == 0
+    assert 0 < kept_total < len(mods)
+    assert len(full[0]["x"]) > 2 * 4096
+
+
 def test_batched_collisions_recomputed():
     """A 32-bit key makes fingerprint collisions certain in 1e6-record
     products: those products are recomputed by the general pipeline after
