@@ -215,6 +215,24 @@ def test_batched_drop_is_one_compaction_of_the_kept_terms(key_bits):
     assert len(full[0]["x"]) > 2 * 4096
 
 
+def test_batched_plan_drop_matches_the_eager_call():
+    """A graph plan with a drop threshold: the results of two replays (each
+    compacted once per class) equal the eager batched call bit for bit."""
+    pairs, GA, GB = _pairs_mixed()
+    eager = [o.export() for o in pl.outer_product_batched(GA, GB, drop_abs=0.02)]
+    P = pl.BatchPlan(GA, GB, drop_abs=0.02)
+    runs = []
+    for _ in range(2):
+        P.run()
+        runs.append([o.export() for o in P.results()])
+    P.destroy()
+    for res in runs:
+        for t, (g, e) in enumerate(zip(res, eager)):
+            for k in ("x", "z", "fp", "phase"):
+                assert np.array_equal(g[k], e[k]), (t, k)
+            assert np.array_equal(g["coef"].view(np.uint8), e["coef"].view(np.uint8)), t
+
+
 def test_batched_collisions_recomputed():
     """A 32-bit key makes fingerprint collisions certain in 1e6-record
     products: those products are recomputed by the general pipeline after
