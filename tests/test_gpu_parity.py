@@ -50,6 +50,22 @@ def test_outer_product_bitexact(n, m1, m2):
     assert np.array_equal(g["fp"], parity.fingerprint(x, z))
 
 
+@pytest.mark.parametrize("n", [64, 128, 512, 1024])
+def test_fused_full_words(n):
+    """Qubit counts that fill their last word (no spare bits in a row),
+    up to the largest width the library takes: the fused product of two
+    sums with phases and repeated strings, over a few buckets with a ragged
+    last one, in FP64 and in the precision form."""
+    A, B = _dup_sum(30 + n, n, 130, 90), _dup_sum(31 + n, n, 117, 80)
+    GA, GB = _gsum(A), _gsum(B)
+    ref = O.product_merge(_osum(A), _osum(B))
+    g = pl.outer_product_merged(GA, GB).export()
+    parity.assert_merged_fp64(g, ref)
+    parity.assert_sorted_by_key(g)
+    g32 = pl.outer_product_merged(GA, GB, mode=pl.COMPENSATED, tau=0.3).export()
+    parity.assert_compensated(g32, ref)
+
+
 def test_outer_product_c64_bitexact():
     n = 200
     A, B = _rand(1, n, 70), _rand(2, n, 90)
