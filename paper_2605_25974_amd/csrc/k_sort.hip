@@ -103,6 +103,33 @@ k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __rest
   }
 }
 
+// A scan of at most kScanTile elements in one launch (the three passes of
+// the general scan in one block); in may equal out, and total may point
+// just past out.
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_one(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __restrict__ nd,
+           uint32_t* total) {
+  if (nd && *nd < n) n = *nd;
+  const int64_t base = threadIdx.x * static_cast<int64_t>(kScanItems);
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + r;
+    v[r] = i < n ? in[i] : 0;
+    s += v[r];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan<uint32_t>(s, &tot);
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + r;
+    if (i < n) out[i] = run;
+    run += v[r];
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
 // ----------------------------------------------------------------- radix
 
 __global__ void __launch_bounds__(kRsBlock)
@@ -225,6 +252,11 @@ size_t scan_workspace_bytes(int64_t n) {
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                         void* work, hipStream_t s, const uint32_t* nd) {
+  if (n <= kScanTile) {  // one block: one launch instead of three
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanBlock), 0, s, in, out, n, nd, total);
+    PAULI_HIP(hipGetLastError());
+    return;
+  }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   uint32_t* partial = static_cast<uint32_t*>(work);
   if (n > 0)
