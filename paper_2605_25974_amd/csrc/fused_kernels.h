@@ -55,8 +55,14 @@ namespace pauli {
 namespace {
 
 
-constexpr int kTile = 4096;  // records per partition tile
-constexpr int kItems = kTile / kB;
+// The generation kernels: blocks of kGenNT threads over partition tiles of
+// kTile records (16 per thread).  Large tiles give long runs of equal digits
+// in the scatter's output (64 records on average at 128 digits), whose writes
+// cover whole lines.
+constexpr int kGenNT = 512;
+constexpr int kItems = 16;
+constexpr int kTile = kGenNT * kItems;
+static_assert(kTile <= 65536, "tile positions are 16-bit");
 constexpr int kSortNT = 512;
 constexpr int kSortWaves = kSortNT / 64;
 constexpr int kSortBlocksPerCU = 2;  // two bucket sorts share a compute unit's LDS
@@ -330,7 +336,7 @@ __device__ __forceinline__ void gen_product(const GenBatch& bt, uint32_t sg, Gen
 // Digit histogram of one partition tile.  Count layout: super-bucket s owns
 // C[tb[s]*256, tb[s+1]*256) as [digit][tile], so one exclusive scan of C
 // gives every (s, digit, tile) its output offset.
-__global__ void __launch_bounds__(kB)
+__global__ void __launch_bounds__(kGenNT)
 k_gcount(GenSides G, GenBatch bt, const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb,
          uint32_t nc, int shift, uint32_t mask, uint32_t* __restrict__ C) {
   __shared__ uint32_t hist[256];
@@ -338,14 +344,14 @@ k_gcount(GenSides G, GenBatch bt, const uint32_t* __restrict__ S, const uint32_t
   uint32_t s, tl, sl;
   if (!tile_of(blockIdx.x, tb, nc, s, tl)) return;
   gen_product(bt, s, G, sl, shift, mask);
-  hist[threadIdx.x] = 0;
+  if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   const uint32_t lo = tl * kTile;
   const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
   load_gen_row(G, sl, lo, hi, R);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const uint32_t q = lo + r * kB + threadIdx.x;
+    const uint32_t q = lo + r * kGenNT + threadIdx.x;
     if (q < hi) {
       uint64_t k;
       uint32_t v;
@@ -355,7 +361,7 @@ k_gcount(GenSides G, GenBatch bt, const uint32_t* __restrict__ S, const uint32_t
   }
   __syncthreads();
   const uint32_t ns = tb[s + 1] - tb[s];
-  C[tb[s] * 256u + threadIdx.x * ns + tl] = hist[threadIdx.x];
+  if (threadIdx.x < 256) C[tb[s] * 256u + threadIdx.x * ns + tl] = hist[threadIdx.x];
 }
 
 // Stable scatter of one partition tile's generated records.  Wave w owns
@@ -366,11 +372,11 @@ k_gcount(GenSides G, GenBatch bt, const uint32_t* __restrict__ S, const uint32_t
 // staged in LDS, in digit order; the record is generated again when its
 // digit's run is written (coalesced), which keeps the kernel small enough
 // for many resident blocks.
-__global__ void __launch_bounds__(kB)
+__global__ void __launch_bounds__(kGenNT)
 k_gscatter(GenSides G, GenBatch bt, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
            const uint32_t* __restrict__ S, const uint32_t* __restrict__ tb, uint32_t nc, int shift,
            uint32_t mask, const uint32_t* __restrict__ C) {
-  constexpr int NW = kB / 64;
+  constexpr int NW = kGenNT / 64;
   __shared__ uint16_t s_pos[kTile];
   __shared__ uint32_t s_start[256], s_goff[256];
   __shared__ uint32_t s_wc[NW][256];
@@ -383,9 +389,12 @@ k_gscatter(GenSides G, GenBatch bt, uint64_t* __restrict__ kout, uint32_t* __res
   const uint32_t lo = tl * kTile;
   const uint32_t hi = S[s] - lo < kTile ? S[s] : lo + kTile;
   const uint32_t ns = tb[s + 1] - tb[s];
+  const bool dig = tid < 256;  // threads 0-255 own one digit each
+  if (dig) {
 #pragma unroll
-  for (int w = 0; w < NW; ++w) s_wc[w][tid] = 0;
-  s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
+    for (int w = 0; w < NW; ++w) s_wc[w][tid] = 0;
+    s_goff[tid] = C[tb[s] * 256u + tid * ns + tl];
+  }
   load_gen_row(G, sl, lo, hi, R);
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
@@ -420,16 +429,20 @@ k_gscatter(GenSides G, GenBatch bt, uint64_t* __restrict__ kout, uint32_t* __res
   __syncthreads();
   // digit starts inside the tile, then each (wave, digit) start
   uint32_t tot = 0;
+  if (dig) {
 #pragma unroll
-  for (int w = 0; w < NW; ++w) tot += s_wc[w][tid];
+    for (int w = 0; w < NW; ++w) tot += s_wc[w][tid];
+  }
   const uint32_t dstart = block_excl<NW>(tot, nullptr, sh);
-  s_start[tid] = dstart;
-  uint32_t run = dstart;
+  if (dig) {
+    s_start[tid] = dstart;
+    uint32_t run = dstart;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const uint32_t c = s_wc[w][tid];
-    s_wc[w][tid] = run;
-    run += c;
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t c = s_wc[w][tid];
+      s_wc[w][tid] = run;
+      run += c;
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -440,7 +453,7 @@ k_gscatter(GenSides G, GenBatch bt, uint64_t* __restrict__ kout, uint32_t* __res
     }
   __syncthreads();
   const uint32_t cnt = hi - lo;
-  for (uint32_t e = tid; e < cnt; e += kB) {
+  for (uint32_t e = tid; e < cnt; e += kGenNT) {
     uint64_t kk;
     uint32_t vv;
     gen_record(G, R, lo + s_pos[e], kk, vv);

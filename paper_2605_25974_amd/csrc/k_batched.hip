@@ -618,10 +618,10 @@ void launch_class(ClassRun& cr, hipStream_t s) {
                        cr.nt);
     scan_exclusive_u32(cr.nt, cr.tb, cr.nsb, cr.tb + cr.nsb, cr.w_sb, s);
     const GenBatch bt{cr.sbprod, cr.sbbase, cr.gen, cr.shift, cr.mask};
-    hipLaunchKernelGGL(k_gcount, dim3(cr.gb), dim3(kB), 0, s, GenSides{}, bt, cr.S, cr.tb,
+    hipLaunchKernelGGL(k_gcount, dim3(cr.gb), dim3(kGenNT), 0, s, GenSides{}, bt, cr.S, cr.tb,
                        cr.nsb, 0, 0u, cr.C);
     scan_exclusive_u32(cr.C, cr.C, static_cast<int64_t>(cr.gb) * 256, nullptr, cr.w_c, s);
-    hipLaunchKernelGGL(k_gscatter, dim3(cr.gb), dim3(kB), 0, s, GenSides{}, bt, cr.K, cr.V, cr.S,
+    hipLaunchKernelGGL(k_gscatter, dim3(cr.gb), dim3(kGenNT), 0, s, GenSides{}, bt, cr.K, cr.V, cr.S,
                        cr.tb, cr.nsb, 0, 0u, cr.C);
     hipLaunchKernelGGL(k_bbucket_offsets, dim3(grid_for(cr.nbk + 1)), dim3(kB), 0, s, cr.bprod,
                        cr.bbase, cr.sbbase, cr.d2tab, cr.soff, cr.tb, cr.C, cr.nbk, cr.nsb,

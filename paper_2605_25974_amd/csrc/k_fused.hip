@@ -139,12 +139,12 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
                   A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
                   Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
                   Tt.as<uint32_t>(), static_cast<uint32_t>(a->m), ibits, d1};
-      hipLaunchKernelGGL(k_gcount, dim3(gb), dim3(kB), 0, s, gs, GenBatch{}, S.as<uint32_t>(),
+      hipLaunchKernelGGL(k_gcount, dim3(gb), dim3(kGenNT), 0, s, gs, GenBatch{}, S.as<uint32_t>(),
                          tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       DBuf w3(scan_workspace_bytes(static_cast<int64_t>(gb) * 256), s);
       scan_exclusive_u32(C.as<uint32_t>(), C.as<uint32_t>(), static_cast<int64_t>(gb) * 256,
                          nullptr, w3.p, s);
-      hipLaunchKernelGGL(k_gscatter, dim3(gb), dim3(kB), 0, s, gs, GenBatch{}, K2, V2,
+      hipLaunchKernelGGL(k_gscatter, dim3(gb), dim3(kGenNT), 0, s, gs, GenBatch{}, K2, V2,
                          S.as<uint32_t>(),
                          tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       hipLaunchKernelGGL(k_bucket_offsets, dim3(grid_for(nbk + 1)), dim3(kB), 0, s,
