@@ -351,21 +351,36 @@ __global__ void k_check_bound(const uint32_t* __restrict__ m, int64_t bound,
   if (static_cast<int64_t>(*m) > bound) atomicOr(flag, 1u);
 }
 
-// nb = M2 - m: the new records of a step (both counts on the device).
-__global__ void k_new_count(const uint32_t* __restrict__ M2, const uint32_t* __restrict__ m,
-                            uint32_t* __restrict__ nb) {
-  *nb = *M2 - *m;
+// nb = M2 - m: the new records of a step (both counts on the device; m
+// taken at most m_bound, as the step's kernels take it).  More than
+// nb_bound new records are cut to nb_bound, M2 with them, and raise the
+// capacity flag, so that no later kernel of the step reads past what the
+// sort and the merge path wrote.
+__global__ void k_new_count(uint32_t* __restrict__ M2, const uint32_t* __restrict__ m,
+                            int64_t m_bound, int64_t nb_bound, uint32_t* __restrict__ nb,
+                            uint32_t* __restrict__ flag) {
+  const int64_t mm = static_cast<int64_t>(*m) < m_bound ? static_cast<int64_t>(*m) : m_bound;
+  int64_t n = static_cast<int64_t>(*M2) - mm;  // M2 >= mm: every processed term gives a record
+  if (n > nb_bound) {
+    if (flag) atomicOr(flag, 1u);
+    n = nb_bound;
+    *M2 = static_cast<uint32_t>(mm + n);
+  }
+  *nb = static_cast<uint32_t>(n);
 }
 
 // One rotation step in device-count form: the sorted state s holds *md
-// terms (at most mb); the merged successor goes to dv.into, its count to
-// *dv.U.  The same kernels as the host-count steps, every size read on the
-// device (no host synchronisation), grids and buffers sized for the bounds.
+// terms (at most mb), of which at most nbb give a new string; the merged
+// successor goes to dv.into, its count to *dv.U.  The same kernels as the
+// host-count steps, every size read on the device (no host
+// synchronisation), grids and buffers sized for the bounds.  With nb_seen
+// (a measuring run only) the step's count of new strings is read back.
 template <typename T>
 void conjugate_dev(const paulisum* s, const RotString& P, double theta, const MergeArgs& o,
-                   bool all_new, int64_t mb, const uint32_t* md, const DevRun& dv0,
-                   hipStream_t st) {
-  const int64_t M2b = 2 * mb;
+                   bool all_new, int64_t mb, int64_t nbb, int64_t* nb_seen, const uint32_t* md,
+                   const DevRun& dv0, hipStream_t st) {
+  if (nbb > mb) nbb = mb;
+  const int64_t M2b = mb + nbb;
   DBuf cnt((mb + 1) * 4, st), off((mb + 1) * 4, st), ctr(64, st);
   DBuf work(scan_workspace_bytes(mb), st);
   uint32_t* M2d = ctr.as<uint32_t>();
@@ -377,7 +392,13 @@ void conjugate_dev(const paulisum* s, const RotString& P, double theta, const Me
     hipLaunchKernelGGL(k_rot_count, dim3(g), dim3(kBlock), 0, st, s->X, s->Z, s->ld, mb, md, P,
                        cnt.as<uint32_t>());
   scan_exclusive_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), mb, M2d, work.p, st, md);
-  hipLaunchKernelGGL(k_new_count, dim3(1), dim3(1), 0, st, M2d, md, nbd);
+  hipLaunchKernelGGL(k_new_count, dim3(1), dim3(1), 0, st, M2d, md, mb, nbb, nbd, dv0.flag);
+  if (nb_seen) {
+    uint32_t h = 0;
+    PAULI_HIP(hipMemcpyAsync(&h, nbd, 4, hipMemcpyDeviceToHost, st));
+    PAULI_HIP(hipStreamSynchronize(st));
+    *nb_seen = h;
+  }
   const int kshift = 64 - o.key_bits;
   DBuf keys(M2b * 8ull + 8, st), vals(M2b * 4ull + 4, st), kk(mb * 8 + 8, st), kv(mb * 4 + 4, st);
   DBuf nk(mb * 8 + 8, st), nv(mb * 4 + 4, st), nk2(mb * 8 + 8, st), nv2(mb * 4 + 4, st);
@@ -387,8 +408,8 @@ void conjugate_dev(const paulisum* s, const RotString& P, double theta, const Me
   PAULI_HIP(hipGetLastError());
   uint64_t* bk = nk.as<uint64_t>();
   uint32_t* bv = nv.as<uint32_t>();
-  if (mb > 1 && sort_records_bucketed(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), mb,
-                                      o.key_bits, st, nbd)) {
+  if (nbb > 1 && sort_records_bucketed(bk, bv, nk2.as<uint64_t>(), nv2.as<uint32_t>(), nbb,
+                                       o.key_bits, st, nbd)) {
     bk = nk2.as<uint64_t>();
     bv = nv2.as<uint32_t>();
   }
@@ -396,7 +417,7 @@ void conjugate_dev(const paulisum* s, const RotString& P, double theta, const Me
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
-                     kk.as<uint64_t>(), kv.as<uint32_t>(), mb, bk, bv, mb, md, nbd,
+                     kk.as<uint64_t>(), kv.as<uint32_t>(), mb, bk, bv, nbb, md, nbd,
                      keys.as<uint64_t>(), vals.as<uint32_t>());
   PAULI_HIP(hipGetLastError());
   DevRun dv = dv0;
@@ -436,9 +457,10 @@ struct PropPlan {
   hipGraphExec_t exec = nullptr;
   int last = 0;  // the state holding the result
   bool ran = false;
-  // host bounds of the state entering each step and of the result (from a
-  // measuring run of the same sequence; empty: min(capacity, |s| 2^t))
-  std::vector<int64_t> bounds;
+  // host bounds of the state entering each step and of the result, and of
+  // each step's new strings (from a measuring run of the same sequence;
+  // empty: min(capacity, |s| 2^t), and the state's bound)
+  std::vector<int64_t> bounds, new_bounds;
   ~PropPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (priv && ev_out) {
@@ -490,7 +512,8 @@ int64_t read_count(const uint32_t* c, hipStream_t st) {
 // The loop's launch sequence on stream st (no host synchronisation).  With
 // `measured`, the sequence runs eagerly and the count of every state is
 // read back after it is formed (the plan's measuring run).
-void launch_loop(PropPlan& pl, hipStream_t st, std::vector<int64_t>* measured = nullptr) {
+void launch_loop(PropPlan& pl, hipStream_t st, std::vector<int64_t>* measured = nullptr,
+                 std::vector<int64_t>* measured_new = nullptr) {
   uint32_t* cnt = pl.counts.as<uint32_t>();
   hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, st, cnt, 4);  // counts and flag
   ScratchScope scratch(pl.tmp.p, pl.tmp_bytes);
@@ -523,13 +546,22 @@ void launch_loop(PropPlan& pl, hipStream_t st, std::vector<int64_t>* measured = 
     hipLaunchKernelGGL(k_check_bound, dim3(1), dim3(1), 0, st, cnt + cur, mb, cnt + 3);
     DevRun d{nullptr, &pl.state[nxt], cnt + nxt, cnt + 3};
     const bool all_new = pl.mode == PAULI_ROTATE_PRODUCT;
+    int64_t nbb = mb;
+    if (static_cast<size_t>(t) < pl.new_bounds.size() && pl.new_bounds[t] < mb)
+      nbb = pl.new_bounds[t];
+    int64_t seen = 0;
+    int64_t* ps = measured_new ? &seen : nullptr;
     if (pl.ff)
-      conjugate_dev<ff>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+      conjugate_dev<ff>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, nbb, ps, cnt + cur, d,
+                        st);
     else if (pl.in->dtype == PAULI_C128)
-      conjugate_dev<double>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+      conjugate_dev<double>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, nbb, ps, cnt + cur,
+                            d, st);
     else
-      conjugate_dev<float>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, cnt + cur, d, st);
+      conjugate_dev<float>(&pl.state[cur], P, pl.theta[t], ms, all_new, mb, nbb, ps, cnt + cur, d,
+                           st);
     if (measured) measured->push_back(read_count(cnt + nxt, st));
+    if (measured_new) measured_new->push_back(seen);
     bound = 2 * mb;
     cur = nxt;
   }
@@ -587,16 +619,22 @@ PropPlan* prop_plan_create(const paulisum* s, int steps, const uint64_t* px, con
   pl->tmp = DBuf(pl->tmp_bytes, st);
   PAULI_HIP(hipStreamSynchronize(st));  // the buffers exist before the capture
   // measuring run: the same sequence, eagerly, reading back every state's
-  // size; the graph's kernels are then sized for those (with a margin; a
-  // count above a bound is cut on the device and raises the flag)
+  // size and every step's count of new strings; the graph's kernels are
+  // then sized for those (with a margin; a count above a bound is cut on
+  // the device and raises the flag)
   {
     NoEvents ne;
-    std::vector<int64_t> sizes;
-    launch_loop(*pl, st, &sizes);
+    std::vector<int64_t> sizes, news;
+    launch_loop(*pl, st, &sizes, &news);
     pl->bounds.clear();
     for (size_t k = 0; k < sizes.size(); ++k) {
       const int64_t b = sizes[k] + sizes[k] / 64 + 4096;
       pl->bounds.push_back(b < cap ? b : cap);
+    }
+    pl->new_bounds.clear();
+    for (size_t k = 0; k < news.size(); ++k) {
+      const int64_t b = news[k] + news[k] / 64 + 4096;
+      pl->new_bounds.push_back(b < cap ? b : cap);
     }
   }
   capture_loop(*pl);

@@ -132,3 +132,23 @@ def test_plan_capacity():
     P.run()
     parity.assert_merged_fp64(P.result().export(),
                               O.propagate(_osum(S), x, z, th, mode=O.PRODUCT))
+
+
+@pytest.mark.parametrize("mode", [pl.PLAIN, pl.COMPENSATED])
+def test_plan_full_state_matches_eager_loop(mode):
+    """The 1e6-term state of the propagation workload through 6 conjugation
+    steps as one graph, with its kernels sized from the measuring run (state
+    and new-string bounds well below the doubling bound): bit-equal to the
+    host-synchronised loop, whose full-size parity against the oracle is
+    checked elsewhere."""
+    S = synth.workload5_state()
+    th, x, z = synth.workload5_rotations(steps=6)
+    G = pl.PauliSum.from_dict(S)
+    P = pl.PropagatePlan(G, x, z, th, max_terms=len(S["coef"]) * 4, mode=mode, drop_abs=1e-10)
+    P.run()
+    P.run()
+    g = P.result().export()
+    P.destroy()
+    eager = pl.propagate(G, x, z, th, mode=mode, drop_abs=1e-10).export()
+    assert len(g["coef"]) > len(S["coef"])
+    _same(g, eager)
