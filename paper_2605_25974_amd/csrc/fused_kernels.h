@@ -9,7 +9,8 @@
 // the key name the product's bucket.  Stages:
 //
 //  1 prep      per operand: rows of word pairs (X_w, Z_w), coefficient +
-//              fingerprint + phase metadata, key, and a stable sort of its
+//              fingerprint + phase metadata (in the row's slot when the row
+//              leaves room in its cache line), key, and a stable sort of its
 //              terms by class (top d1 key bits).
 //  2 gen       the products of class hA of a and class hB of b all have top
 //              bits hA ^ hB, so super-bucket s is the union of the class
@@ -124,13 +125,14 @@ __global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restri
                         int kshift, int cshift, int d1, uint64_t* __restrict__ rows,
                         Aux<T>* __restrict__ aux, uint64_t* __restrict__ key,
                         uint64_t* __restrict__ cls, uint32_t* __restrict__ idx) {
+  const int SW = slot_words(Wp);
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
     int y = 0;
     for (int w = 0; w < Wp; ++w) {
       const uint64_t x = w < W ? X[w * ld + t] : 0ull;
       const uint64_t z = w < W ? Z[w * ld + t] : 0ull;
-      rows[static_cast<size_t>(t) * 2 * Wp + 2 * w] = x;
-      rows[static_cast<size_t>(t) * 2 * Wp + 2 * w + 1] = z;
+      rows[static_cast<size_t>(t) * SW + 2 * w] = x;
+      rows[static_cast<size_t>(t) * SW + 2 * w + 1] = z;
       y += popc64(x & z);
     }
     Aux<T> x;
@@ -142,6 +144,8 @@ __global__ void k_fprep(const uint64_t* __restrict__ X, const uint64_t* __restri
     x.w[3] = static_cast<uint64_t>((ph[t] + y) & 3) | (static_cast<uint64_t>(y & 1) << 2) |
              (c_id << 8);
     aux[t] = x;
+    if (Wp <= 4)
+      for (int q = 0; q < 4; ++q) rows[static_cast<size_t>(t) * SW + 2 * Wp + q] = x.w[q];
     key[t] = k;
     cls[t] = c_id;
     idx[t] = t;

@@ -94,12 +94,13 @@ __global__ void k_bprep(const SumDesc* __restrict__ sums, const uint32_t* __rest
     const uint32_t u = sum_of(start, nsums, r);
     const SumDesc& D = sums[u];
     const uint32_t t = r - start[u];
+    const int SW = slot_words(Wp);
     int y = 0;
     for (int w = 0; w < Wp; ++w) {
       const uint64_t x = w < D.W ? D.X[w * D.ld + t] : 0ull;
       const uint64_t z = w < D.W ? D.Z[w * D.ld + t] : 0ull;
-      rows[static_cast<size_t>(r) * 2 * Wp + 2 * w] = x;
-      rows[static_cast<size_t>(r) * 2 * Wp + 2 * w + 1] = z;
+      rows[static_cast<size_t>(r) * SW + 2 * w] = x;
+      rows[static_cast<size_t>(r) * SW + 2 * w + 1] = z;
       y += popc64(x & z);
     }
     const cplx<T> c = static_cast<const cplx<T>*>(D.coef)[t];
@@ -112,6 +113,8 @@ __global__ void k_bprep(const SumDesc* __restrict__ sums, const uint32_t* __rest
     a.w[3] = static_cast<uint64_t>((D.ph[t] + y) & 3) | (static_cast<uint64_t>(y & 1) << 2) |
              (cid << 8);
     aux[r] = a;
+    if (Wp <= 4)
+      for (int q = 0; q < 4; ++q) rows[static_cast<size_t>(r) * SW + 2 * Wp + q] = a.w[q];
     key[r] = k;
     ckey[r] = (static_cast<uint64_t>(u) << 8) | cid;
     gidx[r] = r;
@@ -349,7 +352,7 @@ void setup_class(ClassRun& cr, hipStream_t s) {
   Carve cv;
   auto side_pieces = [&](uint32_t tot, uint32_t ns, std::vector<size_t>& id) {
     const size_t n = std::max<uint32_t>(tot, 1);
-    id.push_back(cv.add(n * 2 * G * 8));           // rows
+    id.push_back(cv.add(n * slot_words(G) * 8));   // rows
     id.push_back(cv.add(n * sizeof(Aux<T>)));      // aux
     for (int k = 0; k < 4; ++k) id.push_back(cv.add(n * 8));  // key ckey ckey2 skey
     for (int k = 0; k < 3; ++k) id.push_back(cv.add(n * 4));  // gidx gidx2 sidx
@@ -549,8 +552,8 @@ void setup_class(ClassRun& cr, hipStream_t s) {
       const auto& sl = p.sym ? cr.sumsA : cr.sumsB;
       for (uint32_t u = 0; u < ub; ++u) rowB += static_cast<uint32_t>(sl[u]->m);
       OpT& o = ops[k];
-      o.ra = cr.A.rows + static_cast<size_t>(rowA) * 2 * G;
-      o.rb = sbs.rows + static_cast<size_t>(rowB) * 2 * G;
+      o.ra = cr.A.rows + static_cast<size_t>(rowA) * slot_words(G);
+      o.rb = sbs.rows + static_cast<size_t>(rowB) * slot_words(G);
       o.xa = static_cast<const Aux<T>*>(cr.A.aux) + rowA;
       o.xb = static_cast<const Aux<T>*>(sbs.aux) + rowB;
       o.ma = p.m1;

@@ -23,7 +23,7 @@ template <typename T>
 void prep_side(const paulisum* t, int Wp, int kb, int d1, SidePrep<T>& P, hipStream_t s) {
   const uint32_t m = static_cast<uint32_t>(t->m);
   const uint32_t nc = 1u << d1;
-  P.rows = DBuf(static_cast<size_t>(m) * 2 * Wp * 8, s);
+  P.rows = DBuf(static_cast<size_t>(m) * slot_words(Wp) * 8, s);
   P.aux = DBuf(static_cast<size_t>(m) * sizeof(Aux<T>), s);
   P.key = DBuf(m * 8ull, s);
   P.cls = DBuf(m * 8ull, s);
