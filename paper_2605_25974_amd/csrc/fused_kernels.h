@@ -492,7 +492,12 @@ __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32
 constexpr int kBinBits = 13;
 constexpr int kBins = 1 << kBinBits;
 constexpr int kBinWords = kBins / 2;
-constexpr uint32_t kMaxBin = 64;  // a bucket with a larger bin takes k_heavy_sort
+// A bucket with a larger bin (many equal keys) takes the LDS radix sort.  A
+// record's place in its bin costs one pass over the bin, so a full bin costs
+// kMaxBin^2 LDS reads; 256 keeps most buckets of inputs with many repeated
+// strings (products at n = 64) on the counting sort (segment stage 1.73 ->
+// 1.46 ms there; 64 sent them to the radix sort).
+constexpr uint32_t kMaxBin = 256;
 constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited for
 
 struct SortSmem {

@@ -31,6 +31,7 @@ def _repeating(n, m, seed):
 
 @pytest.mark.parametrize("n,m,bits", [
     (70, 600, None),  # buckets of ~5600 records: the bin of P (600 equal keys) -> radix sort
+    (70, 200, None),  # buckets of ~2500 records: a bin of 200 equal keys, ranked in the bin
     (500, 600, 10),   # small buckets, the same repeated string
     (70, 300, 2),     # 4 buckets of ~22,500 records: the global-memory sort
     (500, 300, 16),   # many tiny buckets
