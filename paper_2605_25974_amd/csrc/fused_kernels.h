@@ -20,7 +20,7 @@
 //              straight into their buckets (each record written once).  For
 //              a sum times itself only the tiles hA <= hB are generated and
 //              each record stands for an unordered pair.
-//  3 sort      per bucket, in LDS: counting sort on the 14 key bits below
+//  3 sort      per bucket, in LDS: counting sort on the 13 key bits below
 //              the bucket bits, then each bin in (key, pair id) order; writes
 //              the sorted pair ids and each record's segment index (equal
 //              keys = one segment).  A bucket with a bin of many equal keys
@@ -486,8 +486,8 @@ __global__ void k_bucket_offsets(const uint32_t* __restrict__ soff, const uint32
 
 // ------------------------------------------------------------ bucket sort
 
-// Counting sort of a bucket: 2^14 bins on the key bits just below the bucket
-// bits, two 16-bit counters per word (a bucket holds at most kCap = 8192
+// Counting sort of a bucket: 2^13 bins on the key bits just below the bucket
+// bits, two 16-bit counters per word (a bucket holds at most kCap = 4096
 // records, so neither counts nor starts carry into the other half).
 constexpr int kBinBits = 13;
 constexpr int kBins = 1 << kBinBits;
@@ -513,10 +513,10 @@ struct SortSmem {
 };
 
 // Bit fields of the bucket sort: the counting sort takes bits
-// [lo14, lo14 + 14) (lo14 < 0: not used), the radix sort bits
+// [locnt, locnt + kBinBits) (locnt < 0: not used), the radix sort bits
 // [lo16, lo16 + 8*passes) with ties on fmask finished on the full key.
 struct SortField {
-  int lo14;
+  int locnt;
   int lo16;
   int passes;
   uint64_t fmask;
@@ -526,7 +526,7 @@ struct SortField {
 // The fields for rem key bits below the bucket bits.
 inline SortField sort_field_for(int rem) {
   SortField sf;
-  sf.lo14 = rem >= kBinBits ? rem - kBinBits : -1;
+  sf.locnt = rem >= kBinBits ? rem - kBinBits : -1;
   if (rem >= 16) {
     sf.lo16 = rem - 16;
     sf.passes = 2;
@@ -671,7 +671,7 @@ __device__ __forceinline__ uint32_t bin_start(const SortSmem& S, uint32_t d) {
 }
 
 // Counting sort of a bucket, first half: the (key, id) pairs k[], v[] are
-// counted in 2^14 bins of the key bits at lo (a record's place in its bin
+// counted in 2^13 bins of the key bits at lo (a record's place in its bin
 // comes from an LDS atomic) and scattered to S.key / S.id grouped by bin.
 // Returns false, with S.key / S.id untouched, when a bin holds more than
 // kMaxBin records (many equal keys).  k[], v[] are not read afterwards.
@@ -906,8 +906,8 @@ __device__ void bucket_segments(uint32_t b, uint32_t lo, uint32_t n, SortSmem& S
   if (threadIdx.x == 0) out.nseg[b] = total;
 }
 
-// Buckets that fit in LDS, counting sort.  One block per compute unit
-// takes the buckets blockIdx.x, blockIdx.x + gridDim.x, ...; once a bucket
+// Buckets that fit in LDS, counting sort.  Each block (kSortBlocksPerCU per
+// compute unit) takes the buckets blockIdx.x, blockIdx.x + gridDim.x, ...; once a bucket
 // is scattered into bins, the block loads the records of its next bucket,
 // so that the loads overlap the rest of the work.  A bucket over kCap
 // records is queued for k_heavy_sort, one with a bin of more than kMaxBin
@@ -929,7 +929,7 @@ k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
   for (; b < nbk; b += gridDim.x) {
     const SortField f = sort_field(sb, b, f0);
     const bool fits = n <= static_cast<uint32_t>(kCap);
-    const bool ok = fits && count_scatter(n, f.lo14, k, v, S);
+    const bool ok = fits && count_scatter(n, f.locnt, k, v, S);
     // every load of this bucket has been used: the wait is free, and it
     // keeps the compiler from waiting for the next bucket's loads when it
     // reuses their registers
@@ -942,7 +942,7 @@ k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
     }
     load_bucket(keys, out.vals, lo2, n2, k, v);
     if (ok) {
-      count_order(n, f.lo14, S);
+      count_order(n, f.locnt, S);
       bucket_segments<true>(b, lo, n, S, out);
     } else if (threadIdx.x == 0) {
       if (fits) redo[atomicAdd(nredo, 1u)] = b;

@@ -302,7 +302,7 @@ void plan_products(ClassRun& cr) {
     else if (p.Peff > cr.par.target)
       d = static_cast<int>(std::ceil(std::log2(p.Peff / cr.par.target)));
     if (d > kMaxBits) d = kMaxBits;
-    if (d > cr.kb - 30) d = cr.kb - 30;  // keep 14 + 16 key bits below the bucket bits
+    if (d > cr.kb - 30) d = cr.kb - 30;  // keep 30 key bits below the bucket bits
     if (d < 0) d = 0;
     p.d = d;
     p.d1 = std::min(d, cr.par.d1cap);

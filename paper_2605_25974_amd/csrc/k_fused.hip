@@ -164,10 +164,10 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
   SegOut so{V, segidx.as<uint32_t>(), nseg.as<uint32_t>(), long_list.as<uint32_t>(), ctr32 + 1};
   {
     StageScope sc(PAULI_STAGE_SEGMENT, s, Peff * 20.0);
-    // one block per compute unit (the LDS of a block fills most of one)
+    // two blocks per compute unit (the LDS of a block fills about half of one)
     const uint32_t cus = kSortBlocksPerCU * device_cus();
     const uint32_t gsort = nbk < cus ? nbk : cus;
-    if (sf.lo14 >= 0) {
+    if (sf.locnt >= 0) {
       // the buckets the counting sort gives up on take the radix sort
       hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
                          nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),
@@ -180,8 +180,8 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
       hipLaunchKernelGGL(k_bucket_radix, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
                          nbk, nullptr, nullptr, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32);
     }
-    // one block per compute unit: a workload of many equal strings can make
-    // most buckets heavy
+    // as many blocks as the counting sort: a workload of many equal strings
+    // can make most buckets heavy
     hipLaunchKernelGGL(k_heavy_sort, dim3(gsort), dim3(kSortNT), 0, s, K, K2, V2,
                        boff.as<uint32_t>(), rem, SortBatch{}, heavy.as<uint32_t>(), ctr32, so);
     PAULI_HIP(hipGetLastError());
@@ -319,7 +319,7 @@ bool sort_records_bucketed(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   StageScope sc(PAULI_STAGE_SORT, s, n * 24.0);
   const uint32_t cus = kSortBlocksPerCU * device_cus();
   const uint32_t gsort = nbk < cus ? nbk : cus;
-  if (sf.lo14 >= 0) {
+  if (sf.locnt >= 0) {
     hipLaunchKernelGGL(k_bucket_count, dim3(gsort), dim3(kSortNT), 0, s, K, boff.as<uint32_t>(),
                        nbk, sf, SortBatch{}, so, heavy.as<uint32_t>(), ctr32, redo.as<uint32_t>(),
                          ctr32 + 6);
