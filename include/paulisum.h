@@ -84,7 +84,9 @@ typedef struct {
  *                  buckets by the top bits of their key, each bucket sorted
  *                  in LDS; 0..16 (0: from bucket_records).
  *  bucket_records  records per bucket the bucket bits aim at (the tile size
- *                  of the LDS bucket sort), 256..8192; default 7000.
+ *                  of the LDS bucket sort), 256..8192; default 3500.  A
+ *                  bucket over 4096 records (the LDS capacity) is sorted in
+ *                  global memory instead.
  *  class_bits      at most this many of a product's bucket bits come from
  *                  the class tiles of the record generation; the rest
  *                  (at most 8) form the radix digit of its partition pass
