@@ -309,13 +309,17 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // FP64 sum of the records at bucket positions q0 .. q1-1, in order, from the
-// operands' own coefficients (the re-merge of a cancelled segment).
+// operands' own coefficients (the re-merge of a cancelled segment).  The
+// operands come by value: passed by reference, they had to live in scratch
+// memory for the whole kernel (the precision form's write stage at n = 500
+// took 6.68 instead of 5.72 ms).
 template <int G, int WT, typename T>
-__device__ __noinline__ cplx<double> remerge64(const ExpandArgs& E, const Operands<WT, T>& op,
-                                               uint32_t lo, uint32_t q0, uint32_t q1, int gl) {
+__device__ __noinline__ cplx<double> remerge64(const uint32_t* __restrict__ vals,
+                                               Operands<WT, T> op, uint32_t lo, uint32_t q0,
+                                               uint32_t q1, int gl) {
   double re = 0.0, im = 0.0;
   for (uint32_t q = q0; q < q1; ++q) {
-    const Rec<G, double> r = load_rec<G, WT, T, double>(op, E.vals[lo + q], gl);
+    const Rec<G, double> r = load_rec<G, WT, T, double>(op, vals[lo + q], gl);
     re = re + r.re;
     im = im + r.im;
   }
@@ -524,7 +528,7 @@ k_expand(ExpandArgs E, Operands<WT, T> op0) {
         auto emit = [&](uint32_t seg, uint32_t q0, uint32_t q1) {
           TV vr = acc.value_re(), vi = acc.value_im();
           if (MODE == kComp && acc.cancels(E.tau)) {
-            const cplx<double> c = remerge64<G, WT, T>(E, op, lo, q0, q1, gl);
+            const cplx<double> c = remerge64<G, WT, T>(E.vals, op, lo, q0, q1, gl);
             vr = static_cast<TV>(c.re);
             vi = static_cast<TV>(c.im);
           }
