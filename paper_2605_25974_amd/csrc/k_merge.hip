@@ -325,9 +325,12 @@ paulisum* run_pipeline(const Src& src, int n, int64_t N, int32_t dt, uint64_t* k
   sc_seg.emplace(PAULI_STAGE_SEGMENT, s, N * (12.0 + 4.0 + sizeof(cplx<TV>)));
   hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, nd,
                      head, v, ctr + 0, 0);
-  hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, head, N,
+  // the next two return at once unless a key run holds several strings
+  // (rare): a grid of a few blocks per compute unit, not one thread per record
+  const unsigned gd = g < 2048u ? g : 2048u;
+  hipLaunchKernelGGL((k_fix_runs<WT, Src>), dim3(gd), dim3(kBlock), 0, s, src, keys, vals, head, N,
                      nd, ctr + 0);
-  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(g), dim3(kBlock), 0, s, src, keys, vals, N, nd,
+  hipLaunchKernelGGL((k_heads<WT, TV, Src>), dim3(gd), dim3(kBlock), 0, s, src, keys, vals, N, nd,
                      head, v, ctr + 0, 1);
   PAULI_HIP(hipGetLastError());
 
