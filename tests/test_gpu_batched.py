@@ -233,6 +233,35 @@ def test_batched_plan_drop_matches_the_eager_call():
             assert np.array_equal(g["coef"].view(np.uint8), e["coef"].view(np.uint8)), t
 
 
+@pytest.mark.parametrize("tau", [1e-3, 0.3])
+def test_batched_compensated_remerge(tau):
+    """Cancelling segments in the batched launch sequence: two Hermitian
+    squares (sums times themselves, exact cancellations) and a product
+    whose FP32 inputs lose 2^-30 (the FP64 re-merge must recover it exactly)
+    in one batch; the re-merge reads each product's own operands."""
+    H1, H2 = synth.workload3(m=400), synth.workload3(m=260)
+    G1, G2 = pl.PauliSum.from_dict(H1), pl.PauliSum.from_dict(H2)
+    n = 5
+    A = {"n": n, "x": np.array([[0], [1]], np.uint64), "z": np.zeros((2, 1), np.uint64),
+         "phase": None, "coef": np.array([1.0 + 2.0 ** -30, -1.0], np.complex128)}
+    B = {"n": n, "x": np.array([[0], [1]], np.uint64), "z": np.zeros((2, 1), np.uint64),
+         "phase": None, "coef": np.array([1.0, 1.0], np.complex128)}
+    GA, GB = pl.PauliSum.from_dict(A), pl.PauliSum.from_dict(B)
+    outs = pl.outer_product_batched([G1, GA, G2], [G1, GB, G2], mode=pl.COMPENSATED, tau=tau)
+    for H, o in ((H1, outs[0]), (H2, outs[2])):
+        g = o.export()
+        ref = O.product_merge(_osum(H), _osum(H))
+        parity.assert_compensated(g, ref)
+        gi, ri = parity.align(g["x"], g["z"], ref.x, ref.z)
+        zero = ref.coef[ri] == 0
+        assert np.any(zero)
+        assert np.all(np.abs(g["coef"][gi][zero]) <= 1e-12 * ref.mass[ri][zero])
+    r = outs[1].export()
+    ref = O.product_merge(_osum(A), _osum(B))
+    gi, ri = parity.align(r["x"], r["z"], ref.x, ref.z)
+    assert np.all(r["coef"] == np.complex64(2.0 ** -30))
+
+
 def test_batched_collisions_recomputed():
     """A 32-bit key makes fingerprint collisions certain in 1e6-record
     products: those products are recomputed by the general pipeline after
