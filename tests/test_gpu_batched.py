@@ -42,6 +42,28 @@ def test_batched_mixed_widths_match_oracle(mode):
         parity.assert_sorted_by_key(g)
 
 
+@pytest.mark.parametrize("mode", [pl.PLAIN, pl.COMPENSATED])
+def test_batched_wide_strings(mode):
+    """Products above 512 qubits (the widest class, 16 words) beside narrower
+    ones in one batch, against the oracle."""
+    plan = [(700, 90, 140), (1024, 120, 75), (513, 40, 60), (64, 100, 80)]
+    pairs = [synth.workload4_batch(600 + b, n, m1, m2) for b, (n, m1, m2) in enumerate(plan)]
+    for k, (A, B) in enumerate(pairs):
+        pairs[k] = (dict(A, coef=A["coef"].astype(np.complex128)),
+                    dict(B, coef=B["coef"].astype(np.complex128)))
+    GA = [pl.PauliSum.from_dict(A) for A, _ in pairs]
+    GB = [pl.PauliSum.from_dict(B) for _, B in pairs]
+    outs = pl.outer_product_batched(GA, GB, mode=mode, tau=0.3)
+    for (A, B), o in zip(pairs, outs):
+        g = o.export()
+        ref = O.product_merge(_osum(A), _osum(B))
+        if mode == pl.PLAIN:
+            parity.assert_merged_fp64(g, ref)
+        else:
+            parity.assert_compensated(g, ref)
+        parity.assert_sorted_by_key(g)
+
+
 def test_batched_autotune_gives_the_single_product_result():
     """Products above the tuning threshold (2^22) are run at three bucket
     widths; the kept result equals the plain single call bit for bit."""
