@@ -136,6 +136,9 @@ def _row_keys(x, z):
 def distinct(rng, draw, m: int):
     """Draw strings with ``draw(rng, count)`` until m distinct ones exist;
     keeps first occurrences in draw order."""
+    if m <= 0:  # the words' shape from one draw
+        x, z = draw(rng, 1)
+        return np.ascontiguousarray(x[:0]), np.ascontiguousarray(z[:0])
     xs, zs = [], []
     have = 0
     seen = None
