@@ -493,11 +493,14 @@ constexpr int kBinBits = 13;
 constexpr int kBins = 1 << kBinBits;
 constexpr int kBinWords = kBins / 2;
 // A bucket with a larger bin (many equal keys) takes the LDS radix sort.  A
-// record's place in its bin costs one pass over the bin, so a full bin costs
-// kMaxBin^2 LDS reads; 256 keeps most buckets of inputs with many repeated
-// strings (products at n = 64) on the counting sort (segment stage 1.73 ->
-// 1.46 ms there; 64 sent them to the radix sort).
-constexpr uint32_t kMaxBin = 256;
+// record's place in its bin costs one pass over the bin; a bin of more than
+// kSmallBin records that holds a single key (one repeated string) is ranked
+// on pair ids alone.  512 keeps the buckets of inputs with many repeated
+// strings on the counting sort (segment stage of a 10,000 x 10,000 product
+// at n = 64: 1.73 ms with 64, 1.46 with 256, 1.37 with 512 and the one-key
+// ranking; the 2,000 x 2,000 product at n = 16: 0.25 -> 0.12 ms).
+constexpr uint32_t kMaxBin = 512;
+constexpr uint32_t kSmallBin = 16;  // larger bins are checked for holding one key only
 constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited for
 
 struct SortSmem {
@@ -508,6 +511,8 @@ struct SortSmem {
     uint32_t bins[kBinWords + 1];   // counting sort: counts, then starts; bin kBins starts at N
   };
   uint16_t perm[kCap];  // counting sort: position of the p-th record in key / id
+  uint32_t mixed[kBins / 32];  // counting sort: large bins holding more than one key
+  uint32_t cflag;  // counting sort: 1 a bin over kSmallBin records, 2 a bin over kMaxBin
   uint32_t scan[kSortWaves];
   uint32_t wcount[kSortWaves];
 };
@@ -673,14 +678,16 @@ __device__ __forceinline__ uint32_t bin_start(const SortSmem& S, uint32_t d) {
 // Counting sort of a bucket, first half: the (key, id) pairs k[], v[] are
 // counted in 2^13 bins of the key bits at lo (a record's place in its bin
 // comes from an LDS atomic) and scattered to S.key / S.id grouped by bin.
-// Returns false, with S.key / S.id untouched, when a bin holds more than
-// kMaxBin records (many equal keys).  k[], v[] are not read afterwards.
-__device__ bool count_scatter(uint32_t N, int lo, const uint64_t (&k)[kSortRounds],
+// Returns 0, with S.key / S.id untouched, when a bin holds more than
+// kMaxBin records (many equal keys); else 2 when a bin holds more than
+// kSmallBin records, 1 when none does.  k[], v[] are not read afterwards.
+__device__ int count_scatter(uint32_t N, int lo, const uint64_t (&k)[kSortRounds],
                               const uint32_t (&v)[kSortRounds], SortSmem& S) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t span = sort_span(N);
   const int rounds = static_cast<int>(span / 64);
   for (int i = threadIdx.x; i <= kBinWords; i += kSortNT) S.bins[i] = 0;
+  if (threadIdx.x == 0) S.cflag = 0;
   __syncthreads();
   // a lane past the end adds 0 to a counter of its own
   uint32_t dd[kSortRounds], old[kSortRounds];
@@ -708,8 +715,14 @@ __device__ bool count_scatter(uint32_t N, int lo, const uint64_t (&k)[kSortRound
     tot += c0 + c1;
     mx = max(mx, max(c0, c1));
   }
-  uint32_t run = block_excl<kSortWaves>(tot, nullptr, S.scan);
-  if (__syncthreads_or(mx > kMaxBin)) return false;
+  if (mx > kSmallBin) atomicOr(&S.cflag, mx > kMaxBin ? 3u : 1u);
+  uint32_t run = block_excl<kSortWaves>(tot, nullptr, S.scan);  // (its barriers order the flag)
+  const uint32_t fl = S.cflag;
+  if (fl & 2u) {
+    __syncthreads();  // every thread has read the flag before the next bucket clears it
+    return 0;
+  }
+  const int large = (fl & 1u) ? 2 : 1;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const uint32_t c0 = w[i] & 0xFFFFu, c1 = w[i] >> 16;
@@ -738,7 +751,7 @@ __device__ bool count_scatter(uint32_t N, int lo, const uint64_t (&k)[kSortRound
     }
   }
   __syncthreads();
-  return true;
+  return large;
 }
 
 // Counting sort, second half: every bin is put in (key, id) order.  The
@@ -746,10 +759,28 @@ __device__ bool count_scatter(uint32_t N, int lo, const uint64_t (&k)[kSortRound
 // records in the bin, and S.perm[p] = where the p-th record lies in S.key /
 // S.id.  Equal keys end up ordered by pair id, so the result does not
 // depend on the order of the atomics.
-__device__ void count_order(uint32_t N, int lo, SortSmem& S) {
+__device__ void count_order(uint32_t N, int lo, SortSmem& S, bool large) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t span = sort_span(N);
   const int rounds = static_cast<int>(span / 64);
+  if (large) {
+    // which large bins hold more than one key: records of one repeated
+    // string fill a large bin with one key, ordered by pair id alone
+    for (int i = threadIdx.x; i < kBins / 32; i += kSortNT) S.mixed[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (r >= rounds) break;
+      const uint32_t q = wave * span + r * 64 + lane;
+      if (q < N) {
+        const uint64_t kq = S.key[q];
+        const uint32_t d = static_cast<uint32_t>(kq >> lo) & (kBins - 1u);
+        const uint32_t s0 = bin_start(S, d), e0 = bin_start(S, d + 1);
+        if (e0 - s0 > kSmallBin && kq != S.key[s0]) atomicOr(&S.mixed[d >> 5], 1u << (d & 31u));
+      }
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     if (r >= rounds) break;
@@ -760,7 +791,11 @@ __device__ void count_order(uint32_t N, int lo, SortSmem& S) {
       const uint32_t d = static_cast<uint32_t>(kq >> lo) & (kBins - 1u);
       const uint32_t s0 = bin_start(S, d), e0 = bin_start(S, d + 1);
       uint32_t p = q;
-      if (e0 - s0 > 1) {
+      if (e0 - s0 > kSmallBin && ((S.mixed[d >> 5] >> (d & 31u)) & 1u) == 0) {
+        uint32_t rank = 0;  // one key in the bin: the pair id decides
+        for (uint32_t y = s0; y < e0; ++y) rank += S.id[y] < iq ? 1u : 0u;
+        p = s0 + rank;
+      } else if (e0 - s0 > 1) {
         uint32_t rank = 0;
         for (uint32_t y = s0; y < e0; ++y) {
           const uint64_t ky = S.key[y];
@@ -929,7 +964,8 @@ k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
   for (; b < nbk; b += gridDim.x) {
     const SortField f = sort_field(sb, b, f0);
     const bool fits = n <= static_cast<uint32_t>(kCap);
-    const bool ok = fits && count_scatter(n, f.locnt, k, v, S);
+    const int cs = fits ? count_scatter(n, f.locnt, k, v, S) : 0;
+    const bool ok = cs != 0;
     // every load of this bucket has been used: the wait is free, and it
     // keeps the compiler from waiting for the next bucket's loads when it
     // reuses their registers
@@ -942,7 +978,7 @@ k_bucket_count(const uint64_t* keys, const uint32_t* __restrict__ boff,
     }
     load_bucket(keys, out.vals, lo2, n2, k, v);
     if (ok) {
-      count_order(n, f.locnt, S);
+      count_order(n, f.locnt, S, cs == 2);
       bucket_segments<true>(b, lo, n, S, out);
     } else if (threadIdx.x == 0) {
       if (fits) redo[atomicAdd(nredo, 1u)] = b;
