@@ -307,7 +307,7 @@ pauli_status_t pauli_batch_plan_destroy(pauli_batch_plan_t plan);
 /* The autotuner's table of launch shapes per class, as text (one class per
  * line): pauli_tune_save writes it, pauli_tune_load merges a saved one into
  * the table.  INVALID if the file cannot be written or read, or a line is
- * malformed. */
+ * malformed (then no line of the file is applied). */
 pauli_status_t pauli_tune_save(const char* path);
 pauli_status_t pauli_tune_load(const char* path);
 

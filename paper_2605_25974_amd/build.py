@@ -4,6 +4,8 @@ Every source under csrc/ is compiled by hipcc for gfx950 only, with
 floating-point contraction off (the plain coefficient product is rounded
 operation by operation) and packed-FP32 instructions disabled, then linked
 into one shared library that exports the C ABI of include/paulisum.h.
+`python build.py --asan` builds a host-side AddressSanitizer variant under
+_build/asan/ instead (a checking aid; the package never loads it).
 """
 from __future__ import annotations
 
@@ -31,13 +33,33 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+# Host-side AddressSanitizer build (a checking aid, never loaded by the
+# package): the host code of every unit is instrumented, the device code is
+# not.  The library is linked without the sanitizer runtime; a process that
+# loads it preloads that runtime (asan_runtime()).
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libpaulisum_asan.so")
+ASAN_FLAGS = [f for f in FLAGS if f != "-O3"] + [
+    "-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src, flags=None, outdir=None):
+    obj = os.path.join(outdir or BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + (flags or FLAGS) + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s" % (src, r.stderr[-6000:]))
     return obj
+
+
+def _link(objs, lib):
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s" % r.stderr[-6000:])
+    os.replace(tmp, lib)
+    return lib
 
 
 def build(jobs: int | None = None) -> str:
@@ -46,15 +68,27 @@ def build(jobs: int | None = None) -> str:
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("link failed:\n%s" % r.stderr[-6000:])
-    os.replace(tmp, LIB)
-    return LIB
+    return _link(objs, LIB)
+
+
+def build_asan(jobs: int | None = None) -> str:
+    """Builds _build/asan/libpaulisum_asan.so with host-side ASan."""
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, ASAN_FLAGS, ASAN_DIR), srcs))
+    return _link(objs, ASAN_LIB)
+
+
+def asan_runtime() -> str | None:
+    """The compiler's shared ASan runtime (to preload), or None."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    return path if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path) else None
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build_asan() if "--asan" in sys.argv[1:] else build())
     sys.exit(0)

@@ -741,6 +741,8 @@ bool save_tune_locked(const std::string& path) {
 bool load_tune_locked(const std::string& path) {
   std::ifstream in(path);
   if (!in) return false;
+  // a malformed line rejects the whole file: nothing of it is applied
+  std::vector<std::pair<ClassKey, ClassParams>> rows;
   std::string line;
   while (std::getline(in, line)) {
     if (line.empty() || line[0] == '#') continue;
@@ -751,8 +753,10 @@ bool load_tune_locked(const std::string& path) {
     if (!(p.target >= 256.0 && p.target <= kCap) || p.d1cap < 0 || p.d1cap > 8 ||
         (p.parts != 1 && p.parts != 2 && p.parts != 4 && p.parts != 8))
       return false;
-    g_tune[k] = p;
+    rows.emplace_back(k, p);
   }
+  if (in.bad()) return false;
+  for (const auto& r : rows) g_tune[r.first] = r.second;
   return true;
 }
 

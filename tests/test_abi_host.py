@@ -115,3 +115,33 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pl, "_lib", None)
     with pytest.raises(pl.PauliLibraryMissing):
         pl.lib()
+
+
+def test_tune_file_round_trip_and_all_or_nothing(tmp_path):
+    """The tune table is host state: a saved file loads back unchanged, and a
+    file with one malformed line is refused as a whole (none of its lines
+    enter the table)."""
+    good = tmp_path / "good.txt"
+    good.write_text("# W log2_records dtype mode target class_bits parts\n"
+                    "8 27 1 0 3000 8 4\n")
+    pl.tune_load(str(good))
+    saved = tmp_path / "saved.txt"
+    pl.tune_save(str(saved))
+    rows = [ln.split() for ln in saved.read_text().splitlines() if not ln.startswith("#")]
+    assert ["8", "27", "1", "0", "3000", "8", "4"] in rows
+    mixed = tmp_path / "mixed.txt"
+    mixed.write_text("4 20 1 1 2000 6 2\n"   # valid
+                     "4 21 1 1 100 6 2\n")   # target below 256: malformed
+    with pytest.raises(pl.PauliError) as e:
+        pl.tune_load(str(mixed))
+    assert e.value.status == "INVALID"
+    pl.tune_save(str(saved))
+    rows = [ln.split() for ln in saved.read_text().splitlines() if not ln.startswith("#")]
+    assert not any(r[:2] == ["4", "20"] for r in rows)
+    for text in ("1 2 3\n", "8 27 1 0 3000 9 4\n", "8 27 1 0 3000 8 3\n", "8 27 1 0 nan 8 4\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        with pytest.raises(pl.PauliError):
+            pl.tune_load(str(bad))
+    with pytest.raises(pl.PauliError):
+        pl.tune_load(str(tmp_path / "missing.txt"))
