@@ -164,10 +164,27 @@ __global__ void k_class_count(const uint64_t* __restrict__ cls, uint32_t m,
   }
 }
 
+// The top 16 bits of a kb-bit key (left-aligned when kb < 16).  Every
+// digit the generation passes histogram lies in them (bucket bits <= 16).
+__host__ __device__ __forceinline__ uint16_t key_top16(uint64_t k, int kb) {
+  return static_cast<uint16_t>(kb >= 16 ? k >> (kb - 16) : k << (16 - kb));
+}
+
+// (key, term index) of a term in class order, as one 16-byte piece.
+__host__ __device__ __forceinline__ uint4 key_index(uint64_t k, uint32_t i) {
+  return make_uint4(static_cast<uint32_t>(k), static_cast<uint32_t>(k >> 32), i, 0u);
+}
+
 __global__ void k_gather_keys(const uint64_t* __restrict__ key, const uint32_t* __restrict__ sidx,
-                              uint32_t m, uint64_t* __restrict__ skey) {
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
-    skey[t] = key[sidx[t]];
+                              uint32_t m, int kb, uint64_t* __restrict__ skey,
+                              uint16_t* __restrict__ top, uint4* __restrict__ ki) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+    const uint32_t i = sidx[t];
+    const uint64_t k = key[i];
+    skey[t] = k;
+    top[t] = key_top16(k, kb);
+    ki[t] = key_index(k, i);
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
@@ -248,16 +265,19 @@ __device__ __forceinline__ bool tile_of(uint32_t tau, const uint32_t* tb, uint32
 struct GenSides {
   const uint32_t* gA;
   const uint32_t* gsA;
-  const uint32_t* sidxA;
-  const uint64_t* skeyA;
+  const uint4* kiA;  // key_index of each term of A in class order
   const uint32_t* gB;
   const uint32_t* gsB;
-  const uint32_t* sidxB;
-  const uint64_t* skeyB;
+  const uint4* kiB;
   const uint32_t* Tt;
   uint32_t ma;
   int ibits;
   int d1;
+  // key_top16 of the keys: the passes that need only a record's digit
+  // gather 2 bytes per side instead of 8 (fewer lines per gather)
+  const uint16_t* tA;
+  const uint16_t* tB;
+  int sh16;  // 16 - bucket bits: the digit is (tA ^ tB) >> sh16, masked
 };
 
 // The super-bucket's tile offsets and class sizes, staged in LDS, with
@@ -291,8 +311,8 @@ __device__ __forceinline__ void load_gen_row(const GenSides& G, uint32_t s, uint
   }
 }
 
-__device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, uint32_t q,
-                                           uint64_t& key, uint32_t& val) {
+// The operand positions a (in A's class order) and b of record q.
+__device__ __forceinline__ void gen_pair(const GenRow& R, uint32_t q, uint32_t& a, uint32_t& b) {
   uint32_t lo = R.h0, hi = R.h1 + 1;  // largest h with t[h] <= q
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -306,10 +326,26 @@ __device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, u
     ++ia;
     jb -= nb;
   }
-  const uint32_t a = R.a0[lo] + ia, b = R.b0[lo] + jb;
-  const uint32_t i = G.sidxA[a], j = G.sidxB[b];
-  key = G.skeyA[a] ^ G.skeyB[b];
+  a = R.a0[lo] + ia;
+  b = R.b0[lo] + jb;
+}
+
+__device__ __forceinline__ void gen_record(const GenSides& G, const GenRow& R, uint32_t q,
+                                           uint64_t& key, uint32_t& val) {
+  uint32_t a, b;
+  gen_pair(R, q, a, b);
+  const uint4 ea = G.kiA[a], eb = G.kiB[b];  // one 16-byte gather per side
+  const uint32_t i = ea.z, j = eb.z;
+  key = (static_cast<uint64_t>(ea.y ^ eb.y) << 32) | (ea.x ^ eb.x);
   val = G.ibits >= 0 ? ((j << G.ibits) | i) : j * G.ma + i;
+}
+
+// The digit of record q alone.
+__device__ __forceinline__ uint32_t gen_digit(const GenSides& G, const GenRow& R, uint32_t q,
+                                              uint32_t mask) {
+  uint32_t a, b;
+  gen_pair(R, q, a, b);
+  return (static_cast<uint32_t>(G.tA[a] ^ G.tB[b]) >> G.sh16) & mask;
 }
 
 // Products of a batched launch sequence: the super-buckets of all products
@@ -356,12 +392,7 @@ k_gcount(GenSides G, GenBatch bt, const uint32_t* __restrict__ S, const uint32_t
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t q = lo + r * kGenNT + threadIdx.x;
-    if (q < hi) {
-      uint64_t k;
-      uint32_t v;
-      gen_record(G, R, q, k, v);
-      atomicAdd(&hist[(k >> shift) & mask], 1u);
-    }
+    if (q < hi) atomicAdd(&hist[gen_digit(G, R, q, mask)], 1u);
   }
   __syncthreads();
   const uint32_t ns = tb[s + 1] - tb[s];
@@ -408,13 +439,7 @@ k_gscatter(GenSides G, GenBatch bt, uint64_t* __restrict__ kout, uint32_t* __res
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t q = lo + (static_cast<uint32_t>(wave) * kItems + r) * 64 + lane;
-    int d = -1;
-    if (q < hi) {
-      uint64_t k;
-      uint32_t v;
-      gen_record(G, R, q, k, v);
-      d = static_cast<int>((k >> shift) & mask);
-    }
+    const int d = q < hi ? static_cast<int>(gen_digit(G, R, q, mask)) : -1;
     const bool valid = d >= 0;
     uint64_t peers = __ballot(valid);
 #pragma unroll

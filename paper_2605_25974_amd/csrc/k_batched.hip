@@ -125,13 +125,14 @@ __global__ void k_bprep(const SumDesc* __restrict__ sums, const uint32_t* __rest
 // inside its own sum (the pair ids are local to a product).
 __global__ void k_bgather(const uint64_t* __restrict__ key, const uint32_t* __restrict__ gidx,
                           const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ start,
-                          uint32_t total, uint64_t* __restrict__ skey,
-                          uint32_t* __restrict__ sidx) {
+                          uint32_t total, int kb, uint16_t* __restrict__ top,
+                          uint4* __restrict__ ki) {
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < total;
        q += gridDim.x * blockDim.x) {
     const uint32_t r = gidx[q];
-    skey[q] = key[r];
-    sidx[q] = r - start[ckey[q] >> 8];
+    const uint64_t k = key[r];
+    top[q] = key_top16(k, kb);
+    ki[q] = key_index(k, r - start[ckey[q] >> 8]);
   }
 }
 
@@ -258,8 +259,10 @@ struct ClassRun {
   struct Side {
     uint64_t* rows;
     void* aux;
-    uint64_t *key, *ckey, *ckey2, *skey;
-    uint32_t *gidx, *gidx2, *sidx, *g, *gs;
+    uint64_t *key, *ckey, *ckey2;
+    uint16_t* top;  // key_top16 of the keys in class order
+    uint4* ki;      // key_index: (key, term index within its sum) in class order
+    uint32_t *gidx, *gidx2, *g, *gs;
     SumDesc* desc;
     uint32_t* start;
     void* rwork;
@@ -354,14 +357,16 @@ void setup_class(ClassRun& cr, hipStream_t s) {
     const size_t n = std::max<uint32_t>(tot, 1);
     id.push_back(cv.add(n * slot_words(G) * 8));   // rows
     id.push_back(cv.add(n * sizeof(Aux<T>)));      // aux
-    for (int k = 0; k < 4; ++k) id.push_back(cv.add(n * 8));  // key ckey ckey2 skey
-    for (int k = 0; k < 3; ++k) id.push_back(cv.add(n * 4));  // gidx gidx2 sidx
+    for (int k = 0; k < 3; ++k) id.push_back(cv.add(n * 8));  // key ckey ckey2
+    for (int k = 0; k < 2; ++k) id.push_back(cv.add(n * 4));  // gidx gidx2
     id.push_back(cv.add((ns * 256ull + 1) * 4));   // g
     id.push_back(cv.add((ns * 256ull + 1) * 4));   // gs
     id.push_back(cv.add(ns * sizeof(SumDesc)));    // desc
     id.push_back(cv.add((ns + 1) * 4ull));         // start
     id.push_back(cv.add(radix_workspace_bytes(n)));
     id.push_back(cv.add(scan_workspace_bytes(ns * 256ll)));
+    id.push_back(cv.add(n * 2));                   // top
+    id.push_back(cv.add(n * 16));                  // ki
   };
   std::vector<size_t> ia, ib;
   side_pieces(cr.totA, nsA, ia);
@@ -397,16 +402,16 @@ void setup_class(ClassRun& cr, hipStream_t s) {
     sd.key = static_cast<uint64_t*>(at(id[2]));
     sd.ckey = static_cast<uint64_t*>(at(id[3]));
     sd.ckey2 = static_cast<uint64_t*>(at(id[4]));
-    sd.skey = static_cast<uint64_t*>(at(id[5]));
-    sd.gidx = static_cast<uint32_t*>(at(id[6]));
-    sd.gidx2 = static_cast<uint32_t*>(at(id[7]));
-    sd.sidx = static_cast<uint32_t*>(at(id[8]));
-    sd.g = static_cast<uint32_t*>(at(id[9]));
-    sd.gs = static_cast<uint32_t*>(at(id[10]));
-    sd.desc = static_cast<SumDesc*>(at(id[11]));
-    sd.start = static_cast<uint32_t*>(at(id[12]));
-    sd.rwork = at(id[13]);
-    sd.swork = at(id[14]);
+    sd.gidx = static_cast<uint32_t*>(at(id[5]));
+    sd.gidx2 = static_cast<uint32_t*>(at(id[6]));
+    sd.g = static_cast<uint32_t*>(at(id[7]));
+    sd.gs = static_cast<uint32_t*>(at(id[8]));
+    sd.desc = static_cast<SumDesc*>(at(id[9]));
+    sd.start = static_cast<uint32_t*>(at(id[10]));
+    sd.rwork = at(id[11]);
+    sd.swork = at(id[12]);
+    sd.top = static_cast<uint16_t*>(at(id[13]));
+    sd.ki = static_cast<uint4*>(at(id[14]));
   };
   fill_side(cr.A, ia);
   if (cr.sideB) fill_side(cr.B, ib);
@@ -502,16 +507,17 @@ void setup_class(ClassRun& cr, hipStream_t s) {
     GenSides& gs = gen[k];
     gs.gA = sa.g + p.uA * 256u;
     gs.gsA = sa.gs + p.uA * 256u;
-    gs.sidxA = sa.sidx;
-    gs.skeyA = sa.skey;
+    gs.kiA = sa.ki;
     gs.gB = sbs.g + ub * 256u;
     gs.gsB = sbs.gs + ub * 256u;
-    gs.sidxB = sbs.sidx;
-    gs.skeyB = sbs.skey;
+    gs.kiB = sbs.ki;
     gs.Tt = cr.Tt + p.tt0;
     gs.ma = p.m1;
     gs.ibits = p.ibits;
     gs.d1 = p.d1;
+    gs.tA = sa.top;
+    gs.tB = sbs.top;
+    gs.sh16 = 16 - p.d;
     for (uint32_t x = 0; x < p.nc; ++x) sbprod[p.sb0 + x] = static_cast<uint16_t>(k);
     for (uint32_t x = 0; x < p.nbk; ++x) bprod[p.bb0 + x] = static_cast<uint16_t>(k);
     sbbase[k] = p.sb0;
@@ -595,7 +601,7 @@ void prep_side_b(ClassRun& cr, ClassRun::Side& sd, uint32_t tot, uint32_t ns, hi
     gi = sd.gidx2;
   }
   hipLaunchKernelGGL(k_bgather, dim3(grid_for(tot)), dim3(kB), 0, s, sd.key, gi, ck, sd.start,
-                     tot, sd.skey, sd.sidx);
+                     tot, cr.kb, sd.top, sd.ki);
   hipLaunchKernelGGL(k_class_count, dim3(grid_for(tot)), dim3(kB), 0, s, ck, tot, sd.g);
   scan_exclusive_u32(sd.g, sd.gs, ns * 256ll, sd.gs + ns * 256u, sd.swork, s);
   PAULI_HIP(hipGetLastError());

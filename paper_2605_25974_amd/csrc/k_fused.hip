@@ -15,7 +15,7 @@ namespace {
 
 template <typename T>
 struct SidePrep {
-  DBuf rows, aux, key, cls, cls2, idx, idx2, skey, g, gs;
+  DBuf rows, aux, key, cls, cls2, idx, idx2, skey, top, ki, g, gs;
   uint32_t* sidx = nullptr;
 };
 
@@ -31,6 +31,8 @@ void prep_side(const paulisum* t, int Wp, int kb, int d1, SidePrep<T>& P, hipStr
   P.idx = DBuf(m * 4ull, s);
   P.idx2 = DBuf(m * 4ull, s);
   P.skey = DBuf(m * 8ull, s);
+  P.top = DBuf(m * 2ull, s);
+  P.ki = DBuf(m * 16ull, s);
   P.g = DBuf(nc * 4ull, s);
   P.gs = DBuf(nc * 4ull + 4, s);
   hipLaunchKernelGGL(k_fprep<T>, dim3(grid_for(m)), dim3(kB), 0, s, t->X, t->Z, t->ph,
@@ -58,7 +60,8 @@ void prep_side(const paulisum* t, int Wp, int kb, int d1, SidePrep<T>& P, hipStr
   scan_exclusive_u32(P.g.template as<uint32_t>(), P.gs.template as<uint32_t>(), nc,
                      P.gs.template as<uint32_t>() + nc, w2.p, s);
   hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(m)), dim3(kB), 0, s,
-                     P.key.template as<uint64_t>(), P.sidx, m, P.skey.template as<uint64_t>());
+                     P.key.template as<uint64_t>(), P.sidx, m, kb, P.skey.template as<uint64_t>(),
+                     P.top.template as<uint16_t>(), P.ki.template as<uint4>());
   PAULI_HIP(hipGetLastError());
 }
 
@@ -135,10 +138,11 @@ paulisum* fused_t(const paulisum* a, const paulisum* b, const MergeArgs& o, hipS
       DBuf C(static_cast<size_t>(gb) * 256 * 4, s);
       const int shift = kb - d;
       const uint32_t mask = (1u << d2) - 1u;
-      GenSides gs{A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(), A.sidx,
-                  A.skey.template as<uint64_t>(), Bs.g.template as<uint32_t>(),
-                  Bs.gs.template as<uint32_t>(), Bs.sidx, Bs.skey.template as<uint64_t>(),
-                  Tt.as<uint32_t>(), static_cast<uint32_t>(a->m), ibits, d1};
+      GenSides gs{A.g.template as<uint32_t>(), A.gs.template as<uint32_t>(),
+                  A.ki.template as<uint4>(), Bs.g.template as<uint32_t>(),
+                  Bs.gs.template as<uint32_t>(), Bs.ki.template as<uint4>(), Tt.as<uint32_t>(),
+                  static_cast<uint32_t>(a->m), ibits, d1, A.top.template as<uint16_t>(),
+                  Bs.top.template as<uint16_t>(), 16 - d};
       hipLaunchKernelGGL(k_gcount, dim3(gb), dim3(kGenNT), 0, s, gs, GenBatch{}, S.as<uint32_t>(),
                          tb.as<uint32_t>(), nc, shift, mask, C.as<uint32_t>());
       DBuf w3(scan_workspace_bytes(static_cast<int64_t>(gb) * 256), s);
