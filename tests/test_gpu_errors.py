@@ -25,7 +25,9 @@ def test_overflow_pair_index():
     G = pl.PauliSum.from_dict(S)
     small = pl.PauliSum.from_dict({"n": n, "x": x[:3], "z": z[:3], "phase": None,
                                    "coef": np.ones(3, np.complex128)})
-    for call in (lambda: pl.outer_product(G, G), lambda: pl.outer_product_merged(G, G),
+    # (the plain fused product merges ranges beyond 2^32, tests/test_gpu_chunked.py)
+    for call in (lambda: pl.outer_product(G, G),
+                 lambda: pl.outer_product_merged(G, G, mode=pl.COMPENSATED),
                  lambda: pl.commutator(G, G),
                  lambda: pl.outer_product_batched([small, G], [small, G])):
         with pytest.raises(pl.PauliError) as e:
@@ -41,7 +43,9 @@ def test_oom_under_budget_then_recovers():
     A, B = synth.workload2(m1=2000, m2=2000)
     GA, GB = pl.PauliSum.from_dict(A), pl.PauliSum.from_dict(B)
     try:
-        pl.set_memory_budget(1 << 20)  # 1 MiB: far below what 4e6 products need
+        # 64 KiB: below what the two operands alone hold (about 0.6 MB), so the
+        # first allocation of every call exceeds it whatever else is alive
+        pl.set_memory_budget(1 << 16)
         for call in (lambda: pl.outer_product_merged(GA, GB), lambda: pl.outer_product(GA, GB),
                      lambda: pl.merge(GA)):
             with pytest.raises(pl.PauliError) as e:
