@@ -189,7 +189,14 @@ pauli_status_t pauli_merge_into(paulisum_t s, const pauli_merge_opts_t* opts, ui
 
 /* pauli_outer_product_merged: merge(outer_product(a, b)) without storing
  * the |a|*|b| unmerged products.  Same output definition as pauli_merge.
- * Errors as pauli_outer_product. */
+ * With |a|*|b| >= 2^32 (beyond one pipeline's 32-bit pair index) the plain
+ * merge forms and merges the products of the smaller operand with ranges of
+ * the larger one's terms (about 2^31 products each), then merges the merged
+ * ranges once more; the drop applies to that final merge, and the sums add
+ * the same products in another order.  The merged ranges must fit device
+ * memory together (OOM otherwise) and hold fewer than 2^32 terms (OVERFLOW).
+ * Errors as pauli_outer_product, except that OVERFLOW at |a|*|b| >= 2^32
+ * applies to the compensated mode only. */
 pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
                                           const pauli_merge_opts_t* opts, paulisum_t* out,
                                           void* stream);

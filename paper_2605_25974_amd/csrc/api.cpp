@@ -3,6 +3,7 @@
 // file: every entry point catches and turns errors into status codes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <cstring>
@@ -285,7 +286,9 @@ void use_device(const paulisum* s) {
 // pipeline, whose cost grows with their number).
 constexpr double kCommFilterFrac = 0.125;
 
-void check_pair(paulisum_t a, paulisum_t b) {
+// Operands of a binary call; with pair_limit, |a| |b| must fit the 32-bit
+// pair index.
+void check_pair(paulisum_t a, paulisum_t b, bool pair_limit = true) {
   check_sum(a, "a");
   check_sum(b, "b");
   if (a->n != b->n)
@@ -293,10 +296,106 @@ void check_pair(paulisum_t a, paulisum_t b) {
                               std::to_string(b->n));
   if (a->dtype != b->dtype) fail(PAULI_ERR_SHAPE, "coefficient types differ");
   if (a->device != b->device) fail(PAULI_ERR_SHAPE, "operands live on different devices");
-  const int64_t P = a->m * b->m;
-  if (a->m > 0 && b->m > 0 && (P / b->m != a->m || P >= (int64_t(1) << 32)))
+  if (pair_limit && a->m > 0 && b->m > 0 && a->m * b->m >= (int64_t(1) << 32))
     fail(PAULI_ERR_OVERFLOW, "|a|*|b| = " + std::to_string(a->m) + "*" + std::to_string(b->m) +
                                  " exceeds the 32-bit pair index");
+}
+
+// Products per range of the chunked outer product (below the 32-bit pair
+// index; 24 bytes of records each, double-buffered).
+constexpr int64_t kChunkProducts = int64_t(1) << 31;
+
+// The terms [j0, j0 + m) of b as a sum that borrows b's arrays.
+paulisum slice_of(const paulisum* b, int64_t j0, int64_t m) {
+  paulisum v;
+  v.n = b->n;
+  v.W = b->W;
+  v.m = m;
+  v.ld = b->ld;
+  v.dtype = b->dtype;
+  v.device = b->device;
+  v.X = b->X + j0;
+  v.Z = b->Z + j0;
+  v.ph = b->ph + j0;
+  v.coef = static_cast<char*>(b->coef) + j0 * coef_bytes(b->dtype);
+  v.fp = b->fp + j0;
+  v.last_stream = b->last_stream;
+  v.borrowed = true;
+  return v;
+}
+
+// The terms of several sums one after another in a new sum.
+paulisum* concat_sums(const std::vector<paulisum*>& parts, int n, int32_t dt, hipStream_t s) {
+  int64_t total = 0;
+  for (const paulisum* p : parts) total += p->m;
+  if (total >= (int64_t(1) << 32))
+    fail(PAULI_ERR_OVERFLOW, "the merged ranges hold " + std::to_string(total) +
+                                 " terms, beyond the 32-bit term index of a merge");
+  paulisum* c = new_sum(n, total, total, dt, s);
+  const size_t cb = coef_bytes(dt);
+  int64_t off = 0;
+  for (const paulisum* p : parts) {
+    const size_t m = static_cast<size_t>(p->m);
+    if (m == 0) continue;
+    for (int w = 0; w < c->W; ++w) {
+      PAULI_HIP(hipMemcpyAsync(c->X + w * c->ld + off, p->X + w * p->ld, m * 8,
+                               hipMemcpyDeviceToDevice, s));
+      PAULI_HIP(hipMemcpyAsync(c->Z + w * c->ld + off, p->Z + w * p->ld, m * 8,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    PAULI_HIP(hipMemcpyAsync(c->ph + off, p->ph, m, hipMemcpyDeviceToDevice, s));
+    PAULI_HIP(hipMemcpyAsync(static_cast<char*>(c->coef) + off * cb, p->coef, m * cb,
+                             hipMemcpyDeviceToDevice, s));
+    PAULI_HIP(hipMemcpyAsync(c->fp + off, p->fp, m * 8, hipMemcpyDeviceToDevice, s));
+    off += p->m;
+  }
+  return c;
+}
+
+// merge(a b) for |a| |b| at or beyond 2^32: the products of the smaller
+// operand with ranges of the larger one's terms (at most
+// max(kChunkProducts, smaller size) products per range, below the 32-bit
+// pair index) are formed and merged by the fused pipeline, then the merged
+// ranges are merged once more.  Every product is still summed into its
+// string; only the order of the additions differs from a single call.  The
+// drop applies to the final merge alone.  Plain mode only: the precision
+// form re-merges cancelling sums from the operands' own coefficients, which
+// the second merge no longer sees.
+paulisum* product_merged_chunked(const paulisum* a, const paulisum* b, const MergeArgs& o,
+                                 hipStream_t s) {
+  if (o.mode != PAULI_MERGE_PLAIN)
+    fail(PAULI_ERR_OVERFLOW, "|a|*|b| = " + std::to_string(a->m) + "*" + std::to_string(b->m) +
+                                 " exceeds 2^32: only the plain merge takes more products");
+  const bool cut_b = a->m <= b->m;  // ranges of the larger operand
+  const paulisum* whole = cut_b ? a : b;
+  const paulisum* cut = cut_b ? b : a;
+  const int64_t step = std::max<int64_t>(1, kChunkProducts / whole->m);
+  MergeArgs part = o;
+  part.drop_abs = -1.0;  // a term of one range may combine with another range's
+  std::vector<paulisum*> parts;
+  paulisum* c = nullptr;
+  try {
+    for (int64_t k0 = 0; k0 < cut->m; k0 += step) {
+      const paulisum v = slice_of(cut, k0, std::min(step, cut->m - k0));
+      const paulisum* x = cut_b ? a : &v;
+      const paulisum* y = cut_b ? &v : b;
+      paulisum* r = fused_bucket(x, y, part, s);
+      if (!r) r = merge_generic(x, y, part, s);
+      parts.push_back(r);
+    }
+    c = concat_sums(parts, a->n, a->dtype, s);
+    for (paulisum*& p : parts) {
+      free_sum(p);
+      p = nullptr;
+    }
+    paulisum* r = merge_generic(c, nullptr, o, s);
+    free_sum(c);
+    return r;
+  } catch (...) {
+    for (paulisum* p : parts) free_sum(p);
+    free_sum(c);
+    throw;
+  }
 }
 
 MergeArgs merge_args(const pauli_merge_opts_t* o) {
@@ -571,11 +670,16 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
                                           void* stream) {
   return guarded([&] {
     if (!out) fail(PAULI_ERR_INVALID, "out is NULL");
-    check_pair(a, b);
+    check_pair(a, b, false);
     const MergeArgs m = merge_args(opts);
     use_device(a);
     hipStream_t s = as_stream(stream);
     a->last_stream = b->last_stream = s;
+    if (a->m > 0 && b->m > 0 && a->m * b->m >= (int64_t(1) << 32)) {
+      // beyond the 32-bit pair index: ranges of one operand's terms
+      *out = product_merged_chunked(a, b, m, s);
+      return;
+    }
     paulisum* r = nullptr;
     if (a->m > 0 && b->m > 0) r = fused_bucket(a, b, m, s);
     if (!r) r = merge_generic(a, b, m, s);
