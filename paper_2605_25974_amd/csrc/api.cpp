@@ -286,6 +286,11 @@ void use_device(const paulisum* s) {
 // pipeline, whose cost grows with their number).
 constexpr double kCommFilterFrac = 0.125;
 
+// |a| |b| (term counts are below 2^32, so the product fits 64 bits).
+uint64_t pair_count(const paulisum* a, const paulisum* b) {
+  return static_cast<uint64_t>(a->m) * static_cast<uint64_t>(b->m);
+}
+
 // Operands of a binary call; with pair_limit, |a| |b| must fit the 32-bit
 // pair index.
 void check_pair(paulisum_t a, paulisum_t b, bool pair_limit = true) {
@@ -296,7 +301,7 @@ void check_pair(paulisum_t a, paulisum_t b, bool pair_limit = true) {
                               std::to_string(b->n));
   if (a->dtype != b->dtype) fail(PAULI_ERR_SHAPE, "coefficient types differ");
   if (a->device != b->device) fail(PAULI_ERR_SHAPE, "operands live on different devices");
-  if (pair_limit && a->m > 0 && b->m > 0 && a->m * b->m >= (int64_t(1) << 32))
+  if (pair_limit && pair_count(a, b) >= (uint64_t(1) << 32))
     fail(PAULI_ERR_OVERFLOW, "|a|*|b| = " + std::to_string(a->m) + "*" + std::to_string(b->m) +
                                  " exceeds the 32-bit pair index");
 }
@@ -675,7 +680,7 @@ pauli_status_t pauli_outer_product_merged(paulisum_t a, paulisum_t b,
     use_device(a);
     hipStream_t s = as_stream(stream);
     a->last_stream = b->last_stream = s;
-    if (a->m > 0 && b->m > 0 && a->m * b->m >= (int64_t(1) << 32)) {
+    if (pair_count(a, b) >= (uint64_t(1) << 32)) {
       // beyond the 32-bit pair index: ranges of one operand's terms
       *out = product_merged_chunked(a, b, m, s);
       return;
