@@ -81,26 +81,68 @@ k_scan_partials(uint32_t* __restrict__ partial, int64_t nb, uint32_t* __restrict
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// A thread's kScanItems consecutive elements from `base`: as 16-byte loads
+// when they all lie below n and the arrays are 16-byte aligned (a wave's
+// loads then touch each line kScanItems / 4 times instead of kScanItems),
+// else one by one.
+__device__ __forceinline__ bool scan_vec(const uint32_t* in, const uint32_t* out, int64_t base,
+                                         int64_t n) {
+  return base + kScanItems <= n &&
+         ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+}
+
+__device__ __forceinline__ void scan_load(const uint32_t* in, int64_t base, int64_t n, bool vec,
+                                          uint32_t (&v)[kScanItems]) {
+  if (vec) {
+    const uint4* p = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+    for (int k = 0; k < kScanItems / 4; ++k) {
+      const uint4 q = p[k];
+      v[4 * k] = q.x;
+      v[4 * k + 1] = q.y;
+      v[4 * k + 2] = q.z;
+      v[4 * k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) v[r] = base + r < n ? in[base + r] : 0u;
+  }
+}
+
+// Writes the exclusive prefix run, run + v[0], ... of the thread's elements.
+__device__ __forceinline__ void scan_store(uint32_t* out, int64_t base, int64_t n, bool vec,
+                                           uint32_t run, const uint32_t (&v)[kScanItems]) {
+  uint32_t o[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    o[r] = run;
+    run += v[r];
+  }
+  if (vec) {
+    uint4* p = reinterpret_cast<uint4*>(out + base);
+#pragma unroll
+    for (int k = 0; k < kScanItems / 4; ++k)
+      p[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r)
+      if (base + r < n) out[base + r] = o[r];
+  }
+}
+
 __global__ void __launch_bounds__(kScanBlock)
 k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __restrict__ nd,
             const uint32_t* __restrict__ partial) {
   if (nd && *nd < n) n = *nd;
   const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;
+  const bool vec = scan_vec(in, out, base, n);
   uint32_t v[kScanItems];
+  scan_load(in, base, n, vec, v);
   uint32_t s = 0;
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + r;
-    v[r] = i < n ? in[i] : 0;
-    s += v[r];
-  }
-  uint32_t run = partial[blockIdx.x] + block_exclusive_scan<uint32_t>(s, nullptr);
-#pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
-    int64_t i = base + r;
-    if (i < n) out[i] = run;
-    run += v[r];
-  }
+  for (int r = 0; r < kScanItems; ++r) s += v[r];
+  const uint32_t run = partial[blockIdx.x] + block_exclusive_scan<uint32_t>(s, nullptr);
+  scan_store(out, base, n, vec, run, v);
 }
 
 // A scan of at most kScanTile elements in one launch (the three passes of
@@ -111,22 +153,15 @@ k_scan_one(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* __restr
            uint32_t* total) {
   if (nd && *nd < n) n = *nd;
   const int64_t base = threadIdx.x * static_cast<int64_t>(kScanItems);
+  const bool vec = scan_vec(in, out, base, n);
   uint32_t v[kScanItems];
+  scan_load(in, base, n, vec, v);
   uint32_t s = 0;
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
-    const int64_t i = base + r;
-    v[r] = i < n ? in[i] : 0;
-    s += v[r];
-  }
+  for (int r = 0; r < kScanItems; ++r) s += v[r];
   uint32_t tot;
-  uint32_t run = block_exclusive_scan<uint32_t>(s, &tot);
-#pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
-    const int64_t i = base + r;
-    if (i < n) out[i] = run;
-    run += v[r];
-  }
+  const uint32_t run = block_exclusive_scan<uint32_t>(s, &tot);
+  scan_store(out, base, n, vec, run, v);
   if (threadIdx.x == 0 && total) *total = tot;
 }
 
