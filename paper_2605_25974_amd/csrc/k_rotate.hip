@@ -110,10 +110,11 @@ __global__ void k_rot_records(const uint64_t* __restrict__ fp, const uint32_t* _
 }
 
 // Merge of two key-ordered record lists a (first on equal keys) and b into
-// o: each block takes kMergeOut consecutive outputs, finds where they start
-// in a and b by a co-rank search (merge path), stages both input ranges in
-// LDS and merges them there; each thread then finds its own kMergePer
-// outputs' start the same way inside the block's ranges.
+// o: output tile k is outputs [k kMergeOut, (k + 1) kMergeOut); where each
+// tile starts in a and b is found first by a co-rank search (merge path),
+// one thread per tile boundary (k_merge_splits); a block then stages its
+// tile's two input ranges in LDS and merges them there, each thread finding
+// its own kMergePer outputs' start the same way inside the block's ranges.
 constexpr int kMergePer = 8;
 constexpr int kMergeOut = kBlock * kMergePer;
 
@@ -128,26 +129,40 @@ __device__ __forceinline__ int64_t corank(const uint64_t* a, int64_t na, const u
   return lo;
 }
 
+// split[k] = how many of the first min(k kMergeOut, |a| + |b|) outputs come
+// from a, for k = 0 .. ntiles (every search at once, instead of two threads
+// of each merging block waiting on theirs).
+__global__ void k_merge_splits(const uint64_t* __restrict__ ak, int64_t na,
+                               const uint64_t* __restrict__ bk, int64_t nb,
+                               const uint32_t* __restrict__ nad, const uint32_t* __restrict__ nbd,
+                               int64_t ntiles, int64_t* __restrict__ split) {
+  if (nad && *nad < na) na = *nad;  // device counts, clamped to the host bounds
+  if (nbd && *nbd < nb) nb = *nbd;
+  const int64_t total = na + nb;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k <= ntiles;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = k * kMergeOut < total ? k * kMergeOut : total;
+    split[k] = corank(ak, na, bk, nb, d);
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_merge_path(const uint64_t* __restrict__ ak, const uint32_t* __restrict__ av, int64_t na,
              const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, int64_t nb,
              const uint32_t* __restrict__ nad, const uint32_t* __restrict__ nbd,
-             uint64_t* __restrict__ ok, uint32_t* __restrict__ ov) {
+             const int64_t* __restrict__ split, uint64_t* __restrict__ ok,
+             uint32_t* __restrict__ ov) {
   if (nad && *nad < na) na = *nad;  // device counts, clamped to the host bounds
   if (nbd && *nbd < nb) nb = *nbd;
   __shared__ uint64_t sk[kMergeOut];
   __shared__ uint32_t sv[kMergeOut];
   __shared__ uint64_t so_k[kMergeOut];
   __shared__ uint32_t so_v[kMergeOut];
-  __shared__ int64_t s_split[2];
   const int64_t total = na + nb;
-  for (int64_t d0 = static_cast<int64_t>(blockIdx.x) * kMergeOut; d0 < total;
-       d0 += static_cast<int64_t>(gridDim.x) * kMergeOut) {
+  for (int64_t tile = blockIdx.x; tile * kMergeOut < total; tile += gridDim.x) {
+    const int64_t d0 = tile * kMergeOut;
     const int64_t d1 = d0 + kMergeOut < total ? d0 + kMergeOut : total;
-    if (threadIdx.x == 0) s_split[0] = corank(ak, na, bk, nb, d0);
-    if (threadIdx.x == 1) s_split[1] = corank(ak, na, bk, nb, d1);
-    __syncthreads();
-    const int64_t i0 = s_split[0], i1 = s_split[1];
+    const int64_t i0 = split[tile], i1 = split[tile + 1];
     const int64_t j0 = d0 - i0, j1 = d1 - i1;
     const int la = static_cast<int>(i1 - i0), lb = static_cast<int>(j1 - j0);  // la + lb <= kMergeOut
     for (int e = threadIdx.x; e < la + lb; e += kBlock) {
@@ -264,12 +279,15 @@ paulisum* conjugate_t(const paulisum* s, const RotString& P, double theta, const
         bk = nk2.as<uint64_t>();
         bv = nv2.as<uint32_t>();
       }
-      int64_t blocks = (static_cast<int64_t>(M2) + kMergeOut - 1) / kMergeOut;
-      if (blocks > 65536) blocks = 65536;
-      if (blocks < 1) blocks = 1;
+      const int64_t ntiles = (static_cast<int64_t>(M2) + kMergeOut - 1) / kMergeOut;
+      DBuf split((ntiles + 1) * 8ull, st);
+      hipLaunchKernelGGL(k_merge_splits, dim3(grid_for(ntiles + 1)), dim3(kBlock), 0, st,
+                         kk.as<uint64_t>(), na, bk, nb, nullptr, nullptr, ntiles,
+                         split.as<int64_t>());
+      const int64_t blocks = ntiles < 1 ? 1 : (ntiles > 65536 ? 65536 : ntiles);
       hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
                          kk.as<uint64_t>(), kv.as<uint32_t>(), na, bk, bv, nb, nullptr, nullptr,
-                         keys.as<uint64_t>(), vals.as<uint32_t>());
+                         split.as<int64_t>(), keys.as<uint64_t>(), vals.as<uint32_t>());
       PAULI_HIP(hipGetLastError());
     }
     return merge_rotated(s, P, theta, cnt.as<uint32_t>(), keys.as<uint64_t>(),
@@ -413,11 +431,14 @@ void conjugate_dev(const paulisum* s, const RotString& P, double theta, const Me
     bk = nk2.as<uint64_t>();
     bv = nv2.as<uint32_t>();
   }
-  int64_t blocks = (M2b + kMergeOut - 1) / kMergeOut;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
+  const int64_t ntiles = (M2b + kMergeOut - 1) / kMergeOut;
+  DBuf split((ntiles + 1) * 8ull, st);
+  hipLaunchKernelGGL(k_merge_splits, dim3(grid_for(ntiles + 1)), dim3(kBlock), 0, st,
+                     kk.as<uint64_t>(), mb, bk, nbb, md, nbd, ntiles, split.as<int64_t>());
+  const int64_t blocks = ntiles < 1 ? 1 : (ntiles > 65536 ? 65536 : ntiles);
   hipLaunchKernelGGL(k_merge_path, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st,
                      kk.as<uint64_t>(), kv.as<uint32_t>(), mb, bk, bv, nbb, md, nbd,
+                     split.as<int64_t>(),
                      keys.as<uint64_t>(), vals.as<uint32_t>());
   PAULI_HIP(hipGetLastError());
   DevRun dv = dv0;
